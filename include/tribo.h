@@ -1,0 +1,210 @@
+/*
+ * tribo.h -- C ABI of the MI355X particle-step library (libtribo.so).
+ *
+ * One call of tf_step advances the Lagrangian particle phase of a wall-bounded
+ * periodic channel, driven by a frozen carrier velocity field, by whole time
+ * steps.  Per step and per ensemble (Wilms & Grosshans, Sec. 2.2-2.3):
+ *   1. particles are binned by grid cell (cell = control volume, Sec. 2.2)
+ *      and sorted by (cell, particle id);
+ *   2. cell charge = sum of the particle charges in the cell (Sec. 2.2),
+ *      accumulated exactly in fixed point (q * 2^48, round-to-nearest-even);
+ *   3. the Poisson equation lap(phi) = -rho_el/eps (Sec. 2.2, eps = 1 in
+ *      these units) is solved with grounded walls phi = 0 (Sec. 4.2) and
+ *      periodic x, z (Sec. 3.1) on the second-order finite-volume grid
+ *      (Sec. 3.1): Fourier transforms in x and z, one tridiagonal solve per
+ *      Fourier mode in y;
+ *   4. per particle: trilinear carrier velocity, cell-centred E = -grad(phi)
+ *      (Gauss part, Eq. (2.9)) plus Coulomb's law, Eq. (2.8), between
+ *      particles of the same cell (hybrid scheme, Sec. 2.2), Schiller-Naumann
+ *      drag, Eq. (2.6)-(2.7), gravity/buoyancy, semi-implicit Euler for the
+ *      equation of motion, Eq. (2.5);
+ *   5. wall impact: hard-sphere rebound (Sec. 2.2) with restitution e and
+ *      condenser-model charge transfer (Sec. 2.3.1, Eq. (2.13)-(2.19)) in
+ *      the lumped normalised form dq = -f (dU + q), f = k_c (1+e)^(2/5) u_n^(4/5);
+ *   6. periodic wrap, grid-cell histograms of concentration and charge
+ *      (Sec. 4.1), impact counts, wall charge and impact-velocity histogram.
+ *
+ * Units: wall units (nu = u_tau = 1), half channel height h = Re_tau, charge in
+ * units of q_sat.  All floating-point state is IEEE binary64.
+ *
+ * Memory and ownership.  Every device pointer passed in is owned by the
+ * caller and must stay valid for the lifetime of the handle; the library
+ * never allocates device memory.  All scratch (sorted particle buffers, cell
+ * tables, spectra, statistics, recorded trajectories) lives in the caller's
+ * workspace of tf_workspace_size() bytes.  The host-side handle is allocated
+ * by tf_init and released by tf_destroy.
+ *
+ * Streams.  All device work of a handle is enqueued on the stream given to
+ * tf_init, asynchronously.  tf_stats and tf_adjoint_step synchronise that
+ * stream before returning host data.
+ *
+ * Errors.  Every int-returning call returns TF_OK (0) or a negative TF_E*
+ * code; tf_last_error() describes the most recent failure of the calling
+ * thread.  No C++ exception crosses the ABI.  Faults detected on the device
+ * (non-finite state, fixed-point overflow, a particle outside the channel
+ * after a rebound) are sticky per-ensemble flags reported by tf_stats.
+ */
+#ifndef TRIBO_H
+#define TRIBO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tf_handle tf_handle;
+
+/* return codes */
+#define TF_OK 0
+#define TF_EINVAL (-1)     /* invalid argument or configuration */
+#define TF_ESIZE (-2)      /* workspace too small / size limit exceeded */
+#define TF_EHIP (-3)       /* HIP runtime error */
+#define TF_ESTATE (-4)     /* call not valid in the handle's current state */
+#define TF_EOVERFLOW (-5)  /* fixed-point or counter overflow */
+
+/* tf_init flags */
+#define TF_INIT_KEEP_DEPOSIT 1u   /* also store each step's per-cell fixed-point charge */
+#define TF_INIT_GRAPHS 2u         /* replay steps from captured HIP graphs */
+
+/* tf_step flags */
+#define TF_STEP_RECORD 1u         /* record the steps for tf_adjoint_step (needs trajectory capacity) */
+
+/* sticky device flags (tf_stats_out.flags) */
+#define TF_FLAG_NONFINITE 1
+#define TF_FLAG_OVERFLOW 2
+#define TF_FLAG_OUTSIDE 4
+
+/* fixed-point scales (powers of two) */
+#define TF_FIX_DEPOSIT 48   /* cell charge and q_now: sum rne(q * 2^48) */
+#define TF_FIX_WALL 40      /* wall charge: sum rne(-dq * 2^40) */
+#define TF_FIX_QCUM 32      /* time-summed charge profile: sum rne(q * 2^32) */
+#define TF_NBIN 64          /* impact-velocity histogram bins */
+
+/*
+ * One independent ensemble (channel + particles).
+ *   nx, nz      cells in the periodic directions: even, of the form 2^a 3^b 5^c, 4..256
+ *   ny          cells between the walls, 2..1024
+ *   lx, lz      periodic lengths; cells are uniform, dx = lx/nx, dz = lz/nz
+ *   y_faces     host array of ny+1 strictly increasing wall-normal faces,
+ *               y_faces[0] = 0 (lower wall), y_faces[ny] = ly (upper wall);
+ *               copied at tf_init
+ *   dt          time step; density_ratio = rho_p/rho (> 1)
+ *   k_c, delta_u, e   charge-transfer coefficient, normalised contact
+ *               potential difference, restitution coefficient (0 < e <= 1)
+ *   c_el        electric coupling: specific electric force = c_el q E / d^3
+ *   g           gravitational acceleration vector (buoyancy applied inside)
+ *   un_bin      bin width of the wall-normal impact-velocity histogram
+ *   u_nodes     device pointer, carrier velocity at the mesh nodes,
+ *               layout [3][ny+1][nz][nx] (component, y face, z, x), node
+ *               (i, j, k) at (i dx, y_faces[j], k dz); borrowed
+ *   n_particles 1..2^30
+ */
+typedef struct {
+  int32_t nx, ny, nz, n_particles;
+  double lx, lz;
+  const double* y_faces;
+  double dt, density_ratio, k_c, delta_u, e, c_el;
+  double g[3];
+  double un_bin;
+  const double* u_nodes;
+} tf_ensemble;
+
+/* Particle arrays (device pointers, n_particles doubles each, indexed by
+ * particle id).  d is the diameter (constant in time). */
+typedef struct {
+  double *x, *y, *z, *vx, *vy, *vz, *q, *d;
+} tf_particles;
+
+typedef struct {
+  int64_t steps;              /* steps taken since tf_init */
+  int32_t flags;              /* sticky TF_FLAG_* */
+  int32_t ny;
+  int64_t impacts[2];         /* wall impacts [lower, upper] */
+  int64_t wall_q[2];          /* charge received by each wall, sum rne(-dq 2^40) */
+  int64_t un_hist[TF_NBIN];   /* impacts per bin of u_n / un_bin (last bin open) */
+  int64_t* crel_y;            /* optional host [ny]: time-summed particle count per y cell */
+  int64_t* qcum_y;            /* optional host [ny]: time-summed sum rne(q 2^32) per y cell */
+  int64_t* qnow_y;            /* optional host [ny]: sum rne(q 2^48) per y cell at the latest deposit */
+  double q_sum;               /* total particle charge at the latest deposit */
+} tf_stats_out;
+
+/* Bytes of device workspace for these ensembles.  traj_steps > 0 reserves
+ * room to record that many steps for tf_adjoint_step.  Returns 0 if the
+ * configuration is invalid. */
+size_t tf_workspace_size(const tf_ensemble* ens, int32_t n_ens, int32_t traj_steps);
+
+/* Validate the configuration, carve the workspace, copy the initial
+ * particles (one tf_particles per ensemble, read on the stream), bin them.
+ * stream is a hipStream_t (NULL = default stream). */
+int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init,
+            void* workspace, size_t workspace_bytes, int32_t traj_steps,
+            void* stream, uint32_t flags, tf_handle** out);
+
+/* Advance every ensemble by n_steps >= 0 steps.  With TF_STEP_RECORD the
+ * steps are appended to the recorded trajectory (at most traj_steps since the
+ * last tf_adjoint_step or tf_set_state). */
+int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags);
+
+/* Copy the statistics of ensemble `ens` to the host (synchronises). */
+int tf_stats(tf_handle* h, int32_t ens, tf_stats_out* out);
+
+/* Copy the current particle state of ensemble `ens` into `out` (device
+ * arrays, id order), or replace it from `in`.  Asynchronous on the stream.
+ * tf_set_state also clears the recorded trajectory. */
+int tf_get_state(tf_handle* h, int32_t ens, const tf_particles* out);
+int tf_set_state(tf_handle* h, int32_t ens, const tf_particles* in);
+
+/* Replace (k_c, delta_u, e) of every ensemble: host array [n_ens][3]. */
+int tf_set_params(tf_handle* h, const double* theta);
+
+/*
+ * Reverse-mode derivative of the recorded steps with the discrete events
+ * (cell of each particle, wall impacts, periodic wraps) held fixed.
+ *   lambda   device arrays, id order, one tf_particles per ensemble: on entry
+ *            dJ/d(state) at the end of the recorded steps, on return dJ/d(state)
+ *            at their start (the d member is ignored)
+ *   w_wall   host [n_ens][2]: dJ/d(charge received by the lower/upper wall)
+ *            over the recorded steps (the wall accumulators never feed back)
+ *   dtheta   host [n_ens][3]: dJ/d(k_c, delta_u, e) is ADDED to it
+ * Consumes the recorded trajectory.  The fixed-point deposit is treated as
+ * the identity (its derivative is zero almost everywhere).
+ */
+int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wall, double* dtheta);
+
+/* Solve the Poisson problem of ensemble `ens` for a given per-cell
+ * fixed-point charge q_fixed (device int64 [ncell], scale 2^48, cell index
+ * (j*nz + k)*nx + i) into phi (device double [ncell]).  Uses the handle's
+ * scratch; asynchronous on the stream. */
+int tf_poisson(tf_handle* h, int32_t ens, const int64_t* q_fixed, double* phi);
+
+/* Copy a field of the latest step of ensemble `ens` to device memory `out`:
+ * TF_FIELD_PHI (double [ncell]) or, with TF_INIT_KEEP_DEPOSIT,
+ * TF_FIELD_DEPOSIT (int64 [ncell]). */
+#define TF_FIELD_PHI 0
+#define TF_FIELD_DEPOSIT 1
+int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
+
+/*
+ * Per-phase timing with HIP events on the handle's stream.  After
+ * tf_profile_begin, the next max_steps steps are launched eagerly with an
+ * event at every phase boundary; tf_profile_end synchronises and returns the
+ * summed milliseconds of each phase over the profiled steps.  Phases:
+ *   0 sort (prefix sum, slot assignment, id ranking)
+ *   1 deposit + forward FFT along x     2 forward FFT along z
+ *   3 tridiagonal y-solves              4 inverse FFT along z
+ *   5 inverse FFT along x               6 particle push
+ */
+#define TF_NPHASE 7
+int tf_profile_begin(tf_handle* h, int32_t max_steps);
+int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_steps);
+
+void tf_destroy(tf_handle* h);
+const char* tf_error_string(int code);
+const char* tf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRIBO_H */

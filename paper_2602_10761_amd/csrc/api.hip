@@ -1,0 +1,693 @@
+// C ABI of libtribo.so: configuration checks, workspace layout, host tables,
+// step orchestration (eager or replayed from captured HIP graphs).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tribo.h"
+#include "adjoint.h"
+#include "launch.h"
+#include "tribo_dev.h"
+
+using namespace tf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(TF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool radix_plan(int n, FftPlan* P) {
+  P->n = n;
+  P->npass = 0;
+  P->rcode = 0;
+  int m = n;
+  auto push = [&](int r) {
+    if (P->npass >= kMaxPass) return false;
+    P->rcode |= (unsigned)r << (3 * P->npass++);
+    m /= r;
+    return true;
+  };
+  while (m % 4 == 0) if (!push(4)) return false;
+  while (m % 2 == 0) if (!push(2)) return false;
+  while (m % 3 == 0) if (!push(3)) return false;
+  while (m % 5 == 0) if (!push(5)) return false;
+  return m == 1;
+}
+
+struct Sizes {
+  long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
+  int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
+  int nx_max = 0, nz_max = 0, rpb = 1, wz = 8;
+  std::vector<int> fx_blk, fz_blk, tri_blk;
+  std::map<int, int> tw_off;
+};
+
+int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
+  if (!ens || n_ens < 1 || n_ens > 4096) return fail(TF_EINVAL, "n_ens must be in [1, 4096]");
+  S->fx_blk.assign(n_ens + 1, 0);
+  S->fz_blk.assign(n_ens + 1, 0);
+  S->tri_blk.assign(n_ens + 1, 0);
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_ensemble& E = ens[e];
+    FftPlan P;
+    auto okn = [&](int n) { return n >= 4 && n <= 256 && n % 2 == 0 && radix_plan(n, &P); };
+    char buf[160];
+    snprintf(buf, sizeof buf, "ensemble %d: ", e);
+    std::string pre(buf);
+    if (!okn(E.nx) || !okn(E.nz)) return fail(TF_EINVAL, pre + "nx, nz must be even 2^a 3^b 5^c in [4, 256]");
+    if (E.ny < 2 || E.ny > 1024) return fail(TF_EINVAL, pre + "ny must be in [2, 1024]");
+    if (E.n_particles < 0 || E.n_particles > (1 << 30)) return fail(TF_EINVAL, pre + "n_particles out of range");
+    if (!(E.lx > 0) || !(E.lz > 0) || !(E.dt > 0) || !(E.density_ratio > 0) || !(E.un_bin > 0))
+      return fail(TF_EINVAL, pre + "lx, lz, dt, density_ratio, un_bin must be positive");
+    if (!(E.e > 0 && E.e <= 1)) return fail(TF_EINVAL, pre + "restitution e must be in (0, 1]");
+    if (!std::isfinite(E.k_c) || !std::isfinite(E.delta_u) || !std::isfinite(E.c_el))
+      return fail(TF_EINVAL, pre + "k_c, delta_u, c_el must be finite");
+    if (!E.y_faces) return fail(TF_EINVAL, pre + "y_faces is NULL");
+    if (!E.u_nodes) return fail(TF_EINVAL, pre + "u_nodes is NULL");
+    if (E.y_faces[0] != 0.0) return fail(TF_EINVAL, pre + "y_faces[0] must be 0");
+    for (int j = 0; j < E.ny; ++j)
+      if (!(E.y_faces[j + 1] > E.y_faces[j])) return fail(TF_EINVAL, pre + "y_faces must increase strictly");
+    long long ncell = (long long)E.nx * E.ny * E.nz;
+    int nh = E.nx / 2 + 1, nhp = (nh + 3) & ~3;
+    S->n_tot += E.n_particles;
+    S->c_tot += ncell;
+    S->s_tot += (long long)E.ny * E.nz * nhp;
+    S->rows += (long long)E.ny * E.nz;
+    S->y_tot += E.ny + 1;
+    S->kx_tot += nh;
+    S->kz_tot += E.nz;
+    S->st_tot += stats_len(E.ny);
+    S->nx_max = std::max(S->nx_max, E.nx);
+    S->nz_max = std::max(S->nz_max, E.nz);
+    for (int n : {E.nx, E.nz})
+      if (!S->tw_off.count(n)) {
+        S->tw_off[n] = S->tw_tot;
+        S->tw_tot += n;
+      }
+  }
+  if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
+  S->rpb = std::max(1, 512 / S->nx_max);
+  S->wz = std::max(1, std::min(8, (60 * 1024 / 16 - S->nz_max) / (2 * S->nz_max)));
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_ensemble& E = ens[e];
+    int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
+    S->fx_blk[e + 1] = S->fx_blk[e] + (rows + S->rpb - 1) / S->rpb;
+    S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->wz - 1) / S->wz);
+    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + kBlock - 1) / kBlock;
+  }
+  return TF_OK;
+}
+
+}  // namespace
+
+struct TrajBuf {
+  PState st;
+  int* perm;
+  double* phi;
+};
+
+struct tf_handle {
+  int n_ens = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  Sizes S;
+  std::vector<Ens> eh;              // host copies of the ensemble descriptors
+  std::vector<long long> p_off, c_off;
+  Ctx C{};
+  LaunchGeo G{};
+  Ens* d_ens = nullptr;
+  PState A{}, B{}, cur{};
+  bool cur_is_A = true;
+  int* d_fx = nullptr;
+  int* d_fz = nullptr;
+  int* d_tri = nullptr;
+  // recorded trajectory
+  int traj_cap = 0, traj_len = 0;
+  std::vector<TrajBuf> traj;        // traj_cap + 1 states (perm/phi used for the first traj_cap)
+  AdjWork adj{};
+  // graphs: one step A->B and one B->A
+  hipGraphExec_t g_ab = nullptr, g_ba = nullptr;
+  // phase timing: TF_NPHASE + 1 events per profiled step
+  int prof_cap = 0, prof_n = 0;
+  std::vector<hipEvent_t> prof_ev;
+};
+
+namespace {
+
+PState carve_state(Carver& cv, long long n) {
+  PState s;
+  double** f[8] = {&s.x, &s.y, &s.z, &s.vx, &s.vy, &s.vz, &s.q, &s.d};
+  for (auto* p : f) *p = cv.take<double>(n);
+  s.id = cv.take<int>(n);
+  s.key = cv.take<int>(n);
+  return s;
+}
+
+// Lay out every device array; with h == nullptr only the size is computed.
+size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* base, tf_handle* h) {
+  Carver cv(base);
+  Ctx C{};
+  C.ens = cv.take<Ens>(n_ens);
+  C.p_off = cv.take<long long>(n_ens + 1);
+  C.c_off = cv.take<long long>(n_ens + 1);
+  int* fx = cv.take<int>(n_ens + 1);
+  int* fz = cv.take<int>(n_ens + 1);
+  int* tri = cv.take<int>(n_ens + 1);
+  C.yf = cv.take<double>(S.y_tot);
+  C.dy = cv.take<double>(S.y_tot);
+  C.vol = cv.take<double>(S.y_tot);
+  C.am = cv.take<double>(S.y_tot);
+  C.ap = cv.take<double>(S.y_tot);
+  C.beta = cv.take<double>(S.y_tot);
+  C.kx2 = cv.take<double>(S.kx_tot);
+  C.kz2 = cv.take<double>(S.kz_tot);
+  C.tw = cv.take<double2>(S.tw_tot);
+  C.stats = cv.take<long long>(S.st_tot);
+  C.rowq = cv.take<long long>(S.rows);
+  PState A = carve_state(cv, S.n_tot);
+  PState B = carve_state(cv, S.n_tot);
+  C.count = cv.take<int>(S.c_tot);
+  C.start = cv.take<int>(S.c_tot + 1);
+  C.tmp = cv.take<unsigned long long>(S.n_tot);
+  C.perm = cv.take<int>(S.n_tot);
+  const long long nbs = (S.c_tot + 4 * kBlock - 1) / (4 * kBlock);
+  C.scan_part = cv.take<int>(nbs + 1);
+  C.spec = cv.take<double2>(S.s_tot);
+  C.cp = cv.take<double>(S.s_tot);
+  C.phi = cv.take<double>(S.c_tot);
+  C.qdep = (flags & TF_INIT_KEEP_DEPOSIT) ? cv.take<long long>(S.c_tot) : nullptr;
+  std::vector<TrajBuf> traj;
+  if (traj_steps > 0) {
+    for (int t = 0; t <= traj_steps; ++t) {
+      TrajBuf tb;
+      tb.st = carve_state(cv, S.n_tot);
+      tb.perm = (t < traj_steps) ? cv.take<int>(S.n_tot) : nullptr;
+      tb.phi = (t < traj_steps) ? cv.take<double>(S.c_tot) : nullptr;
+      traj.push_back(tb);
+    }
+  }
+  AdjWork adj = carve_adjoint(cv, S.n_tot, S.c_tot, S.s_tot, n_ens, traj_steps > 0);
+  if (h) {
+    C.n_ens = n_ens;
+    C.n_tot = S.n_tot;
+    C.c_tot = S.c_tot;
+    h->C = C;
+    h->A = A;
+    h->B = B;
+    h->d_fx = fx;
+    h->d_fz = fz;
+    h->d_tri = tri;
+    h->d_ens = (Ens*)C.ens;
+    h->traj = traj;
+    h->traj_cap = traj_steps;
+    h->adj = adj;
+  }
+  return cv.off + 256;
+}
+
+void destroy_graphs(tf_handle* h) {
+  if (h->g_ab) hipGraphExecDestroy(h->g_ab);
+  if (h->g_ba) hipGraphExecDestroy(h->g_ba);
+  h->g_ab = h->g_ba = nullptr;
+}
+
+hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, int* perm_rec, double* phi_rec) {
+  hipError_t e;
+  hipEvent_t* ev = nullptr;
+  if (h->prof_n < h->prof_cap) ev = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
+  if (ev && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
+  if ((e = launch_scan(h->C, h->stream)) != hipSuccess) return e;
+  if ((e = launch_sort(h->C, in, h->stream)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
+  if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, nullptr, 0, h->C.phi, 0, 1, h->stream,
+                          ev ? ev + 2 : nullptr)) != hipSuccess)
+    return e;
+  if (phi_rec && (e = hipMemcpyAsync(phi_rec, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
+                                     h->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_push(h->C, in, out, perm_rec, h->stream)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+int capture(tf_handle* h, const PState& in, const PState& out, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_step(h, in, out, nullptr, nullptr);
+  hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+  if (e != hipSuccess) return fail(TF_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(TF_EHIP, std::string("graph capture end: ") + hipGetErrorString(e2));
+  HIPCHK(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphDestroy(g));
+  return TF_OK;
+}
+
+PState& other(tf_handle* h) { return h->cur_is_A ? h->B : h->A; }
+
+}  // namespace
+
+extern "C" {
+
+const char* tf_error_string(int code) {
+  switch (code) {
+    case TF_OK: return "ok";
+    case TF_EINVAL: return "invalid argument";
+    case TF_ESIZE: return "size limit or workspace too small";
+    case TF_EHIP: return "HIP runtime error";
+    case TF_ESTATE: return "invalid call for the handle state";
+    case TF_EOVERFLOW: return "fixed-point overflow";
+    default: return "unknown error";
+  }
+}
+
+const char* tf_last_error(void) { return g_err.c_str(); }
+
+size_t tf_workspace_size(const tf_ensemble* ens, int32_t n_ens, int32_t traj_steps) {
+  Sizes S;
+  if (check_config(ens, n_ens, &S) != TF_OK || traj_steps < 0) return 0;
+  return layout(S, n_ens, traj_steps, TF_INIT_KEEP_DEPOSIT, nullptr, nullptr);
+}
+
+int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, void* workspace,
+            size_t workspace_bytes, int32_t traj_steps, void* stream, uint32_t flags, tf_handle** out) {
+  if (!out) return fail(TF_EINVAL, "out is NULL");
+  *out = nullptr;
+  Sizes S;
+  int rc = check_config(ens, n_ens, &S);
+  if (rc != TF_OK) return rc;
+  if (traj_steps < 0 || traj_steps > 100000) return fail(TF_EINVAL, "traj_steps out of range");
+  if (!init) return fail(TF_EINVAL, "init is NULL");
+  if (!workspace) return fail(TF_EINVAL, "workspace is NULL");
+  if ((uintptr_t)workspace % 256) return fail(TF_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = layout(S, n_ens, traj_steps, flags, nullptr, nullptr);
+  if (workspace_bytes < need) return fail(TF_ESIZE, "workspace too small");
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_particles& P = init[e];
+    if (ens[e].n_particles > 0 && (!P.x || !P.y || !P.z || !P.vx || !P.vy || !P.vz || !P.q || !P.d))
+      return fail(TF_EINVAL, "initial particle pointer is NULL");
+  }
+
+  tf_handle* h = new tf_handle();
+  h->n_ens = n_ens;
+  h->flags = flags;
+  h->stream = (hipStream_t)stream;
+  h->S = S;
+  layout(S, n_ens, traj_steps, flags, workspace, h);
+
+  // host tables (same floating-point operations as the textbook definitions)
+  std::vector<double> yf(S.y_tot, 0.0), dy(S.y_tot, 0.0), vol(S.y_tot, 0.0), am(S.y_tot, 0.0),
+      ap(S.y_tot, 0.0), beta(S.y_tot, 0.0), kx2(S.kx_tot), kz2(S.kz_tot);
+  std::vector<double2> tw(S.tw_tot);
+  for (auto& kv : S.tw_off) {
+    const int n = kv.first;
+    for (int k = 0; k < n; ++k) {
+      const double a = 2.0 * M_PI * k / n;
+      tw[kv.second + k] = make_double2(std::cos(a), -std::sin(a));
+    }
+  }
+  h->eh.resize(n_ens);
+  h->p_off.assign(n_ens + 1, 0);
+  h->c_off.assign(n_ens + 1, 0);
+  int y_off = 0, kx_off = 0, kz_off = 0, st_off = 0;
+  long long s_off = 0, row_off = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_ensemble& T = ens[e];
+    Ens& E = h->eh[e];
+    E.nx = T.nx;
+    E.ny = T.ny;
+    E.nz = T.nz;
+    E.nh = T.nx / 2 + 1;
+    E.nhp = (E.nh + 3) & ~3;
+    E.np = T.n_particles;
+    E.p_off = h->p_off[e];
+    E.c_off = h->c_off[e];
+    E.s_off = s_off;
+    E.row_off = row_off;
+    E.y_off = y_off;
+    E.kx_off = kx_off;
+    E.kz_off = kz_off;
+    E.st_off = st_off;
+    E.lx = T.lx;
+    E.lz = T.lz;
+    E.ly = T.y_faces[T.ny];
+    E.dx = T.lx / T.nx;
+    E.dz = T.lz / T.nz;
+    E.dt = T.dt;
+    E.rr = T.density_ratio;
+    E.kc = T.k_c;
+    E.dU = T.delta_u;
+    E.e = T.e;
+    E.cel = T.c_el;
+    E.gp0 = (1.0 - 1.0 / T.density_ratio) * T.g[0];
+    E.gp1 = (1.0 - 1.0 / T.density_ratio) * T.g[1];
+    E.gp2 = (1.0 - 1.0 / T.density_ratio) * T.g[2];
+    E.un_bin = T.un_bin;
+    E.U = T.u_nodes;
+    radix_plan(T.nx, &E.fx);
+    E.fx.tw_off = S.tw_off.at(T.nx);
+    radix_plan(T.nz, &E.fz);
+    E.fz.tw_off = S.tw_off.at(T.nz);
+    const int ny = T.ny;
+    double* Y = &yf[y_off];
+    for (int j = 0; j <= ny; ++j) Y[j] = T.y_faces[j];
+    std::vector<double> yc(ny), hm(ny), hp(ny);
+    for (int j = 0; j < ny; ++j) {
+      dy[y_off + j] = Y[j + 1] - Y[j];
+      yc[j] = 0.5 * (Y[j] + Y[j + 1]);
+      vol[y_off + j] = (E.dx * dy[y_off + j]) * E.dz;
+    }
+    for (int j = 0; j < ny; ++j) {
+      hm[j] = (j > 0) ? yc[j] - yc[j - 1] : yc[0] - Y[0];
+      hp[j] = (j < ny - 1) ? yc[j + 1] - yc[j] : Y[ny] - yc[ny - 1];
+      am[y_off + j] = 1.0 / (dy[y_off + j] * hm[j]);
+      ap[y_off + j] = 1.0 / (dy[y_off + j] * hp[j]);
+    }
+    for (int f = 1; f < ny; ++f) beta[y_off + f] = dy[y_off + f - 1] / (dy[y_off + f - 1] + dy[y_off + f]);
+    for (int m = 0; m < E.nh; ++m)
+      kx2[kx_off + m] = (2.0 - 2.0 * std::cos(2.0 * M_PI * m / T.nx)) / (E.dx * E.dx);
+    for (int m = 0; m < T.nz; ++m)
+      kz2[kz_off + m] = (2.0 - 2.0 * std::cos(2.0 * M_PI * m / T.nz)) / (E.dz * E.dz);
+    h->p_off[e + 1] = h->p_off[e] + T.n_particles;
+    h->c_off[e + 1] = h->c_off[e] + (long long)T.nx * T.ny * T.nz;
+    s_off += (long long)ny * T.nz * E.nhp;
+    row_off += (long long)ny * T.nz;
+    y_off += ny + 1;
+    kx_off += E.nh;
+    kz_off += T.nz;
+    st_off += stats_len(ny);
+  }
+
+  auto up = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, h->stream);
+  };
+  hipError_t he = hipSuccess;
+#define UP(dst, vec) \
+  if (he == hipSuccess && !vec.empty()) he = up(dst, vec.data(), vec.size() * sizeof(vec[0]));
+  UP(h->C.ens, h->eh);
+  UP(h->C.p_off, h->p_off);
+  UP(h->C.c_off, h->c_off);
+  UP(h->d_fx, S.fx_blk);
+  UP(h->d_fz, S.fz_blk);
+  UP(h->d_tri, S.tri_blk);
+  UP(h->C.yf, yf);
+  UP(h->C.dy, dy);
+  UP(h->C.vol, vol);
+  UP(h->C.am, am);
+  UP(h->C.ap, ap);
+  UP(h->C.beta, beta);
+  UP(h->C.kx2, kx2);
+  UP(h->C.kz2, kz2);
+  UP(h->C.tw, tw);
+#undef UP
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.stats, 0, sizeof(long long) * S.st_tot, h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
+  if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.count, 0, sizeof(int) * S.c_tot, h->stream);
+  if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.phi, 0, sizeof(double) * S.c_tot, h->stream);
+  for (int e = 0; e < n_ens && he == hipSuccess; ++e) {
+    if (ens[e].n_particles == 0) continue;
+    const tf_particles& P = init[e];
+    const double* in8[8] = {P.x, P.y, P.z, P.vx, P.vy, P.vz, P.q, P.d};
+    he = launch_put_state(h->A, in8, h->p_off[e], ens[e].n_particles, h->stream);
+  }
+  if (he == hipSuccess) he = launch_bin(h->C, h->A, 0, S.n_tot, h->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(h->stream);
+  if (he != hipSuccess) {
+    delete h;
+    return fail(TF_EHIP, std::string("tf_init: ") + hipGetErrorString(he));
+  }
+  h->G.fx_rpb = S.rpb;
+  h->G.nx_max = S.nx_max;
+  h->G.nz_max = S.nz_max;
+  h->G.wz = S.wz;
+  h->G.fx_blk = h->S.fx_blk.data();
+  h->G.fz_blk = h->S.fz_blk.data();
+  h->G.tri_blk = h->S.tri_blk.data();
+  h->G.d_fx_blk = h->d_fx;
+  h->G.d_fz_blk = h->d_fz;
+  h->G.d_tri_blk = h->d_tri;
+  h->cur = h->A;
+  h->cur_is_A = true;
+  *out = h;
+  return TF_OK;
+}
+
+int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
+  if (!h) return fail(TF_EINVAL, "handle is NULL");
+  if (n_steps < 0) return fail(TF_EINVAL, "n_steps < 0");
+  if (h->C.n_tot == 0) {
+    for (int s = 0; s < n_steps; ++s) {
+      HIPCHK(launch_scan(h->C, h->stream));
+      HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, nullptr, 0, h->C.phi, 0, 1, h->stream));
+      HIPCHK(launch_push(h->C, h->cur, other(h), nullptr, h->stream));
+    }
+    return TF_OK;
+  }
+  const bool rec = (flags & TF_STEP_RECORD) != 0;
+  if (rec) {
+    if (h->traj_cap == 0) return fail(TF_ESTATE, "no trajectory capacity (traj_steps = 0 at tf_init)");
+    if (h->traj_len + n_steps > h->traj_cap) return fail(TF_ESIZE, "recorded trajectory would exceed traj_steps");
+    for (int s = 0; s < n_steps; ++s) {
+      TrajBuf& tb = h->traj[h->traj_len];
+      if (h->traj_len == 0) {
+        // the current state becomes the first recorded state
+        const size_t n = h->C.n_tot;
+        const PState& c = h->cur;
+        const PState& t = tb.st;
+        double* src[8] = {c.x, c.y, c.z, c.vx, c.vy, c.vz, c.q, c.d};
+        double* dst[8] = {t.x, t.y, t.z, t.vx, t.vy, t.vz, t.q, t.d};
+        for (int f = 0; f < 8; ++f)
+          HIPCHK(hipMemcpyAsync(dst[f], src[f], n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(t.id, c.id, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(t.key, c.key, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        h->cur = t;
+      }
+      const PState in = h->cur;
+      const PState out = h->traj[h->traj_len + 1].st;
+      HIPCHK(enqueue_step(h, in, out, tb.perm, tb.phi));
+      h->cur = out;
+      h->traj_len++;
+    }
+    return TF_OK;
+  }
+  // leave the trajectory store: continue in the ping-pong buffers
+  const bool in_traj = !(h->cur.x == h->A.x || h->cur.x == h->B.x);
+  int s = 0;
+  if (in_traj && n_steps > 0) {
+    HIPCHK(enqueue_step(h, h->cur, h->A, nullptr, nullptr));
+    h->cur = h->A;
+    h->cur_is_A = true;
+    s = 1;
+  }
+  const bool graphs = (h->flags & TF_INIT_GRAPHS) != 0 && h->prof_cap == 0;
+  if (graphs && s < n_steps) {
+    if (!h->g_ab) {
+      int rc = capture(h, h->A, h->B, &h->g_ab);
+      if (rc != TF_OK) return rc;
+      rc = capture(h, h->B, h->A, &h->g_ba);
+      if (rc != TF_OK) return rc;
+    }
+  }
+  for (; s < n_steps; ++s) {
+    if (graphs) {
+      HIPCHK(hipGraphLaunch(h->cur_is_A ? h->g_ab : h->g_ba, h->stream));
+    } else {
+      HIPCHK(enqueue_step(h, h->cur, other(h), nullptr, nullptr));
+    }
+    h->cur = other(h);
+    h->cur_is_A = !h->cur_is_A;
+  }
+  return TF_OK;
+}
+
+int tf_stats(tf_handle* h, int32_t e, tf_stats_out* out) {
+  if (!h || !out) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  const Ens& E = h->eh[e];
+  std::vector<long long> st(stats_len(E.ny)), rq((size_t)E.ny * E.nz);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(st.data(), h->C.stats + E.st_off, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rq.data(), h->C.rowq + E.row_off, rq.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  out->steps = st[ST_STEPS];
+  out->flags = (int32_t)st[ST_FLAGS];
+  out->ny = E.ny;
+  for (int w = 0; w < 2; ++w) {
+    out->impacts[w] = st[ST_IMP + w];
+    out->wall_q[w] = st[ST_WQ + w];
+  }
+  for (int b = 0; b < kNbin; ++b) out->un_hist[b] = st[ST_HIST + b];
+  __int128 tot = 0;
+  for (int j = 0; j < E.ny; ++j) {
+    long long qj = 0;
+    for (int k = 0; k < E.nz; ++k) qj += rq[(size_t)j * E.nz + k];
+    tot += qj;
+    if (out->crel_y) out->crel_y[j] = st[ST_Y + j];
+    if (out->qcum_y) out->qcum_y[j] = st[ST_Y + E.ny + j];
+    if (out->qnow_y) out->qnow_y[j] = qj;
+  }
+  out->q_sum = (double)(long double)tot * (1.0 / 281474976710656.0);
+  return TF_OK;
+}
+
+int tf_get_state(tf_handle* h, int32_t e, const tf_particles* out) {
+  if (!h || !out) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  const int n = h->eh[e].np;
+  if (n == 0) return TF_OK;
+  double* o8[8] = {out->x, out->y, out->z, out->vx, out->vy, out->vz, out->q, out->d};
+  for (auto* p : o8)
+    if (!p) return fail(TF_EINVAL, "output pointer is NULL");
+  HIPCHK(launch_get_state(h->cur, o8, h->p_off[e], n, h->stream));
+  return TF_OK;
+}
+
+int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
+  if (!h || !in) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  const int n = h->eh[e].np;
+  h->traj_len = 0;
+  // the current buffer may be a recorded one: continue in A (all ensembles)
+  if (!(h->cur.x == h->A.x || h->cur.x == h->B.x)) {
+    const size_t nt = h->C.n_tot;
+    const PState& c = h->cur;
+    const PState& t = h->A;
+    double* src[8] = {c.x, c.y, c.z, c.vx, c.vy, c.vz, c.q, c.d};
+    double* dst[8] = {t.x, t.y, t.z, t.vx, t.vy, t.vz, t.q, t.d};
+    for (int f = 0; f < 8 && nt; ++f)
+      HIPCHK(hipMemcpyAsync(dst[f], src[f], nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    if (nt) {
+      HIPCHK(hipMemcpyAsync(t.id, c.id, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(t.key, c.key, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+    }
+    h->cur = h->A;
+    h->cur_is_A = true;
+  }
+  if (n == 0) return TF_OK;
+  const double* in8[8] = {in->x, in->y, in->z, in->vx, in->vy, in->vz, in->q, in->d};
+  for (auto* p : in8)
+    if (!p) return fail(TF_EINVAL, "input pointer is NULL");
+  const long long ncell = (long long)h->eh[e].nx * h->eh[e].ny * h->eh[e].nz;
+  HIPCHK(hipMemsetAsync(h->C.count + h->c_off[e], 0, sizeof(int) * ncell, h->stream));
+  HIPCHK(launch_put_state(h->cur, in8, h->p_off[e], n, h->stream));
+  HIPCHK(launch_bin(h->C, h->cur, h->p_off[e], h->p_off[e] + n, h->stream));
+  return TF_OK;
+}
+
+int tf_set_params(tf_handle* h, const double* theta) {
+  if (!h || !theta) return fail(TF_EINVAL, "NULL argument");
+  for (int e = 0; e < h->n_ens; ++e) {
+    const double kc = theta[3 * e], du = theta[3 * e + 1], ee = theta[3 * e + 2];
+    if (!std::isfinite(kc) || !std::isfinite(du) || !(ee > 0 && ee <= 1))
+      return fail(TF_EINVAL, "theta must be finite with 0 < e <= 1");
+  }
+  for (int e = 0; e < h->n_ens; ++e) {
+    h->eh[e].kc = theta[3 * e];
+    h->eh[e].dU = theta[3 * e + 1];
+    h->eh[e].e = theta[3 * e + 2];
+  }
+  HIPCHK(hipMemcpyAsync((void*)h->C.ens, h->eh.data(), sizeof(Ens) * h->n_ens, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return TF_OK;
+}
+
+int tf_poisson(tf_handle* h, int32_t e, const int64_t* q_fixed, double* phi) {
+  if (!h || !q_fixed || !phi) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  HIPCHK(launch_poisson(h->C, h->G, e, e + 1, nullptr, (const long long*)q_fixed, h->c_off[e], phi, h->c_off[e], 0,
+                        h->stream));
+  return TF_OK;
+}
+
+int tf_field(tf_handle* h, int32_t e, int32_t which, void* out) {
+  if (!h || !out) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  const long long ncell = (long long)h->eh[e].nx * h->eh[e].ny * h->eh[e].nz;
+  if (which == TF_FIELD_PHI) {
+    HIPCHK(hipMemcpyAsync(out, h->C.phi + h->c_off[e], ncell * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else if (which == TF_FIELD_DEPOSIT) {
+    if (!h->C.qdep) return fail(TF_ESTATE, "deposit not kept (TF_INIT_KEEP_DEPOSIT)");
+    HIPCHK(hipMemcpyAsync(out, h->C.qdep + h->c_off[e], ncell * sizeof(long long), hipMemcpyDeviceToDevice,
+                          h->stream));
+  } else {
+    return fail(TF_EINVAL, "unknown field");
+  }
+  return TF_OK;
+}
+
+int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wall, double* dtheta) {
+  if (!h || !lambda || !w_wall || !dtheta) return fail(TF_EINVAL, "NULL argument");
+  if (h->traj_len == 0) return fail(TF_ESTATE, "no recorded steps (tf_step with TF_STEP_RECORD)");
+  std::vector<const double*> lam(8 * (size_t)h->n_ens);
+  for (int e = 0; e < h->n_ens; ++e) {
+    const tf_particles& L = lambda[e];
+    const double* l8[8] = {L.x, L.y, L.z, L.vx, L.vy, L.vz, L.q, L.d};
+    for (int f = 0; f < 7; ++f)
+      if (h->eh[e].np > 0 && !l8[f]) return fail(TF_EINVAL, "lambda pointer is NULL");
+    for (int f = 0; f < 8; ++f) lam[8 * e + f] = l8[f];
+  }
+  std::vector<TrajStep> steps(h->traj_len + 1);
+  for (int t = 0; t <= h->traj_len; ++t) {
+    steps[t].st = h->traj[t].st;
+    steps[t].perm = h->traj[t].perm;
+    steps[t].phi = h->traj[t].phi;
+  }
+  std::vector<double> dth(3 * (size_t)h->n_ens, 0.0);
+  hipError_t he = run_adjoint(h->C, h->G, h->adj, h->n_ens, h->eh.data(), h->p_off.data(), steps.data(),
+                              h->traj_len, lam.data(), w_wall, dth.data(), h->stream);
+  if (he != hipSuccess) return fail(TF_EHIP, std::string("adjoint: ") + hipGetErrorString(he));
+  for (size_t i = 0; i < dth.size(); ++i) dtheta[i] += dth[i];
+  h->traj_len = 0;
+  return TF_OK;
+}
+
+int tf_profile_begin(tf_handle* h, int32_t max_steps) {
+  if (!h) return fail(TF_EINVAL, "handle is NULL");
+  if (max_steps < 1 || max_steps > 100000) return fail(TF_EINVAL, "max_steps out of range");
+  if (h->prof_cap) return fail(TF_ESTATE, "profiling already active");
+  h->prof_ev.assign((size_t)max_steps * (TF_NPHASE + 1), nullptr);
+  for (auto& e : h->prof_ev) HIPCHK(hipEventCreate(&e));
+  h->prof_cap = max_steps;
+  h->prof_n = 0;
+  return TF_OK;
+}
+
+int tf_profile_end(tf_handle* h, double* phase_ms, int32_t* n_steps) {
+  if (!h || !phase_ms || !n_steps) return fail(TF_EINVAL, "NULL argument");
+  if (!h->prof_cap) return fail(TF_ESTATE, "profiling not active");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int p = 0; p < TF_NPHASE; ++p) phase_ms[p] = 0.0;
+  for (int s = 0; s < h->prof_n; ++s) {
+    hipEvent_t* ev = &h->prof_ev[(size_t)s * (TF_NPHASE + 1)];
+    for (int p = 0; p < TF_NPHASE; ++p) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
+      phase_ms[p] += ms;
+    }
+  }
+  *n_steps = h->prof_n;
+  for (auto& e : h->prof_ev) hipEventDestroy(e);
+  h->prof_ev.clear();
+  h->prof_cap = h->prof_n = 0;
+  return TF_OK;
+}
+
+void tf_destroy(tf_handle* h) {
+  if (!h) return;
+  destroy_graphs(h);
+  for (auto& e : h->prof_ev) hipEventDestroy(e);
+  delete h;
+}
+
+}  // extern "C"

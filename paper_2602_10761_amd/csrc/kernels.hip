@@ -1,0 +1,742 @@
+// Forward-step kernels of libtribo.so (gfx950, FP64, wave64).
+//
+// Per step (launch order):
+//   scan_reduce / scan_part / scan_down   count -> start (exclusive prefix)
+//   assign                                unordered slot per particle in its cell run
+//   rank                                  order each cell run by particle id -> perm
+//   dep_fftx                              cell charge from the sorted runs (exact int64),
+//                                         rho = Q 2^-48 / V, forward FFT along x
+//   fftz<fwd>                             forward FFT along z
+//   tri                                   one tridiagonal y-solve per Fourier mode
+//   fftz<inv>, ifftx                      back to phi on the cells
+//   push                                  per particle: forces, integration, wall
+//                                         impact and charging, wrap, next cell key
+//
+// Particle state is stored in the slot order of the previous step's sort; the
+// push gathers through perm (nearly coalesced) and writes in the new order.
+#include "tribo_dev.h"
+
+namespace tf {
+
+// ---------------------------------------------------------------------------
+// block-level scans (256 threads = 4 waves, or 1024 threads = 16 waves)
+// ---------------------------------------------------------------------------
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int wsum[NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    int x = wsum[i];
+    off += (i < w) ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+constexpr int kScanChunk = 4 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ cnt, long long n,
+                                                        int* __restrict__ part) {
+  const long long base = (long long)blockIdx.x * kScanChunk + 4LL * threadIdx.x;
+  int s = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (base + r < n) s += cnt[base + r];
+  int tot;
+  block_excl_scan<kBlock / 64>(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block of 1024 threads: exclusive scan of the block partials, total at part[nb]
+__global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int nb) {
+  int carry = 0;
+  for (int base = 0; base < nb; base += 1024) {
+    int i = base + threadIdx.x;
+    int v = (i < nb) ? part[i] : 0;
+    int tot;
+    int ex = block_excl_scan<16>(v, &tot);
+    if (i < nb) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cnt, long long n,
+                                                      const int* __restrict__ part, int nb,
+                                                      int* __restrict__ start) {
+  const long long base = (long long)blockIdx.x * kScanChunk + 4LL * threadIdx.x;
+  int v[4];
+  int s = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v[r] = (base + r < n) ? cnt[base + r] : 0;
+    s += v[r];
+  }
+  int tot;
+  int ex = block_excl_scan<kBlock / 64>(s, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (base + r < n) start[base + r] = ex;
+    ex += v[r];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = part[nb];
+}
+
+// ---------------------------------------------------------------------------
+// counting sort by (cell, id)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_assign(Ctx C, const int* __restrict__ key,
+                                                   const int* __restrict__ id) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= C.n_tot) return;
+  const int c = key[p];
+  const int slot = C.start[c] + atomicSub(&C.count[c], 1) - 1;
+  if (slot < C.start[c] || slot >= C.start[c + 1]) return;  // counts inconsistent with keys: never by construction
+  C.tmp[slot] = ((unsigned long long)(unsigned)id[p] << 32) | (unsigned long long)(unsigned)p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank(Ctx C, const int* __restrict__ key) {
+  const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (s >= C.n_tot) return;
+  const unsigned long long v = C.tmp[s];
+  const int p = (int)(v & 0xffffffffull);
+  const unsigned idv = (unsigned)(v >> 32);
+  if (p < 0 || p >= C.n_tot) return;
+  const int c = key[p];
+  const int a = C.start[c], b = C.start[c + 1];
+  int r = 0;
+  if (b - a > 1)
+    for (int t = a; t < b; ++t) r += ((unsigned)(C.tmp[t] >> 32) < idv) ? 1 : 0;
+  C.perm[a + r] = p;
+}
+
+// ---------------------------------------------------------------------------
+// FFT in LDS: Stockham autosort, mixed radix 2/3/4/5, runtime plan
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 mul_mi(double2 a) {
+  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void butterfly(double2* v) {
+  if constexpr (R == 2) {
+    double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    double2 c = cadd(v[1], v[3]), d = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  } else if constexpr (R == 3) {
+    const double s3 = 0.86602540378443864676;  // sin(2 pi/3)
+    double2 t = cadd(v[1], v[2]);
+    double2 u = mul_mi<INV>(csub(v[1], v[2]));
+    double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+    v[0] = cadd(v[0], t);
+    v[1] = make_double2(m.x + s3 * u.x, m.y + s3 * u.y);
+    v[2] = make_double2(m.x - s3 * u.x, m.y - s3 * u.y);
+  } else if constexpr (R == 5) {
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    double2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    double2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    double2 m1 = make_double2(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+    double2 m2 = make_double2(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+    double2 n1 = mul_mi<INV>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    double2 n2 = mul_mi<INV>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(m1, n1);
+    v[4] = csub(m1, n1);
+    v[2] = cadd(m2, n2);
+    v[3] = csub(m2, n2);
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2* __restrict__ b, int rows,
+                                         int n, int Ns, const double2* __restrict__ tw) {
+  const int nb = n / R;
+  const int stride = n / (Ns * R);
+  const int total = rows * nb;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int row = t / nb, jj = t - row * nb;
+    const double2* s = a + row * n;
+    double2* d = b + row * n;
+    const int k = jj % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[jj + r * nb];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      double2 w = tw[r * k * stride];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    butterfly<R, INV>(v);
+    const int base = (jj / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
+  }
+}
+
+// Transforms `rows` lines of length P.n held in a (scratch b); returns the
+// buffer holding the result.  Caller must __syncthreads() before the call.
+template <bool INV>
+__device__ double2* lds_fft(double2* a, double2* b, int rows, const FftPlan& P, const double2* tw) {
+  const int n = P.n;
+  int Ns = 1;
+  for (int ps = 0; ps < P.npass; ++ps) {
+    const int R = (int)((P.rcode >> (3 * ps)) & 7u);
+    switch (R) {
+      case 2: fft_pass<2, INV>(a, b, rows, n, Ns, tw); break;
+      case 3: fft_pass<3, INV>(a, b, rows, n, Ns, tw); break;
+      case 4: fft_pass<4, INV>(a, b, rows, n, Ns, tw); break;
+      default: fft_pass<5, INV>(a, b, rows, n, Ns, tw); break;
+    }
+    __syncthreads();
+    double2* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// deposit + forward FFT along x, one block = rpb rows (j, k) of one ensemble
+// ---------------------------------------------------------------------------
+// q source: particles (q_in == nullptr) or a per-cell fixed-point array
+__global__ __launch_bounds__(kBlock) void k_dep_fftx(Ctx C, const double* __restrict__ q,
+                                                     const int* __restrict__ blk_off, int blk0, int rpb,
+                                                     int nmax, const long long* __restrict__ q_in,
+                                                     long long q_shift, int do_stats) {
+  extern __shared__ double2 lds[];
+  double2* buf0 = lds;
+  double2* buf1 = lds + rpb * nmax;
+  double2* tw = lds + 2 * rpb * nmax;
+  unsigned long long* racc = (unsigned long long*)(tw + nmax);  // [rpb][3]
+
+  const int gb = blk0 + blockIdx.x;
+  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+  const Ens& E = C.ens[e];
+  const int nx = E.nx, nz = E.nz;
+  const int nrow_e = E.ny * nz;
+  const int r0 = (gb - blk_off[e]) * rpb;
+  const int nrows = min(rpb, nrow_e - r0);
+
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = C.tw[E.fx.tw_off + t];
+  for (int t = threadIdx.x; t < 3 * rpb; t += blockDim.x) racc[t] = 0ull;
+  __syncthreads();
+
+  bool ovf = false;
+  const int ncell = nrows * nx;
+  for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+    const int row = t / nx, i = t - row * nx;
+    const int jk = r0 + row;
+    const long long cg = E.c_off + (long long)jk * nx + i;
+    long long Q = 0, Q32 = 0;
+    int cnt = 0;
+    if (q_in) {
+      Q = q_in[cg - q_shift];
+    } else {
+      const int a = C.start[cg], b = C.start[cg + 1];
+      cnt = b - a;
+      for (int s = a; s < b; ++s) {
+        const double qv = q[C.perm[s]];
+        Q += fixed_round(qv, kFixDep, &ovf);
+        Q32 += fixed_round(qv, kFixQcum, &ovf);
+      }
+      if (C.qdep) C.qdep[cg] = Q;
+    }
+    const int j = jk / nz;
+    const double rho = ((double)Q * (1.0 / 281474976710656.0)) / C.vol[E.y_off + j];
+    buf0[row * nx + i] = make_double2(rho, 0.0);
+    if (do_stats) {
+      if (cnt) atomicAdd(&racc[3 * row + 0], (unsigned long long)cnt);
+      if (Q32) atomicAdd(&racc[3 * row + 1], (unsigned long long)Q32);
+      if (Q) atomicAdd(&racc[3 * row + 2], (unsigned long long)Q);
+    }
+  }
+  if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+  __syncthreads();
+
+  FftPlan P = E.fx;
+  double2* a = buf0;
+  double2* b = buf1;
+  double2* res = lds_fft<false>(a, b, nrows, P, tw);
+
+  const int nh = E.nh, nhp = E.nhp;
+  for (int t = threadIdx.x; t < nrows * nh; t += blockDim.x) {
+    const int row = t / nh, m = t - row * nh;
+    C.spec[E.s_off + (long long)(r0 + row) * nhp + m] = res[row * nx + m];
+  }
+  if (do_stats && threadIdx.x < nrows) {
+    const int row = threadIdx.x;
+    const int jk = r0 + row;
+    const int j = jk / nz;
+    long long* st = C.stats + E.st_off;
+    atomicAdd((unsigned long long*)&st[ST_Y + j], racc[3 * row + 0]);
+    atomicAdd((unsigned long long*)&st[ST_Y + E.ny + j], racc[3 * row + 1]);
+    C.rowq[E.row_off + jk] = (long long)racc[3 * row + 2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FFT along z on the half spectrum: block = (ensemble, y plane, wz columns)
+// ---------------------------------------------------------------------------
+template <bool INV>
+__global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, const int* __restrict__ blk_off, int blk0, int wz,
+                                                 int nmax) {
+  extern __shared__ double2 lds[];
+  double2* buf0 = lds;
+  double2* buf1 = lds + wz * nmax;
+  double2* tw = lds + 2 * wz * nmax;
+  const int gb = blk0 + blockIdx.x;
+  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+  const Ens& E = C.ens[e];
+  const int nz = E.nz, nh = E.nh, nhp = E.nhp;
+  const int nchunk = (nh + wz - 1) / wz;
+  const int lb = gb - blk_off[e];
+  const int j = lb / nchunk;
+  const int m0 = (lb - j * nchunk) * wz;
+  const int w = min(wz, nh - m0);
+  for (int t = threadIdx.x; t < nz; t += blockDim.x) tw[t] = C.tw[E.fz.tw_off + t];
+  double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
+  for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
+    const int c = t % w, k = t / w;
+    buf0[c * nz + k] = sp[(long long)k * nhp + c];
+  }
+  __syncthreads();
+  FftPlan P = E.fz;
+  double2* res = lds_fft<INV>(buf0, buf1, w, P, tw);
+  const double sc = INV ? 1.0 / (double)nz : 1.0;
+  for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
+    const int c = t % w, k = t / w;
+    double2 v = res[c * nz + k];
+    if (INV) v = make_double2(v.x * sc, v.y * sc);
+    sp[(long long)k * nhp + c] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tridiagonal solve in y, one thread per Fourier mode (mz, mx)
+//   -am_j phi_{j-1} + (am_j + ap_j + k^2) phi_j - ap_j phi_{j+1} = rho_j
+// (FV Laplacian times -1, phi = 0 on both walls)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tri(Ctx C, const int* __restrict__ blk_off, int blk0) {
+  const int gb = blk0 + blockIdx.x;
+  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+  const Ens& E = C.ens[e];
+  const int mode = (gb - blk_off[e]) * kBlock + threadIdx.x;
+  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  if (mode >= nh * nz) return;
+  const int mz = mode / nh, m = mode - mz * nh;
+  const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
+  const double* am = C.am + E.y_off;
+  const double* ap = C.ap + E.y_off;
+  const long long pitch = (long long)nz * nhp;
+  double2* sp = C.spec + E.s_off + (long long)mz * nhp + m;
+  double* cp = C.cp + E.s_off + (long long)mz * nhp + m;
+  // forward elimination
+  double diag = (am[0] + ap[0]) + K2;
+  double cpv = (-ap[0]) / diag;
+  double2 r = sp[0];
+  double2 dp = make_double2(r.x / diag, r.y / diag);
+  cp[0] = cpv;
+  sp[0] = dp;
+  for (int j = 1; j < ny; ++j) {
+    const double lo = -am[j];
+    const double dg = (am[j] + ap[j]) + K2;
+    const double piv = dg - lo * cpv;
+    cpv = (-ap[j]) / piv;
+    r = sp[j * pitch];
+    dp = make_double2((r.x - lo * dp.x) / piv, (r.y - lo * dp.y) / piv);
+    cp[j * pitch] = cpv;
+    sp[j * pitch] = dp;
+  }
+  // back substitution
+  double2 xv = dp;
+  for (int j = ny - 2; j >= 0; --j) {
+    const double c = cp[j * pitch];
+    const double2 d = sp[j * pitch];
+    xv = make_double2(d.x - c * xv.x, d.y - c * xv.y);
+    sp[j * pitch] = xv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse FFT along x (Hermitian half spectrum -> real), phi on the cells
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ifftx(Ctx C, const int* __restrict__ blk_off, int blk0, int rpb,
+                                                  int nmax, double* __restrict__ phi_out, long long phi_shift) {
+  extern __shared__ double2 lds[];
+  double2* buf0 = lds;
+  double2* buf1 = lds + rpb * nmax;
+  double2* tw = lds + 2 * rpb * nmax;
+  const int gb = blk0 + blockIdx.x;
+  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+  const Ens& E = C.ens[e];
+  const int nx = E.nx, nh = E.nh, nhp = E.nhp;
+  const int r0 = (gb - blk_off[e]) * rpb;
+  const int nrows = min(rpb, E.ny * E.nz - r0);
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = C.tw[E.fx.tw_off + t];
+  for (int t = threadIdx.x; t < nrows * nx; t += blockDim.x) {
+    const int row = t / nx, i = t - row * nx;
+    const double2* sp = C.spec + E.s_off + (long long)(r0 + row) * nhp;
+    double2 v;
+    if (i < nh) {
+      v = sp[i];
+    } else {
+      v = sp[nx - i];
+      v.y = -v.y;
+    }
+    buf0[row * nx + i] = v;
+  }
+  __syncthreads();
+  FftPlan P = E.fx;
+  double2* res = lds_fft<true>(buf0, buf1, nrows, P, tw);
+  const double sc = 1.0 / (double)nx;
+  double* out = phi_out + (E.c_off - phi_shift) + (long long)r0 * nx;
+  for (int t = threadIdx.x; t < nrows * nx; t += blockDim.x) out[t] = res[t].x * sc;
+}
+
+// ---------------------------------------------------------------------------
+// particle helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int clamp_floor(double v, int n) {
+  const double f = floor(v);
+  return (f >= 0.0) ? (f < (double)(n - 1) ? (int)f : n - 1) : 0;
+}
+
+// local cell (j*nz + k)*nx + i holding (x, y, z): floor in x, z; face search in y
+__device__ __forceinline__ int locate_local(const Ens& E, const double* __restrict__ yf, double x, double y,
+                                            double z) {
+  const int i = clamp_floor(x / E.dx, E.nx);
+  const int k = clamp_floor(z / E.dz, E.nz);
+  int lo = 0, hi = E.ny - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (yf[mid] <= y) lo = mid; else hi = mid - 1;
+  }
+  return (lo * E.nz + k) * E.nx + i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, long long n1) {
+  const long long p = n0 + (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n1) return;
+  const int e = find_off(C.p_off, C.n_ens + 1, p);
+  const Ens& E = C.ens[e];
+  const int c = (int)(E.c_off + locate_local(E, C.yf + E.y_off, S.x[p], S.y[p], S.z[p]));
+  S.key[p] = c;
+  atomicAdd(&C.count[c], 1);
+}
+
+// ---------------------------------------------------------------------------
+// the particle push
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, int* __restrict__ perm_rec) {
+  const long long nblk = gridDim.x;
+  const long long s = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (s >= C.n_tot) return;
+  const int p = C.perm[s];
+  if (perm_rec) perm_rec[s] = p;
+  const int c = in.key[p];
+  const int e = find_off(C.c_off, C.n_ens + 1, c);
+  const Ens& E = C.ens[e];
+  const int nx = E.nx, ny = E.ny, nz = E.nz;
+  const int cl = (int)(c - E.c_off);
+  const int i = cl % nx;
+  const int jk = cl / nx;
+  const int k = jk % nz;
+  const int j = jk / nz;
+  const double* __restrict__ yf = C.yf + E.y_off;
+  const double* __restrict__ dyt = C.dy + E.y_off;
+
+  const double x = in.x[p], y = in.y[p], z = in.z[p];
+  const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
+  const double q = in.q[p], d = in.d[p];
+
+  // carrier velocity: trilinear in the cell, linear in physical y
+  const int i1 = (i + 1 == nx) ? 0 : i + 1;
+  const int k1 = (k + 1 == nz) ? 0 : k + 1;
+  const double tx = (x - (double)i * E.dx) / E.dx;
+  const double ty = (y - yf[j]) / dyt[j];
+  const double tz = (z - (double)k * E.dz) / E.dz;
+  const long long plane = (long long)(ny + 1) * nz * nx;
+  const long long n00 = ((long long)j * nz + k) * nx, n01 = ((long long)j * nz + k1) * nx;
+  const long long n10 = ((long long)(j + 1) * nz + k) * nx, n11 = ((long long)(j + 1) * nz + k1) * nx;
+  double uc[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const double* __restrict__ b = E.U + cc * plane;
+    const double c00 = b[n00 + i] * (1.0 - tx) + b[n00 + i1] * tx;
+    const double c01 = b[n01 + i] * (1.0 - tx) + b[n01 + i1] * tx;
+    const double c10 = b[n10 + i] * (1.0 - tx) + b[n10 + i1] * tx;
+    const double c11 = b[n11 + i] * (1.0 - tx) + b[n11 + i1] * tx;
+    const double c0 = c00 * (1.0 - tz) + c01 * tz;
+    const double c1 = c10 * (1.0 - tz) + c11 * tz;
+    uc[cc] = c0 * (1.0 - ty) + c1 * ty;
+  }
+
+  // Gauss part: cell-centred E = -grad(phi), Gauss-linear, phi = 0 on the walls
+  const double* __restrict__ ph = C.phi + E.c_off;
+  const int im = (i == 0) ? nx - 1 : i - 1;
+  const int km = (k == 0) ? nz - 1 : k - 1;
+  const double pc = ph[cl];
+  const double Ex = -(ph[n00 + i1] - ph[n00 + im]) / (2.0 * E.dx);
+  const double Ez = -(ph[n01 + i] - ph[((long long)j * nz + km) * nx + i]) / (2.0 * E.dz);
+  double ftop = 0.0, fbot = 0.0;
+  if (j < ny - 1) {
+    const double pn = ph[n10 + i];
+    ftop = pc + C.beta[E.y_off + j + 1] * (pn - pc);
+  }
+  if (j > 0) {
+    const double pm = ph[((long long)(j - 1) * nz + k) * nx + i];
+    fbot = pm + C.beta[E.y_off + j] * (pc - pm);
+  }
+  const double Ey = -(ftop - fbot) / dyt[j];
+
+  // near field: Coulomb's law with the other particles of the cell, ascending id
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  {
+    const int a = C.start[c], b = C.start[c + 1];
+    for (int t = a; t < b; ++t) {
+      if (t == s) continue;
+      const int pj = C.perm[t];
+      const double rx = x - in.x[pj], ry = y - in.y[pj], rz = z - in.z[pj];
+      const double r2 = (rx * rx + ry * ry) + rz * rz;
+      if (r2 > 0.0) {
+        const double w = in.q[pj] / (r2 * sqrt(r2));
+        sx = sx + w * rx;
+        sy = sy + w * ry;
+        sz = sz + w * rz;
+      }
+    }
+  }
+
+  // forces and semi-implicit Euler
+  const double ke = (E.cel * q) / ((d * d) * d);
+  const double ax = E.gp0 + ke * (Ex + sx * kInv4Pi);
+  const double ay = E.gp1 + ke * (Ey + sy * kInv4Pi);
+  const double az = E.gp2 + ke * (Ez + sz * kInv4Pi);
+  const double dux = vx - uc[0], duy = vy - uc[1], duz = vz - uc[2];
+  const double rel = sqrt((dux * dux + duy * duy) + duz * duz);
+  const double re = rel * d;
+  const double phid = (re <= 1000.0) ? 1.0 + pow(re, 2.0 / 3.0) / 6.0 : 0.424 * re / 24.0;
+  const double taup = ((E.rr * d) * d) / 18.0;
+  const double sdr = phid / taup;
+  const double den = 1.0 + E.dt * sdr;
+  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) / den;
+  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) / den;
+  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) / den;
+  double x1 = x + E.dt * v1x;
+  const double y1 = y + E.dt * v1y;
+  double z1 = z + E.dt * v1z;
+
+  // wall impact: rebound with restitution e, condenser charge transfer
+  const double r = 0.5 * d;
+  const double top = E.ly - r;
+  int wall = -1;
+  double un = 0.0, yr = y1, vyr = v1y, q1 = q;
+  if (y1 < r) {
+    wall = 0;
+    un = -v1y;
+    yr = r + E.e * (r - y1);
+  } else if (y1 > top) {
+    wall = 1;
+    un = v1y;
+    yr = top - E.e * (y1 - top);
+  }
+  long long* st = C.stats + E.st_off;
+  if (wall >= 0) {
+    vyr = -E.e * v1y;
+    const double f = (E.kc * pow(1.0 + E.e, 0.4)) * pow(un, 0.8);
+    const double dq = -f * (E.dU + q);
+    q1 = q + dq;
+    bool ovf = false;
+    const long long wq = fixed_round(-dq, kFixWall, &ovf);
+    atomicAdd((unsigned long long*)&st[ST_IMP + wall], 1ull);
+    atomicAdd((unsigned long long*)&st[ST_WQ + wall], (unsigned long long)wq);
+    const double bf = un / E.un_bin;
+    const int bin = (bf < (double)(kNbin - 1)) ? (int)bf : kNbin - 1;
+    atomicAdd((unsigned long long*)&st[ST_HIST + bin], 1ull);
+    int fl = ovf ? FLAG_OVERFLOW : 0;
+    if (yr < r || yr > top) fl |= FLAG_OUTSIDE;
+    if (fl) atomicOr((unsigned long long*)&st[ST_FLAGS], (unsigned long long)fl);
+  }
+
+  // periodic wrap
+  if (x1 >= E.lx) x1 = x1 - E.lx;
+  else if (x1 < 0.0) x1 = x1 + E.lx;
+  if (z1 >= E.lz) z1 = z1 - E.lz;
+  else if (z1 < 0.0) z1 = z1 + E.lz;
+
+  if (!(isfinite(x1) && isfinite(yr) && isfinite(z1) && isfinite(v1x) && isfinite(vyr) && isfinite(v1z) &&
+        isfinite(q1)))
+    atomicOr((unsigned long long*)&st[ST_FLAGS], (unsigned long long)FLAG_NONFINITE);
+
+  out.x[s] = x1;
+  out.y[s] = yr;
+  out.z[s] = z1;
+  out.vx[s] = v1x;
+  out.vy[s] = vyr;
+  out.vz[s] = v1z;
+  out.q[s] = q1;
+  out.d[s] = d;
+  out.id[s] = in.id[p];
+  const int key = (int)(E.c_off + locate_local(E, yf, x1, yr, z1));
+  out.key[s] = key;
+  atomicAdd(&C.count[key], 1);
+}
+
+// ---------------------------------------------------------------------------
+// state in/out (id order) and bookkeeping
+// ---------------------------------------------------------------------------
+struct PIn {
+  const double *x, *y, *z, *vx, *vy, *vz, *q, *d;
+};
+
+__global__ __launch_bounds__(kBlock) void k_put_state(PState S, PIn in, long long p0, int n) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const long long p = p0 + t;
+  S.x[p] = in.x[t];
+  S.y[p] = in.y[t];
+  S.z[p] = in.z[t];
+  S.vx[p] = in.vx[t];
+  S.vy[p] = in.vy[t];
+  S.vz[p] = in.vz[t];
+  S.q[p] = in.q[t];
+  S.d[p] = in.d[t];
+  S.id[p] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_state(PState S, PIn out, long long p0, int n) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const long long p = p0 + t;
+  const int id = S.id[p];
+  ((double*)out.x)[id] = S.x[p];
+  ((double*)out.y)[id] = S.y[p];
+  ((double*)out.z)[id] = S.z[p];
+  ((double*)out.vx)[id] = S.vx[p];
+  ((double*)out.vy)[id] = S.vy[p];
+  ((double*)out.vz)[id] = S.vz[p];
+  ((double*)out.q)[id] = S.q[p];
+  ((double*)out.d)[id] = S.d[p];
+}
+
+__global__ void k_step_count(Ctx C, int e0, int e1) {
+  const int e = e0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < e1) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+}
+
+// ---------------------------------------------------------------------------
+// host-callable launchers (used by api.hip)
+// ---------------------------------------------------------------------------
+}  // namespace tf
+
+#include "launch.h"
+
+namespace tf {
+
+hipError_t launch_scan(const Ctx& C, hipStream_t st) {
+  const long long n = C.c_tot;
+  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+  k_scan_reduce<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part);
+  k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb);
+  k_scan_down<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part, nb, C.start);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st) {
+  const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
+  if (nb == 0) return hipSuccess;
+  k_assign<<<nb, kBlock, 0, st>>>(C, cur.key, cur.id);
+  k_rank<<<nb, kBlock, 0, st>>>(C, cur.key);
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q,
+                          const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
+                          int do_stats, hipStream_t st, hipEvent_t* ev) {
+  auto mark = [&](int i) {
+    if (ev) hipEventRecord(ev[i], st);
+  };
+  {
+    const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
+    const size_t lds = (size_t)(2 * G.fx_rpb * G.nx_max + G.nx_max) * sizeof(double2) +
+                       (size_t)3 * G.fx_rpb * sizeof(long long);
+    if (nb > 0)
+      k_dep_fftx<<<nb, kBlock, lds, st>>>(C, q, G.d_fx_blk, b0, G.fx_rpb, G.nx_max, q_in, q_shift, do_stats);
+    mark(0);
+  }
+  {
+    const int b0 = G.fz_blk[e0], nb = G.fz_blk[e1] - b0;
+    const size_t lds = (size_t)(2 * G.wz * G.nz_max + G.nz_max) * sizeof(double2);
+    if (nb > 0) k_fftz<false><<<nb, kBlock, lds, st>>>(C, G.d_fz_blk, b0, G.wz, G.nz_max);
+    mark(1);
+    const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
+    if (nt > 0) k_tri<<<nt, kBlock, 0, st>>>(C, G.d_tri_blk, t0);
+    mark(2);
+    if (nb > 0) k_fftz<true><<<nb, kBlock, lds, st>>>(C, G.d_fz_blk, b0, G.wz, G.nz_max);
+    mark(3);
+  }
+  {
+    const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
+    const size_t lds = (size_t)(2 * G.fx_rpb * G.nx_max + G.nx_max) * sizeof(double2);
+    if (nb > 0) k_ifftx<<<nb, kBlock, lds, st>>>(C, G.d_fx_blk, b0, G.fx_rpb, G.nx_max, phi_out, phi_shift);
+    mark(4);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_push(const Ctx& C, const PState& in, const PState& out, int* perm_rec, hipStream_t st) {
+  const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
+  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, in, out, perm_rec);
+  k_step_count<<<(C.n_ens + kBlock - 1) / kBlock, kBlock, 0, st>>>(C, 0, C.n_ens);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st) {
+  if (n1 <= n0) return hipSuccess;
+  const int nb = (int)((n1 - n0 + kBlock - 1) / kBlock);
+  k_bin<<<nb, kBlock, 0, st>>>(C, S, n0, n1);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_state(const PState& S, const double* const* in8, long long p0, int n, hipStream_t st) {
+  PIn in{in8[0], in8[1], in8[2], in8[3], in8[4], in8[5], in8[6], in8[7]};
+  k_put_state<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(S, in, p0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const PState& S, double* const* out8, long long p0, int n, hipStream_t st) {
+  PIn out{out8[0], out8[1], out8[2], out8[3], out8[4], out8[5], out8[6], out8[7]};
+  k_get_state<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(S, out, p0, n);
+  return hipGetLastError();
+}
+
+}  // namespace tf

@@ -1,0 +1,45 @@
+// Host-side launch geometry and kernel launchers (internal).
+#pragma once
+#include "tribo_dev.h"
+
+namespace tf {
+
+// bump allocator over the caller's workspace (base == nullptr: size only)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// Block tables of the cell-structured kernels: blocks of ensemble e are
+// [xx_blk[e], xx_blk[e+1]) (host copies) / d_xx_blk (device copies).
+struct LaunchGeo {
+  int fx_rpb;      // (j,k) rows per block in the x transforms
+  int nx_max, nz_max;
+  int wz;          // spectral columns per block in the z transforms
+  const int* fx_blk;
+  const int* fz_blk;
+  const int* tri_blk;
+  const int* d_fx_blk;
+  const int* d_fz_blk;
+  const int* d_tri_blk;
+};
+
+hipError_t launch_scan(const Ctx& C, hipStream_t st);
+hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st);
+hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q,
+                          const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
+                          int do_stats, hipStream_t st, hipEvent_t* ev = nullptr);
+hipError_t launch_push(const Ctx& C, const PState& in, const PState& out, int* perm_rec, hipStream_t st);
+hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);
+hipError_t launch_put_state(const PState& S, const double* const* in8, long long p0, int n, hipStream_t st);
+hipError_t launch_get_state(const PState& S, double* const* out8, long long p0, int n, hipStream_t st);
+
+}  // namespace tf

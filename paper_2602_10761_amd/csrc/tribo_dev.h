@@ -1,0 +1,108 @@
+// Internal device-side definitions shared by the kernels and the C-ABI layer
+// of libtribo.so.  Not a public header.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tf {
+
+constexpr int kMaxPass = 10;
+constexpr int kNbin = 64;
+constexpr int kBlock = 256;
+constexpr int kFixDep = 48;
+constexpr int kFixWall = 40;
+constexpr int kFixQcum = 32;
+constexpr double kInv4Pi = 1.0 / (4.0 * 3.14159265358979323846);
+
+// Complex FFT of length n, Stockham autosort; the radix of pass p is
+// (rcode >> 3p) & 7, passes in order.
+struct FftPlan {
+  int n, npass, tw_off;
+  unsigned rcode;
+};
+
+// One ensemble as seen by the kernels.
+struct Ens {
+  int nx, ny, nz, nh, nhp, np;
+  long long p_off;   // first particle slot of this ensemble
+  long long c_off;   // first cell (global cell index = c_off + (j*nz + k)*nx + i)
+  long long s_off;   // first spectrum entry ([ny][nz][nhp] complex)
+  long long row_off; // first (j, k) row
+  int y_off;         // first entry in the per-y tables (ny+1 reserved)
+  int kx_off, kz_off;
+  int st_off;        // first int64 of the statistics block
+  double lx, ly, lz, dx, dz;
+  double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
+  const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
+  FftPlan fx, fz;
+};
+
+// statistics block (int64) of one ensemble: header, then crel_y[ny], qcum_y[ny]
+enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_Y = 6 + kNbin };
+inline int stats_len(int ny) { return ST_Y + 2 * ny; }
+
+enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
+
+// Particle buffer (structure of arrays).  key = global cell of the position.
+struct PState {
+  double *x, *y, *z, *vx, *vy, *vz, *q, *d;
+  int *id, *key;
+};
+
+// Everything the kernels share (device pointers into the workspace).
+struct Ctx {
+  const Ens* ens;
+  const long long* p_off;    // [n_ens+1] particle slot offsets
+  const long long* c_off;    // [n_ens+1] cell offsets
+  int n_ens;
+  int pad0;
+  long long n_tot, c_tot;
+  int* count;                // [c_tot]   particles per cell (built by atomics)
+  int* start;                // [c_tot+1] exclusive prefix of count
+  unsigned long long* tmp;   // [n_tot]   (id << 32 | old slot), unordered within a cell
+  int* perm;                 // [n_tot]   new slot -> old slot, ordered by (cell, id)
+  int* scan_part;            // scan block partials
+  double2* spec;             // spectra
+  double* cp;                // Thomas scratch (same indexing as spec)
+  double* phi;               // [c_tot]   potential of the latest step
+  long long* stats;          // statistics blocks
+  long long* rowq;           // [sum ny*nz] sum rne(q 2^48) per (j,k) row, latest deposit
+  long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
+  const double *yf, *dy, *vol, *am, *ap, *beta, *kx2, *kz2;
+  const double2* tw;         // twiddles exp(-2 pi i k/n)
+};
+
+__device__ __forceinline__ int find_off(const long long* off, int n, long long v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_off_i(const int* off, int n, int v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD gets a
+// contiguous range of logical blocks (neighbouring particles share L2 lines).
+__device__ __forceinline__ long long xcd_block(long long b, long long nb) {
+  const long long nx = 8;
+  long long q = nb / nx, r = nb % nx;
+  long long x = b % nx, w = b / nx;
+  return x * q + (x < r ? x : r) + w;
+}
+
+__device__ __forceinline__ long long fixed_round(double v, int shift, bool* ovf) {
+  double s = rint(v * (double)(1ULL << shift));
+  if (!(fabs(s) < 4.0e18)) { *ovf = true; return 0; }
+  return (long long)s;
+}
+
+}  // namespace tf

@@ -1,0 +1,262 @@
+"""Thin Python binding of libtribo.so (include/tribo.h): argument marshalling only.
+
+PyTorch supplies device memory and the stream; every step of the particle
+phase runs in the library's HIP kernels.  Importing this module does not load
+the library; the first TriboSim (or ``lib()``) does, and raises if it is not
+built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_double, c_int32, c_int64, c_uint32, c_void_p
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtribo.so")
+
+TF_INIT_KEEP_DEPOSIT = 1
+TF_INIT_GRAPHS = 2
+TF_STEP_RECORD = 1
+TF_FIELD_PHI = 0
+TF_FIELD_DEPOSIT = 1
+TF_NBIN = 64
+TF_NPHASE = 7
+PHASES = ("sort", "deposit_fftx", "fftz_fwd", "tridiag", "fftz_inv", "ifftx", "push")
+FIX_DEPOSIT, FIX_WALL, FIX_QCUM = 48, 40, 32
+KEYS = ("x", "y", "z", "vx", "vy", "vz", "q", "d")
+
+
+class TfEnsemble(Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("n_particles", c_int32),
+                ("lx", c_double), ("lz", c_double), ("y_faces", POINTER(c_double)),
+                ("dt", c_double), ("density_ratio", c_double), ("k_c", c_double), ("delta_u", c_double),
+                ("e", c_double), ("c_el", c_double), ("g", c_double * 3), ("un_bin", c_double),
+                ("u_nodes", c_void_p)]
+
+
+class TfParticles(Structure):
+    _fields_ = [(k, c_void_p) for k in KEYS]
+
+
+class TfStatsOut(Structure):
+    _fields_ = [("steps", c_int64), ("flags", c_int32), ("ny", c_int32), ("impacts", c_int64 * 2),
+                ("wall_q", c_int64 * 2), ("un_hist", c_int64 * TF_NBIN), ("crel_y", POINTER(c_int64)),
+                ("qcum_y", POINTER(c_int64)), ("qnow_y", POINTER(c_int64)), ("q_sum", c_double)]
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (python -m paper_2602_10761_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.tf_workspace_size.restype = ctypes.c_size_t
+        L.tf_workspace_size.argtypes = [POINTER(TfEnsemble), c_int32, c_int32]
+        L.tf_init.argtypes = [POINTER(TfEnsemble), c_int32, POINTER(TfParticles), c_void_p, ctypes.c_size_t,
+                              c_int32, c_void_p, c_uint32, POINTER(c_void_p)]
+        L.tf_step.argtypes = [c_void_p, c_int32, c_uint32]
+        L.tf_stats.argtypes = [c_void_p, c_int32, POINTER(TfStatsOut)]
+        L.tf_get_state.argtypes = [c_void_p, c_int32, POINTER(TfParticles)]
+        L.tf_set_state.argtypes = [c_void_p, c_int32, POINTER(TfParticles)]
+        L.tf_set_params.argtypes = [c_void_p, POINTER(c_double)]
+        L.tf_adjoint_step.argtypes = [c_void_p, POINTER(TfParticles), POINTER(c_double), POINTER(c_double)]
+        L.tf_poisson.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+        L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
+        L.tf_profile_begin.argtypes = [c_void_p, c_int32]
+        L.tf_profile_end.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
+        L.tf_destroy.argtypes = [c_void_p]
+        L.tf_destroy.restype = None
+        L.tf_error_string.restype = ctypes.c_char_p
+        L.tf_error_string.argtypes = [ctypes.c_int]
+        L.tf_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+class TriboError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        L = lib()
+        raise TriboError(f"{L.tf_error_string(rc).decode()} ({rc}): {L.tf_last_error().decode()}")
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+class TriboSim:
+    """Ensembles of particles stepped by libtribo.so on one GPU.
+
+    ensembles: sequence of paper_2602_10761_amd.workload.Ensemble (host numpy
+    inputs); they are copied to the device once.
+    """
+
+    def __init__(self, ensembles: Sequence, device: str = "cuda", traj_steps: int = 0, graphs: bool = False,
+                 keep_deposit: bool = False):
+        import torch
+
+        self.torch = torch
+        self.L = lib()
+        self.dev = torch.device(device)
+        self.ens = list(ensembles)
+        self.n_ens = len(self.ens)
+        self.stream = torch.cuda.Stream(self.dev)
+        t = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.dev)
+        self._keep = []
+        self.U = [t(E.U) for E in self.ens]
+        self._yf = [np.ascontiguousarray(E.mesh.yf, dtype=np.float64) for E in self.ens]
+        cfg = (TfEnsemble * self.n_ens)()
+        init = (TfParticles * self.n_ens)()
+        init_t = []
+        for e, E in enumerate(self.ens):
+            c = cfg[e]
+            c.nx, c.ny, c.nz, c.n_particles = E.mesh.nx, E.mesh.ny, E.mesh.nz, E.n
+            c.lx, c.lz = E.mesh.lx, E.mesh.lz
+            c.y_faces = self._yf[e].ctypes.data_as(POINTER(c_double))
+            p = E.params
+            c.dt, c.density_ratio, c.k_c, c.delta_u, c.e, c.c_el = (p["dt"], p["density_ratio"], p["k_c"],
+                                                                    p["delta_u"], p["e"], p["c_el"])
+            for i in range(3):
+                c.g[i] = p["g"][i]
+            c.un_bin = p["un_bin"]
+            c.u_nodes = self.U[e].data_ptr()
+            arrs = {k: t(getattr(E, k)) for k in KEYS}
+            init_t.append(arrs)
+            for k in KEYS:
+                setattr(init[e], k, arrs[k].data_ptr())
+        self.cfg = cfg
+        nbytes = self.L.tf_workspace_size(cfg, self.n_ens, traj_steps)
+        if nbytes == 0:
+            raise TriboError("invalid configuration (tf_workspace_size returned 0)")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        flags = (TF_INIT_KEEP_DEPOSIT if keep_deposit else 0) | (TF_INIT_GRAPHS if graphs else 0)
+        h = c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.dev))
+        _check(self.L.tf_init(cfg, self.n_ens, init, c_void_p(self.ws_ptr), nbytes, traj_steps,
+                              c_void_p(self.stream.cuda_stream), flags, ctypes.byref(h)))
+        self.h = h
+        self.traj_steps = traj_steps
+
+    # ------------------------------------------------------------------
+    def _sync_in(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.dev))
+
+    def _sync_out(self):
+        self.torch.cuda.current_stream(self.dev).wait_stream(self.stream)
+
+    def step(self, n: int = 1, record: bool = False):
+        _check(self.L.tf_step(self.h, n, TF_STEP_RECORD if record else 0))
+
+    def stats(self, e: int = 0) -> Dict[str, np.ndarray]:
+        ny = self.ens[e].mesh.ny
+        crel = np.zeros(ny, dtype=np.int64)
+        qcum = np.zeros(ny, dtype=np.int64)
+        qnow = np.zeros(ny, dtype=np.int64)
+        o = TfStatsOut()
+        o.crel_y = crel.ctypes.data_as(POINTER(c_int64))
+        o.qcum_y = qcum.ctypes.data_as(POINTER(c_int64))
+        o.qnow_y = qnow.ctypes.data_as(POINTER(c_int64))
+        _check(self.L.tf_stats(self.h, e, ctypes.byref(o)))
+        return dict(steps=o.steps, flags=o.flags, impacts=np.array(o.impacts[:]), wallq=np.array(o.wall_q[:]),
+                    unhist=np.array(o.un_hist[:]), crel_y=crel, qcum_y=qcum, qnow_y=qnow, q_sum=o.q_sum)
+
+    def state(self, e: int = 0) -> Dict[str, "object"]:
+        """Current particle state of ensemble e (device tensors, id order)."""
+        n = self.ens[e].n
+        out = {k: self.torch.empty(n, dtype=self.torch.float64, device=self.dev) for k in KEYS}
+        P = TfParticles(*[out[k].data_ptr() for k in KEYS])
+        self._sync_in()
+        _check(self.L.tf_get_state(self.h, e, ctypes.byref(P)))
+        self._sync_out()
+        return out
+
+    def state_np(self, e: int = 0) -> Dict[str, np.ndarray]:
+        return {k: v.cpu().numpy() for k, v in self.state(e).items()}
+
+    def set_state(self, e: int, st: Dict[str, "object"]):
+        arrs = {k: self.torch.as_tensor(st[k], dtype=self.torch.float64).to(self.dev).contiguous() for k in KEYS}
+        P = TfParticles(*[arrs[k].data_ptr() for k in KEYS])
+        self._sync_in()
+        _check(self.L.tf_set_state(self.h, e, ctypes.byref(P)))
+        self._keep = [arrs]
+        self.stream.synchronize()
+
+    def set_params(self, theta: np.ndarray):
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.n_ens, 3)
+        _check(self.L.tf_set_params(self.h, th.ctypes.data_as(POINTER(c_double))))
+
+    def poisson(self, e: int, q_fixed) -> "object":
+        E = self.ens[e].mesh
+        q = self.torch.as_tensor(q_fixed, dtype=self.torch.int64).to(self.dev).contiguous()
+        phi = self.torch.empty(E.nx * E.ny * E.nz, dtype=self.torch.float64, device=self.dev)
+        self._sync_in()
+        _check(self.L.tf_poisson(self.h, e, q.data_ptr(), phi.data_ptr()))
+        self._sync_out()
+        self.stream.synchronize()
+        return phi
+
+    def field(self, e: int, which: int) -> "object":
+        E = self.ens[e].mesh
+        dt = self.torch.float64 if which == TF_FIELD_PHI else self.torch.int64
+        out = self.torch.empty(E.nx * E.ny * E.nz, dtype=dt, device=self.dev)
+        self._sync_in()
+        _check(self.L.tf_field(self.h, e, which, out.data_ptr()))
+        self._sync_out()
+        self.stream.synchronize()
+        return out
+
+    def adjoint(self, lambdas: List[Dict[str, "object"]], w_wall: np.ndarray) -> np.ndarray:
+        """Reverse the recorded steps; lambdas (id order, device) are updated in place."""
+        P = (TfParticles * self.n_ens)()
+        keep = []
+        for e in range(self.n_ens):
+            lam = lambdas[e]
+            for k in KEYS:
+                if k == "d":
+                    setattr(P[e], k, 0)
+                    continue
+                tns = lam[k]
+                keep.append(tns)
+                setattr(P[e], k, tns.data_ptr())
+        ww = np.ascontiguousarray(w_wall, dtype=np.float64).reshape(self.n_ens, 2)
+        dth = np.zeros((self.n_ens, 3))
+        self._sync_in()
+        _check(self.L.tf_adjoint_step(self.h, P, ww.ctypes.data_as(POINTER(c_double)),
+                                      dth.ctypes.data_as(POINTER(c_double))))
+        self._sync_out()
+        return dth
+
+    def profile_begin(self, max_steps: int):
+        _check(self.L.tf_profile_begin(self.h, max_steps))
+
+    def profile_end(self):
+        ms = (c_double * TF_NPHASE)()
+        n = c_int32()
+        _check(self.L.tf_profile_end(self.h, ms, ctypes.byref(n)))
+        return dict(zip(PHASES, list(ms))), n.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            self.L.tf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,86 @@
+"""The C ABI: the library loads and exports every entry point of include/tribo.h,
+and rejects invalid configurations on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_10761_amd import runtime as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tribo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tf_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("tf_init", "tf_step", "tf_adjoint_step", "tf_stats", "tf_workspace_size", "tf_get_state",
+              "tf_set_state", "tf_set_params", "tf_poisson", "tf_field", "tf_destroy", "tf_error_string",
+              "tf_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = R.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def cfg(nx=32, ny=16, nz=32, n=100, **kw):
+    yf = np.linspace(0.0, 360.0, ny + 1)
+    c = R.TfEnsemble()
+    c.nx, c.ny, c.nz, c.n_particles = nx, ny, nz, n
+    c.lx, c.lz = 100.0, 50.0
+    c.y_faces = yf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.dt, c.density_ratio, c.k_c, c.delta_u, c.e, c.c_el = 0.1, 1000.0, 1e-3, 1.0, 0.9, 1.0
+    c.un_bin = 0.05
+    c.u_nodes = 4096
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c, yf
+
+
+def ws(c):
+    arr = (R.TfEnsemble * 1)(c)
+    return R.lib().tf_workspace_size(arr, 1, 0)
+
+
+def test_workspace_size_valid_and_monotone():
+    c, yf = cfg()
+    a = ws(c)
+    c2, yf2 = cfg(n=10000)
+    assert 0 < a < ws(c2)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=7), dict(nx=14), dict(nz=2), dict(nx=512), dict(ny=1),
+                                 dict(n_particles=-1), dict(dt=0.0), dict(e=0.0), dict(e=1.5),
+                                 dict(density_ratio=-1.0), dict(u_nodes=None), dict(un_bin=0.0)])
+def test_invalid_configs_rejected(bad):
+    c, yf = cfg(**bad)
+    assert ws(c) == 0
+
+
+def test_non_monotone_faces_rejected():
+    c, yf = cfg()
+    yf[3] = yf[2]
+    assert ws(c) == 0
+    c, yf = cfg()
+    yf[0] = 1.0
+    assert ws(c) == 0
+
+
+def test_init_rejects_without_touching_device():
+    L = R.lib()
+    c, yf = cfg(nx=9)
+    h = ctypes.c_void_p()
+    rc = L.tf_init((R.TfEnsemble * 1)(c), 1, (R.TfParticles * 1)(), ctypes.c_void_p(256), 1 << 20, 0, None, 0,
+                   ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert b"nx" in L.tf_last_error()
+    assert L.tf_error_string(-2) == b"size limit or workspace too small"

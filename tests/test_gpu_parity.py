@@ -1,0 +1,231 @@
+"""GPU parity of the HIP particle step against the CPU oracle (through the C ABI).
+
+Bars: deposit, impact counts and all integer statistics bit-exact; particle
+state within 1e-12 normwise relative per step from the same input state;
+potential within 1e-12 relative to its maximum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import KEYS, oracle_run, state_errors
+from paper_2602_10761_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def sim_of(ens_list, **kw):
+    from paper_2602_10761_amd.runtime import TriboSim
+    return TriboSim(ens_list if isinstance(ens_list, list) else [ens_list], **kw)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ens_small(nx=32, ny=32, nz=32, n=4000, seed=0, **kw):
+    spec = W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=n, **kw)
+    return W.make_ensemble(spec, 1, seed)
+
+
+def assert_stats_equal(gs, os_):
+    assert gs["steps"] == os_.steps
+    assert gs["flags"] == os_.flags
+    np.testing.assert_array_equal(gs["impacts"], os_.impacts)
+    np.testing.assert_array_equal(gs["wallq"], os_.wallq)
+    np.testing.assert_array_equal(gs["unhist"], os_.unhist)
+    np.testing.assert_array_equal(gs["crel_y"], os_.crel_y)
+    np.testing.assert_array_equal(gs["qcum_y"], os_.qcum_y)
+    np.testing.assert_array_equal(gs["qnow_y"], os_.qnow_y)
+
+
+# ---------------------------------------------------------------------------
+# Poisson stage in isolation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,stretch", [((8, 6, 12), 1.5), ((24, 20, 40), 2.0), ((32, 32, 32), 2.0),
+                                           ((64, 64, 64), 2.0), ((96, 64, 96), 2.0), ((128, 128, 128), 2.0),
+                                           ((160, 160, 160), 2.0), ((192, 160, 192), 2.0), ((256, 8, 256), 1.0),
+                                           ((4, 2, 4), 0.0)])
+def test_poisson_parity(shape, stretch):
+    nx, ny, nz = shape
+    say("poisson", shape)
+    ens = W.make_ensemble(W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=10, stretch=stretch, n_modes=4))
+    g = O.Geo.from_mesh(ens.mesh)
+    rng = np.random.default_rng(nx * 7 + ny)
+    Q = np.zeros(g.ncell, dtype=np.int64)
+    idx = rng.integers(0, g.ncell, max(4, g.ncell // 50))
+    Q[idx] = rng.integers(-(1 << 50), 1 << 50, idx.size)
+    sim = sim_of(ens)
+    phi = sim.poisson(0, Q).cpu().numpy().reshape(ny, nz, nx)
+    ref = O.poisson(g, Q)
+    err = np.abs(phi - ref).max() / np.abs(ref).max()
+    say("  rel err", err)
+    assert err < TOL
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# one step from the same initial state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["plain", "charged", "dense", "gravity"])
+def test_one_step_parity(case):
+    say("one step", case)
+    kw = dict(plain=dict(v_jitter=3.0, density_ratio=50.0),
+              charged=dict(v_jitter=3.0, precharge=0.5, density_ratio=50.0, c_el=30.0),
+              dense=dict(nx=8, ny=8, nz=8, n=20000, precharge=0.3, c_el=5.0, v_jitter=2.0),
+              gravity=dict(g=(0.0, -0.02, 0.01), precharge=0.1, v_jitter=1.0))[case]
+    ens = ens_small(**kw)
+    sim = sim_of(ens, keep_deposit=True)
+    sim.step(1)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    Qg = sim.field(0, 1).cpu().numpy()
+    phig = sim.field(0, 0).cpu().numpy()
+    g = O.Geo.from_mesh(ens.mesh)
+    st = O.Stats(g.ny)
+    want = {}
+    ref = O.step(g, ens.U, O.state_of(ens), ens.params, st, want=want)
+    np.testing.assert_array_equal(Qg, want["Q"])
+    perr = np.abs(phig - want["phi"].ravel()).max() / max(np.abs(want["phi"]).max(), 1e-300)
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  phi err", perr, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert perr < TOL
+    assert max(err.values()) < TOL
+    assert_stats_equal(gst, st)
+    sim.close()
+
+
+def test_multi_step_parity():
+    say("multi step")
+    # shallow channel (h = 20) so that many particles reach the walls within the window
+    ens = ens_small(n=6000, v_jitter=4.0, precharge=0.2, density_ratio=30.0, re_tau=20.0, c_el=5.0)
+    ens.params["k_c"] = 0.02
+    n = 40
+    sim = sim_of(ens)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    ref, st = oracle_run(ens, n)
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  impacts", st.impacts, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert st.impacts.sum() > 50
+    assert_stats_equal(gst, st)
+    assert max(err.values()) < 1e-10
+    sim.close()
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_one_step(cfg):
+    """The benchmark workloads at full size: one step, every particle compared."""
+    say("full size config", cfg)
+    ens = W.make_workload(cfg, precharge=0.05)[0]
+    sim = sim_of(ens)
+    sim.step(1)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    phig = sim.field(0, 0).cpu().numpy()
+    sim.close()
+    g = O.Geo.from_mesh(ens.mesh)
+    st = O.Stats(g.ny)
+    want = {}
+    ref = O.step(g, ens.U, O.state_of(ens), ens.params, st, want=want)
+    perr = np.abs(phig - want["phi"].ravel()).max() / np.abs(want["phi"]).max()
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  phi err", perr, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert perr < TOL
+    assert max(err.values()) < TOL
+    assert_stats_equal(gst, st)
+
+
+# ---------------------------------------------------------------------------
+# determinism, graphs, batching, checkpoint/resume, edge cases
+# ---------------------------------------------------------------------------
+def test_run_twice_bitwise():
+    ens = ens_small(n=5000, v_jitter=3.0, precharge=0.3, c_el=20.0)
+    outs = []
+    for _ in range(2):
+        sim = sim_of(ens)
+        sim.step(15)
+        outs.append((sim.state_np(0), sim.stats(0)))
+        sim.close()
+    for k in KEYS:
+        np.testing.assert_array_equal(outs[0][0][k], outs[1][0][k])
+    for k in ("impacts", "wallq", "crel_y", "qcum_y", "qnow_y", "unhist"):
+        np.testing.assert_array_equal(outs[0][1][k], outs[1][1][k])
+
+
+def test_graphs_equal_eager():
+    ens = ens_small(n=3000, v_jitter=3.0, precharge=0.3)
+    res = []
+    for graphs in (False, True):
+        sim = sim_of(ens, graphs=graphs)
+        sim.step(7)
+        sim.step(4)
+        res.append((sim.state_np(0), sim.stats(0)))
+        sim.close()
+    for k in KEYS:
+        np.testing.assert_array_equal(res[0][0][k], res[1][0][k])
+    np.testing.assert_array_equal(res[0][1]["crel_y"], res[1][1]["crel_y"])
+    assert res[1][1]["steps"] == 11
+
+
+def test_batched_equals_plain():
+    specs = [W.CONFIGS[1].replace(nx=16, ny=24, nz=32, n_particles=2500, v_jitter=3.0, precharge=0.2),
+             W.CONFIGS[1].replace(re_tau=300.0, nx=48, ny=40, nz=20, n_particles=7000, v_jitter=2.0, d_choices=(1.0,)),
+             W.CONFIGS[1].replace(nx=8, ny=8, nz=8, n_particles=0),
+             W.CONFIGS[1].replace(re_tau=550.0, nx=40, ny=16, nz=12, n_particles=1, v_jitter=1.0)]
+    ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
+    sim = sim_of(ens, graphs=True)
+    sim.step(9)
+    batched = [(sim.state_np(e), sim.stats(e)) for e in range(len(ens))]
+    sim.close()
+    for e, E in enumerate(ens):
+        s1 = sim_of(E)
+        s1.step(9)
+        st, ss = s1.state_np(0), s1.stats(0)
+        s1.close()
+        for k in KEYS:
+            np.testing.assert_array_equal(batched[e][0][k], st[k])
+        for k in ("impacts", "wallq", "crel_y", "qcum_y", "qnow_y", "unhist"):
+            np.testing.assert_array_equal(batched[e][1][k], ss[k])
+
+
+def test_resume_equals_continuous():
+    ens = ens_small(n=4000, v_jitter=3.0, precharge=0.3, c_el=10.0)
+    a = sim_of(ens)
+    a.step(12)
+    ref = a.state_np(0)
+    a.close()
+    b = sim_of(ens)
+    b.step(5)
+    mid = b.state(0)
+    b.close()
+    c = sim_of(ens)
+    c.set_state(0, mid)
+    c.step(7)
+    out = c.state_np(0)
+    c.close()
+    for k in KEYS:
+        np.testing.assert_array_equal(out[k], ref[k])
+
+
+def test_conservation_and_flags():
+    ens = ens_small(n=5000, v_jitter=4.0, precharge=0.2, density_ratio=30.0, re_tau=20.0, c_el=5.0)
+    ens.params["k_c"] = 0.05
+    sim = sim_of(ens)
+    q0 = ens.q.sum()
+    sim.step(60)
+    s = sim.state_np(0)
+    st = sim.stats(0)
+    sim.close()
+    assert st["impacts"].sum() > 100
+    assert st["flags"] == 0
+    wall = st["wallq"].sum() * 2.0 ** -40
+    assert abs(s["q"].sum() - q0 + wall) < 1e-9
+    r = 0.5 * s["d"]
+    assert np.all((s["y"] >= r) & (s["y"] <= ens.mesh.ly - r))
