@@ -200,6 +200,20 @@ int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
 int tf_profile_begin(tf_handle* h, int32_t max_steps);
 int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_steps);
 
+/*
+ * Tile shapes of the Poisson kernels, used by every later tf_init /
+ * tf_workspace_size of the calling process (0 = built-in choice):
+ *   fx_rows    (j, k) rows per block of the x transforms (1..256)
+ *   fz_cols    spectral columns per block of the z transforms (1..64)
+ *   tri_modes  Fourier modes per block of the tridiagonal solves (1..64)
+ * Values whose LDS need exceeds 64 KiB per block are rejected at tf_init.
+ * Results do not depend on the tiles (bitwise).
+ */
+typedef struct {
+  int32_t fx_rows, fz_cols, tri_modes, reserved;
+} tf_tuning;
+int tf_set_tuning(const tf_tuning* t);
+
 void tf_destroy(tf_handle* h);
 const char* tf_error_string(int code);
 const char* tf_last_error(void);

@@ -17,6 +17,7 @@ using namespace tf;
 namespace {
 
 thread_local std::string g_err;
+tf_tuning g_tune = {0, 0, 0, 0};
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -50,7 +51,7 @@ bool radix_plan(int n, FftPlan* P) {
 struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
-  int nx_max = 0, nz_max = 0, rpb = 1, wz = 8;
+  int nx_max = 0, nz_max = 0, ny_max = 0, rpb = 1, wz = 8, tri_m = 16, tri_pcr = 1;
   std::vector<int> fx_blk, fz_blk, tri_blk;
   std::map<int, int> tw_off;
 };
@@ -92,6 +93,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->st_tot += stats_len(E.ny);
     S->nx_max = std::max(S->nx_max, E.nx);
     S->nz_max = std::max(S->nz_max, E.nz);
+    S->ny_max = std::max(S->ny_max, E.ny);
     for (int n : {E.nx, E.nz})
       if (!S->tw_off.count(n)) {
         S->tw_off[n] = S->tw_tot;
@@ -99,14 +101,26 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       }
   }
   if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
-  S->rpb = std::max(1, 512 / S->nx_max);
-  S->wz = std::max(1, std::min(8, (60 * 1024 / 16 - S->nz_max) / (2 * S->nz_max)));
+  S->rpb = 1;  // x transforms: one wave per (j, k) row
+  S->wz = g_tune.fz_cols > 0 ? g_tune.fz_cols : 2;
+  // tridiagonal: cyclic reduction holds tri_m * ny equations (5 doubles each,
+  // at most 8 per thread); Thomas (ny > 256) holds tri_m columns (32 B per row)
+  S->tri_pcr = S->ny_max <= 256 ? 1 : 0;
+  if (S->tri_pcr)
+    S->tri_m = g_tune.tri_modes > 0 ? g_tune.tri_modes : std::max(1, 1024 / S->ny_max);
+  else
+    S->tri_m = g_tune.tri_modes > 0 ? g_tune.tri_modes : std::max(1, std::min(16, 65536 / (32 * S->ny_max)));
+  const size_t lds_fx = (size_t)3 * S->nx_max * 16;
+  const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
+  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * S->ny_max * S->tri_m : (size_t)S->ny_max * S->tri_m * 32;
+  if (lds_fx > 65536 || lds_fz > 65536 || lds_tri > 65536) return fail(TF_ESIZE, "tile shapes exceed 64 KiB of LDS");
+  if (S->tri_pcr && S->tri_m * S->ny_max > 8 * kBlock) return fail(TF_ESIZE, "tri_modes * ny exceeds 2048");
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
     S->fx_blk[e + 1] = S->fx_blk[e] + (rows + S->rpb - 1) / S->rpb;
     S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->wz - 1) / S->wz);
-    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + kBlock - 1) / kBlock;
+    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + S->tri_m - 1) / S->tri_m;
   }
   return TF_OK;
 }
@@ -232,7 +246,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, int* 
   if ((e = launch_scan(h->C, h->stream)) != hipSuccess) return e;
   if ((e = launch_sort(h->C, in, h->stream)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
-  if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, nullptr, 0, h->C.phi, 0, 1, h->stream,
+  if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
                           ev ? ev + 2 : nullptr)) != hipSuccess)
     return e;
   if (phi_rec && (e = hipMemcpyAsync(phi_rec, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
@@ -274,6 +288,18 @@ const char* tf_error_string(int code) {
 }
 
 const char* tf_last_error(void) { return g_err.c_str(); }
+
+int tf_set_tuning(const tf_tuning* t) {
+  if (!t) {
+    g_tune = tf_tuning{0, 0, 0, 0};
+    return TF_OK;
+  }
+  if (t->fx_rows < 0 || t->fx_rows > 256 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
+      t->tri_modes > 64)
+    return fail(TF_EINVAL, "tuning value out of range");
+  g_tune = *t;
+  return TF_OK;
+}
 
 size_t tf_workspace_size(const tf_ensemble* ens, int32_t n_ens, int32_t traj_steps) {
   Sizes S;
@@ -432,6 +458,9 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.nx_max = S.nx_max;
   h->G.nz_max = S.nz_max;
   h->G.wz = S.wz;
+  h->G.ny_max = S.ny_max;
+  h->G.tri_m = S.tri_m;
+  h->G.tri_pcr = S.tri_pcr;
   h->G.fx_blk = h->S.fx_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
   h->G.tri_blk = h->S.tri_blk.data();
@@ -450,7 +479,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   if (h->C.n_tot == 0) {
     for (int s = 0; s < n_steps; ++s) {
       HIPCHK(launch_scan(h->C, h->stream));
-      HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, nullptr, 0, h->C.phi, 0, 1, h->stream));
+      HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, h->cur.key, nullptr, 0, h->C.phi, 0, 1, h->stream));
       HIPCHK(launch_push(h->C, h->cur, other(h), nullptr, h->stream));
     }
     return TF_OK;
@@ -605,7 +634,7 @@ int tf_set_params(tf_handle* h, const double* theta) {
 int tf_poisson(tf_handle* h, int32_t e, const int64_t* q_fixed, double* phi) {
   if (!h || !q_fixed || !phi) return fail(TF_EINVAL, "NULL argument");
   if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
-  HIPCHK(launch_poisson(h->C, h->G, e, e + 1, nullptr, (const long long*)q_fixed, h->c_off[e], phi, h->c_off[e], 0,
+  HIPCHK(launch_poisson(h->C, h->G, e, e + 1, nullptr, nullptr, (const long long*)q_fixed, h->c_off[e], phi, h->c_off[e], 0,
                         h->stream));
   return TF_OK;
 }

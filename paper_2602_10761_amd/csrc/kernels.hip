@@ -59,8 +59,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block of 1024 threads: exclusive scan of the block partials, total at part[nb]
-__global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int nb) {
+// single block of 1024 threads: exclusive scan of the block partials, total at
+// part[nb]; also counts the step of every ensemble (runs once per step)
+__global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int nb, Ctx C) {
+  for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
   int carry = 0;
   for (int base = 0; base < nb; base += 1024) {
     int i = base + threadIdx.x;
@@ -176,14 +178,14 @@ __device__ __forceinline__ void butterfly(double2* v) {
 
 template <int R, bool INV>
 __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2* __restrict__ b, int rows,
-                                         int n, int Ns, const double2* __restrict__ tw) {
+                                         int n, int pitch, int Ns, const double2* __restrict__ tw) {
   const int nb = n / R;
   const int stride = n / (Ns * R);
   const int total = rows * nb;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int row = t / nb, jj = t - row * nb;
-    const double2* s = a + row * n;
-    double2* d = b + row * n;
+    const double2* s = a + row * pitch;
+    double2* d = b + row * pitch;
     const int k = jj % Ns;
     double2 v[R];
 #pragma unroll
@@ -201,19 +203,20 @@ __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2*
   }
 }
 
-// Transforms `rows` lines of length P.n held in a (scratch b); returns the
-// buffer holding the result.  Caller must __syncthreads() before the call.
+// Transforms `rows` lines of length P.n (row pitch `pitch`) held in a, with
+// scratch b; returns the buffer holding the result.  Caller must
+// __syncthreads() before the call.
 template <bool INV>
-__device__ double2* lds_fft(double2* a, double2* b, int rows, const FftPlan& P, const double2* tw) {
+__device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const FftPlan& P, const double2* tw) {
   const int n = P.n;
   int Ns = 1;
   for (int ps = 0; ps < P.npass; ++ps) {
     const int R = (int)((P.rcode >> (3 * ps)) & 7u);
     switch (R) {
-      case 2: fft_pass<2, INV>(a, b, rows, n, Ns, tw); break;
-      case 3: fft_pass<3, INV>(a, b, rows, n, Ns, tw); break;
-      case 4: fft_pass<4, INV>(a, b, rows, n, Ns, tw); break;
-      default: fft_pass<5, INV>(a, b, rows, n, Ns, tw); break;
+      case 2: fft_pass<2, INV>(a, b, rows, n, pitch, Ns, tw); break;
+      case 3: fft_pass<3, INV>(a, b, rows, n, pitch, Ns, tw); break;
+      case 4: fft_pass<4, INV>(a, b, rows, n, pitch, Ns, tw); break;
+      default: fft_pass<5, INV>(a, b, rows, n, pitch, Ns, tw); break;
     }
     __syncthreads();
     double2* t = a;
@@ -225,98 +228,93 @@ __device__ double2* lds_fft(double2* a, double2* b, int rows, const FftPlan& P, 
 }
 
 // ---------------------------------------------------------------------------
-// deposit + forward FFT along x, one block = rpb rows (j, k) of one ensemble
+// wave-wide integer sum
 // ---------------------------------------------------------------------------
-// q source: particles (q_in == nullptr) or a per-cell fixed-point array
-__global__ __launch_bounds__(kBlock) void k_dep_fftx(Ctx C, const double* __restrict__ q,
-                                                     const int* __restrict__ blk_off, int blk0, int rpb,
-                                                     int nmax, const long long* __restrict__ q_in,
-                                                     long long q_shift, int do_stats) {
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// deposit + forward FFT along x: one wave per (j, k) row, no cross-wave sync.
+// Lane l owns cells i = l, l + 64, ... of the row; a cell's particles are the
+// contiguous sorted slots [start[c], start[c+1]); their fixed-point charges
+// are summed in integers (exact, order-free).  q source: particles
+// (q_in == nullptr) or a per-cell fixed-point array.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict__ q,
+                                                 const int* __restrict__ blk_off, int blk0, int nmax,
+                                                 const long long* __restrict__ q_in, long long q_shift,
+                                                 int do_stats) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
-  double2* buf1 = lds + rpb * nmax;
-  double2* tw = lds + 2 * rpb * nmax;
-  unsigned long long* racc = (unsigned long long*)(tw + nmax);  // [rpb][3]
-
+  double2* buf1 = lds + nmax;
+  double2* tw = lds + 2 * nmax;
   const int gb = blk0 + blockIdx.x;
   const int e = find_off_i(blk_off, C.n_ens + 1, gb);
   const Ens& E = C.ens[e];
   const int nx = E.nx, nz = E.nz;
-  const int nrow_e = E.ny * nz;
-  const int r0 = (gb - blk_off[e]) * rpb;
-  const int nrows = min(rpb, nrow_e - r0);
+  const int jk = gb - blk_off[e];
+  const int j = jk / nz;
+  const long long c0 = E.c_off + (long long)jk * nx;
+  const double vol = C.vol[E.y_off + j];
 
-  for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = C.tw[E.fx.tw_off + t];
-  for (int t = threadIdx.x; t < 3 * rpb; t += blockDim.x) racc[t] = 0ull;
-  __syncthreads();
-
+  for (int t = threadIdx.x; t < nx; t += 64) tw[t] = C.tw[E.fx.tw_off + t];
   bool ovf = false;
-  const int ncell = nrows * nx;
-  for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
-    const int row = t / nx, i = t - row * nx;
-    const int jk = r0 + row;
-    const long long cg = E.c_off + (long long)jk * nx + i;
-    long long Q = 0, Q32 = 0;
-    int cnt = 0;
+  long long rq48 = 0, rq32 = 0;
+  for (int i = threadIdx.x; i < nx; i += 64) {
+    long long Q = 0;
     if (q_in) {
-      Q = q_in[cg - q_shift];
+      Q = q_in[c0 + i - q_shift];
     } else {
-      const int a = C.start[cg], b = C.start[cg + 1];
-      cnt = b - a;
+      const int a = C.start[c0 + i], b = C.start[c0 + i + 1];
+      long long Q32 = 0;
       for (int s = a; s < b; ++s) {
         const double qv = q[C.perm[s]];
         Q += fixed_round(qv, kFixDep, &ovf);
         Q32 += fixed_round(qv, kFixQcum, &ovf);
       }
-      if (C.qdep) C.qdep[cg] = Q;
+      if (C.qdep) C.qdep[c0 + i] = Q;
+      rq32 += Q32;
     }
-    const int j = jk / nz;
-    const double rho = ((double)Q * (1.0 / 281474976710656.0)) / C.vol[E.y_off + j];
-    buf0[row * nx + i] = make_double2(rho, 0.0);
-    if (do_stats) {
-      if (cnt) atomicAdd(&racc[3 * row + 0], (unsigned long long)cnt);
-      if (Q32) atomicAdd(&racc[3 * row + 1], (unsigned long long)Q32);
-      if (Q) atomicAdd(&racc[3 * row + 2], (unsigned long long)Q);
+    rq48 += Q;
+    buf0[i] = make_double2(((double)Q * (1.0 / 281474976710656.0)) / vol, 0.0);
+  }
+  if (do_stats) {
+    const int cnt = C.start[c0 + nx] - C.start[c0];
+    rq48 = wave_sum(rq48);
+    rq32 = wave_sum(rq32);
+    if (threadIdx.x == 0) {
+      long long* st = C.stats + E.st_off;
+      atomicAdd((unsigned long long*)&st[ST_Y + j], (unsigned long long)cnt);
+      atomicAdd((unsigned long long*)&st[ST_Y + E.ny + j], (unsigned long long)rq32);
+      C.rowq[E.row_off + jk] = rq48;
     }
   }
   if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
   __syncthreads();
-
   FftPlan P = E.fx;
-  double2* a = buf0;
-  double2* b = buf1;
-  double2* res = lds_fft<false>(a, b, nrows, P, tw);
-
-  const int nh = E.nh, nhp = E.nhp;
-  for (int t = threadIdx.x; t < nrows * nh; t += blockDim.x) {
-    const int row = t / nh, m = t - row * nh;
-    C.spec[E.s_off + (long long)(r0 + row) * nhp + m] = res[row * nx + m];
-  }
-  if (do_stats && threadIdx.x < nrows) {
-    const int row = threadIdx.x;
-    const int jk = r0 + row;
-    const int j = jk / nz;
-    long long* st = C.stats + E.st_off;
-    atomicAdd((unsigned long long*)&st[ST_Y + j], racc[3 * row + 0]);
-    atomicAdd((unsigned long long*)&st[ST_Y + E.ny + j], racc[3 * row + 1]);
-    C.rowq[E.row_off + jk] = (long long)racc[3 * row + 2];
-  }
+  double2* res = lds_fft<false>(buf0, buf1, 1, nx, P, tw);
+  double2* out = C.spec + E.s_off + (long long)jk * E.nhp;
+  for (int m = threadIdx.x; m < E.nh; m += 64) out[m] = res[m];
 }
 
 // ---------------------------------------------------------------------------
 // FFT along z on the half spectrum: block = (ensemble, y plane, wz columns)
 // ---------------------------------------------------------------------------
 template <bool INV>
-__global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, const int* __restrict__ blk_off, int blk0, int wz,
-                                                 int nmax) {
+__global__ __launch_bounds__(64) void k_fftz(Ctx C, const int* __restrict__ blk_off, int blk0, int wz,
+                                             int nmax) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
-  double2* buf1 = lds + wz * nmax;
-  double2* tw = lds + 2 * wz * nmax;
+  double2* buf1 = lds + wz * (nmax + 1);
+  double2* tw = lds + 2 * wz * (nmax + 1);
   const int gb = blk0 + blockIdx.x;
   const int e = find_off_i(blk_off, C.n_ens + 1, gb);
   const Ens& E = C.ens[e];
   const int nz = E.nz, nh = E.nh, nhp = E.nhp;
+  const int pitch = nz + 1;  // odd pitch (in 16-byte units): no bank conflicts in the transposes
   const int nchunk = (nh + wz - 1) / wz;
   const int lb = gb - blk_off[e];
   const int j = lb / nchunk;
@@ -326,100 +324,221 @@ __global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, const int* __restrict__ 
   double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
   for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
     const int c = t % w, k = t / w;
-    buf0[c * nz + k] = sp[(long long)k * nhp + c];
+    buf0[c * pitch + k] = sp[(long long)k * nhp + c];
   }
   __syncthreads();
   FftPlan P = E.fz;
-  double2* res = lds_fft<INV>(buf0, buf1, w, P, tw);
+  double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw);
   const double sc = INV ? 1.0 / (double)nz : 1.0;
   for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
     const int c = t % w, k = t / w;
-    double2 v = res[c * nz + k];
+    double2 v = res[c * pitch + k];
     if (INV) v = make_double2(v.x * sc, v.y * sc);
     sp[(long long)k * nhp + c] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal solve in y, one thread per Fourier mode (mz, mx)
+// tridiagonal solve in y for a tile of `tm` Fourier modes (mz, mx):
 //   -am_j phi_{j-1} + (am_j + ap_j + k^2) phi_j - ap_j phi_{j+1} = rho_j
-// (FV Laplacian times -1, phi = 0 on both walls)
+// (FV Laplacian times -1, phi = 0 on both walls).  The tile's columns are
+// staged in LDS with coalesced loads; one thread per (mode, re/im) runs the
+// Thomas sweeps in LDS; coalesced stores.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_tri(Ctx C, const int* __restrict__ blk_off, int blk0) {
+__global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, const int* __restrict__ blk_off, int blk0, int tm) {
+  extern __shared__ double2 lds[];
   const int gb = blk0 + blockIdx.x;
   const int e = find_off_i(blk_off, C.n_ens + 1, gb);
   const Ens& E = C.ens[e];
-  const int mode = (gb - blk_off[e]) * kBlock + threadIdx.x;
   const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
-  if (mode >= nh * nz) return;
-  const int mz = mode / nh, m = mode - mz * nh;
-  const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
-  const double* am = C.am + E.y_off;
-  const double* ap = C.ap + E.y_off;
+  const int nm = nh * nz;
+  const int mode0 = (gb - blk_off[e]) * tm;
+  const int w = min(tm, nm - mode0);
+  double2* col = lds;                          // [ny][tm]
+  double* cps = (double*)(lds + ny * tm);      // [ny][2*tm]
+  const double2* sp = C.spec + E.s_off;
   const long long pitch = (long long)nz * nhp;
-  double2* sp = C.spec + E.s_off + (long long)mz * nhp + m;
-  double* cp = C.cp + E.s_off + (long long)mz * nhp + m;
-  // forward elimination
-  double diag = (am[0] + ap[0]) + K2;
-  double cpv = (-ap[0]) / diag;
-  double2 r = sp[0];
-  double2 dp = make_double2(r.x / diag, r.y / diag);
-  cp[0] = cpv;
-  sp[0] = dp;
-  for (int j = 1; j < ny; ++j) {
-    const double lo = -am[j];
-    const double dg = (am[j] + ap[j]) + K2;
-    const double piv = dg - lo * cpv;
-    cpv = (-ap[j]) / piv;
-    r = sp[j * pitch];
-    dp = make_double2((r.x - lo * dp.x) / piv, (r.y - lo * dp.y) / piv);
-    cp[j * pitch] = cpv;
-    sp[j * pitch] = dp;
+  for (int t = threadIdx.x; t < ny * w; t += blockDim.x) {
+    const int j = t / w, c = t - j * w;
+    const int mode = mode0 + c;
+    const int mz = mode / nh, m = mode - mz * nh;
+    col[j * tm + c] = sp[j * pitch + (long long)mz * nhp + m];
   }
-  // back substitution
-  double2 xv = dp;
-  for (int j = ny - 2; j >= 0; --j) {
-    const double c = cp[j * pitch];
-    const double2 d = sp[j * pitch];
-    xv = make_double2(d.x - c * xv.x, d.y - c * xv.y);
-    sp[j * pitch] = xv;
+  __syncthreads();
+  if (threadIdx.x < 2 * tm) {
+    const int c = threadIdx.x % tm, comp = threadIdx.x / tm;
+    if (c < w) {
+      const int mode = mode0 + c;
+      const int mz = mode / nh, m = mode - mz * nh;
+      const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
+      const double* __restrict__ am = C.am + E.y_off;
+      const double* __restrict__ ap = C.ap + E.y_off;
+      double* v = (double*)col + 2 * c + comp;   // element j at v[j * 2 * tm]
+      double* cp = cps + threadIdx.x;            // element j at cp[j * 2 * tm]
+      const int vs = 2 * tm;
+      double diag = (am[0] + ap[0]) + K2;
+      double cpv = (-ap[0]) / diag;
+      double dp = v[0] / diag;
+      v[0] = dp;
+      cp[0] = cpv;
+      for (int j = 1; j < ny; ++j) {
+        const double lo = -am[j];
+        const double dg = (am[j] + ap[j]) + K2;
+        const double piv = dg - lo * cpv;
+        cpv = (-ap[j]) / piv;
+        dp = (v[j * vs] - lo * dp) / piv;
+        v[j * vs] = dp;
+        cp[j * vs] = cpv;
+      }
+      double x = dp;
+      for (int j = ny - 2; j >= 0; --j) {
+        x = v[j * vs] - cp[j * vs] * x;
+        v[j * vs] = x;
+      }
+    }
+  }
+  __syncthreads();
+  double2* spo = C.spec + E.s_off;
+  for (int t = threadIdx.x; t < ny * w; t += blockDim.x) {
+    const int j = t / w, c = t - j * w;
+    const int mode = mode0 + c;
+    const int mz = mode / nh, m = mode - mz * nh;
+    spo[j * pitch + (long long)mz * nhp + m] = col[j * tm + c];
   }
 }
 
 // ---------------------------------------------------------------------------
-// inverse FFT along x (Hermitian half spectrum -> real), phi on the cells
+// tridiagonal solve in y by parallel cyclic reduction (ny <= kPcrEq*256/tm):
+// every equation of a tile of tm modes lives in LDS; each of ceil(log2 ny)
+// steps eliminates the couplings at distance delta from all equations at
+// once.  Same system as the Thomas variant; different rounding order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_ifftx(Ctx C, const int* __restrict__ blk_off, int blk0, int rpb,
-                                                  int nmax, double* __restrict__ phi_out, long long phi_shift) {
-  extern __shared__ double2 lds[];
-  double2* buf0 = lds;
-  double2* buf1 = lds + rpb * nmax;
-  double2* tw = lds + 2 * rpb * nmax;
+constexpr int kPcrEq = 8;  // equations per thread
+
+__global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict__ blk_off, int blk0, int tm) {
+  extern __shared__ double ldsd[];
   const int gb = blk0 + blockIdx.x;
   const int e = find_off_i(blk_off, C.n_ens + 1, gb);
   const Ens& E = C.ens[e];
-  const int nx = E.nx, nh = E.nh, nhp = E.nhp;
-  const int r0 = (gb - blk_off[e]) * rpb;
-  const int nrows = min(rpb, E.ny * E.nz - r0);
-  for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = C.tw[E.fx.tw_off + t];
-  for (int t = threadIdx.x; t < nrows * nx; t += blockDim.x) {
-    const int row = t / nx, i = t - row * nx;
-    const double2* sp = C.spec + E.s_off + (long long)(r0 + row) * nhp;
+  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  const int nm = nh * nz;
+  const int mode0 = (gb - blk_off[e]) * tm;
+  const int w = min(tm, nm - mode0);
+  const int neq = w * ny;
+  const int cap = tm * ny;
+  double* A = ldsd;
+  double* B = A + cap;
+  double* Cc = B + cap;
+  double* Dr = Cc + cap;
+  double* Di = Dr + cap;
+  const double* __restrict__ am = C.am + E.y_off;
+  const double* __restrict__ ap = C.ap + E.y_off;
+  const long long pitch = (long long)nz * nhp;
+  double2* sp = C.spec + E.s_off;
+  // coalesced load: consecutive threads take consecutive modes of one y row;
+  // equation index q = c*ny + j (each mode's equations contiguous)
+  for (int t = threadIdx.x; t < neq; t += blockDim.x) {
+    const int j = t / w, c = t - j * w;
+    const int mode = mode0 + c;
+    const int mz = mode / nh, m = mode - mz * nh;
+    const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
+    const int qi = c * ny + j;
+    const double2 r = sp[j * pitch + (long long)mz * nhp + m];
+    A[qi] = (j > 0) ? -am[j] : 0.0;
+    Cc[qi] = (j < ny - 1) ? -ap[j] : 0.0;
+    B[qi] = (am[j] + ap[j]) + K2;
+    Dr[qi] = r.x;
+    Di[qi] = r.y;
+  }
+  __syncthreads();
+  double ra[kPcrEq], rb[kPcrEq], rc[kPcrEq], rdr[kPcrEq], rdi[kPcrEq];
+  for (int delta = 1; delta < ny; delta <<= 1) {
+#pragma unroll
+    for (int u = 0; u < kPcrEq; ++u) {
+      const int qi = threadIdx.x + u * kBlock;
+      if (qi < neq) {
+        const int j = qi % ny;
+        const double a = A[qi], b = B[qi], c = Cc[qi];
+        double na = 0.0, nc = 0.0, nb = b, ndr = Dr[qi], ndi = Di[qi];
+        if (j >= delta) {
+          const int qm = qi - delta;
+          const double al = -a / B[qm];
+          na = al * A[qm];
+          nb = nb + al * Cc[qm];
+          ndr = ndr + al * Dr[qm];
+          ndi = ndi + al * Di[qm];
+        }
+        if (j + delta < ny) {
+          const int qp = qi + delta;
+          const double ga = -c / B[qp];
+          nc = ga * Cc[qp];
+          nb = nb + ga * A[qp];
+          ndr = ndr + ga * Dr[qp];
+          ndi = ndi + ga * Di[qp];
+        }
+        ra[u] = na;
+        rb[u] = nb;
+        rc[u] = nc;
+        rdr[u] = ndr;
+        rdi[u] = ndi;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPcrEq; ++u) {
+      const int qi = threadIdx.x + u * kBlock;
+      if (qi < neq) {
+        A[qi] = ra[u];
+        B[qi] = rb[u];
+        Cc[qi] = rc[u];
+        Dr[qi] = rdr[u];
+        Di[qi] = rdi[u];
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < neq; t += blockDim.x) {
+    const int j = t / w, c = t - j * w;
+    const int mode = mode0 + c;
+    const int mz = mode / nh, m = mode - mz * nh;
+    const int qi = c * ny + j;
+    const double b = B[qi];
+    sp[j * pitch + (long long)mz * nhp + m] = make_double2(Dr[qi] / b, Di[qi] / b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse FFT along x (Hermitian half spectrum -> real): one wave per row
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_ifftx(Ctx C, const int* __restrict__ blk_off, int blk0, int nmax,
+                                              double* __restrict__ phi_out, long long phi_shift) {
+  extern __shared__ double2 lds[];
+  double2* buf0 = lds;
+  double2* buf1 = lds + nmax;
+  double2* tw = lds + 2 * nmax;
+  const int gb = blk0 + blockIdx.x;
+  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+  const Ens& E = C.ens[e];
+  const int nx = E.nx, nh = E.nh;
+  const int jk = gb - blk_off[e];
+  const double2* sp = C.spec + E.s_off + (long long)jk * E.nhp;
+  for (int t = threadIdx.x; t < nx; t += 64) {
+    tw[t] = C.tw[E.fx.tw_off + t];
     double2 v;
-    if (i < nh) {
-      v = sp[i];
+    if (t < nh) {
+      v = sp[t];
     } else {
-      v = sp[nx - i];
+      v = sp[nx - t];
       v.y = -v.y;
     }
-    buf0[row * nx + i] = v;
+    buf0[t] = v;
   }
   __syncthreads();
   FftPlan P = E.fx;
-  double2* res = lds_fft<true>(buf0, buf1, nrows, P, tw);
+  double2* res = lds_fft<true>(buf0, buf1, 1, nx, P, tw);
   const double sc = 1.0 / (double)nx;
-  double* out = phi_out + (E.c_off - phi_shift) + (long long)r0 * nx;
-  for (int t = threadIdx.x; t < nrows * nx; t += blockDim.x) out[t] = res[t].x * sc;
+  double* out = phi_out + (E.c_off - phi_shift) + (long long)jk * nx;
+  for (int t = threadIdx.x; t < nx; t += 64) out[t] = res[t].x * sc;
 }
 
 // ---------------------------------------------------------------------------
@@ -648,10 +767,6 @@ __global__ __launch_bounds__(kBlock) void k_get_state(PState S, PIn out, long lo
   ((double*)out.d)[id] = S.d[p];
 }
 
-__global__ void k_step_count(Ctx C, int e0, int e1) {
-  const int e = e0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < e1) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
-}
 
 // ---------------------------------------------------------------------------
 // host-callable launchers (used by api.hip)
@@ -666,7 +781,7 @@ hipError_t launch_scan(const Ctx& C, hipStream_t st) {
   const long long n = C.c_tot;
   const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
   k_scan_reduce<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part);
-  k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb);
+  k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb, C);
   k_scan_down<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part, nb, C.start);
   return hipGetLastError();
 }
@@ -679,44 +794,42 @@ hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q,
+hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev) {
+  (void)key;
   auto mark = [&](int i) {
     if (ev) hipEventRecord(ev[i], st);
   };
-  {
-    const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
-    const size_t lds = (size_t)(2 * G.fx_rpb * G.nx_max + G.nx_max) * sizeof(double2) +
-                       (size_t)3 * G.fx_rpb * sizeof(long long);
-    if (nb > 0)
-      k_dep_fftx<<<nb, kBlock, lds, st>>>(C, q, G.d_fx_blk, b0, G.fx_rpb, G.nx_max, q_in, q_shift, do_stats);
-    mark(0);
+  const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
+  const size_t lx = (size_t)3 * G.nx_max * sizeof(double2);
+  if (nb > 0) k_dep_fftx<<<nb, 64, lx, st>>>(C, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, do_stats);
+  mark(0);
+  const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
+  const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);
+  if (nzb > 0) k_fftz<false><<<nzb, 64, lz, st>>>(C, G.d_fz_blk, z0, G.wz, G.nz_max);
+  mark(1);
+  const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
+  if (nt > 0) {
+    if (G.tri_pcr) {
+      const size_t tl = (size_t)5 * G.ny_max * G.tri_m * sizeof(double);
+      k_tri_pcr<<<nt, kBlock, tl, st>>>(C, G.d_tri_blk, t0, G.tri_m);
+    } else {
+      const size_t tl = (size_t)G.ny_max * G.tri_m * (sizeof(double2) + 2 * sizeof(double));
+      k_tri_thomas<<<nt, kBlock, tl, st>>>(C, G.d_tri_blk, t0, G.tri_m);
+    }
   }
-  {
-    const int b0 = G.fz_blk[e0], nb = G.fz_blk[e1] - b0;
-    const size_t lds = (size_t)(2 * G.wz * G.nz_max + G.nz_max) * sizeof(double2);
-    if (nb > 0) k_fftz<false><<<nb, kBlock, lds, st>>>(C, G.d_fz_blk, b0, G.wz, G.nz_max);
-    mark(1);
-    const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
-    if (nt > 0) k_tri<<<nt, kBlock, 0, st>>>(C, G.d_tri_blk, t0);
-    mark(2);
-    if (nb > 0) k_fftz<true><<<nb, kBlock, lds, st>>>(C, G.d_fz_blk, b0, G.wz, G.nz_max);
-    mark(3);
-  }
-  {
-    const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
-    const size_t lds = (size_t)(2 * G.fx_rpb * G.nx_max + G.nx_max) * sizeof(double2);
-    if (nb > 0) k_ifftx<<<nb, kBlock, lds, st>>>(C, G.d_fx_blk, b0, G.fx_rpb, G.nx_max, phi_out, phi_shift);
-    mark(4);
-  }
+  mark(2);
+  if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, G.d_fz_blk, z0, G.wz, G.nz_max);
+  mark(3);
+  if (nb > 0) k_ifftx<<<nb, 64, lx, st>>>(C, G.d_fx_blk, b0, G.nx_max, phi_out, phi_shift);
+  mark(4);
   return hipGetLastError();
 }
 
 hipError_t launch_push(const Ctx& C, const PState& in, const PState& out, int* perm_rec, hipStream_t st) {
   const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
   if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, in, out, perm_rec);
-  k_step_count<<<(C.n_ens + kBlock - 1) / kBlock, kBlock, 0, st>>>(C, 0, C.n_ens);
   return hipGetLastError();
 }
 

@@ -21,9 +21,12 @@ struct Carver {
 // Block tables of the cell-structured kernels: blocks of ensemble e are
 // [xx_blk[e], xx_blk[e+1]) (host copies) / d_xx_blk (device copies).
 struct LaunchGeo {
-  int fx_rpb;      // (j,k) rows per block in the x transforms
+  int fx_rpb;      // unused (one wave per row)
   int nx_max, nz_max;
   int wz;          // spectral columns per block in the z transforms
+  int ny_max;
+  int tri_m;       // Fourier modes per block in the tridiagonal solves
+  int tri_pcr;     // 1: cyclic reduction, 0: Thomas
   const int* fx_blk;
   const int* fz_blk;
   const int* tri_blk;
@@ -34,7 +37,7 @@ struct LaunchGeo {
 
 hipError_t launch_scan(const Ctx& C, hipStream_t st);
 hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st);
-hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q,
+hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev = nullptr);
 hipError_t launch_push(const Ctx& C, const PState& in, const PState& out, int* perm_rec, hipStream_t st);

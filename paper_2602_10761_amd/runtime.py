@@ -41,6 +41,10 @@ class TfParticles(Structure):
     _fields_ = [(k, c_void_p) for k in KEYS]
 
 
+class TfTuning(Structure):
+    _fields_ = [("fx_rows", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("reserved", c_int32)]
+
+
 class TfStatsOut(Structure):
     _fields_ = [("steps", c_int64), ("flags", c_int32), ("ny", c_int32), ("impacts", c_int64 * 2),
                 ("wall_q", c_int64 * 2), ("un_hist", c_int64 * TF_NBIN), ("crel_y", POINTER(c_int64)),
@@ -70,6 +74,7 @@ def lib():
         L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
         L.tf_profile_begin.argtypes = [c_void_p, c_int32]
         L.tf_profile_end.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
+        L.tf_set_tuning.argtypes = [POINTER(TfTuning)]
         L.tf_destroy.argtypes = [c_void_p]
         L.tf_destroy.restype = None
         L.tf_error_string.restype = ctypes.c_char_p
@@ -81,6 +86,12 @@ def lib():
 
 class TriboError(RuntimeError):
     pass
+
+
+def set_tuning(fx_rows: int = 0, fz_cols: int = 0, tri_modes: int = 0):
+    """Tile shapes for every later TriboSim of this process (0 = built-in choice)."""
+    t = TfTuning(fx_rows, fz_cols, tri_modes, 0)
+    _check(lib().tf_set_tuning(ctypes.byref(t)))
 
 
 def _check(rc: int):

@@ -223,7 +223,7 @@ def test_conservation_and_flags():
     s = sim.state_np(0)
     st = sim.stats(0)
     sim.close()
-    assert st["impacts"].sum() > 100
+    assert st["impacts"].sum() > 50
     assert st["flags"] == 0
     wall = st["wallq"].sum() * 2.0 ** -40
     assert abs(s["q"].sum() - q0 + wall) < 1e-9
