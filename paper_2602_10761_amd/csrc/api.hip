@@ -112,7 +112,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->tri_m = g_tune.tri_modes > 0 ? g_tune.tri_modes : std::max(1, std::min(16, 65536 / (32 * S->ny_max)));
   const size_t lds_fx = (size_t)3 * S->nx_max * 16;
   const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
-  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * S->ny_max * S->tri_m : (size_t)S->ny_max * S->tri_m * 32;
+  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * (S->ny_max + 1) * S->tri_m : (size_t)S->ny_max * S->tri_m * 32;
   if (lds_fx > 65536 || lds_fz > 65536 || lds_tri > 65536) return fail(TF_ESIZE, "tile shapes exceed 64 KiB of LDS");
   if (S->tri_pcr && S->tri_m * S->ny_max > 8 * kBlock) return fail(TF_ESIZE, "tri_modes * ny exceeds 2048");
   for (int e = 0; e < n_ens; ++e) {
@@ -167,6 +167,7 @@ PState carve_state(Carver& cv, long long n) {
   for (auto* p : f) *p = cv.take<double>(n);
   s.id = cv.take<int>(n);
   s.key = cv.take<int>(n);
+  s.rank = cv.take<int>(n);
   return s;
 }
 
@@ -182,6 +183,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   int* tri = cv.take<int>(n_ens + 1);
   C.yf = cv.take<double>(S.y_tot);
   C.dy = cv.take<double>(S.y_tot);
+  C.idy = cv.take<double>(S.y_tot);
   C.vol = cv.take<double>(S.y_tot);
   C.am = cv.take<double>(S.y_tot);
   C.ap = cv.take<double>(S.y_tot);
@@ -197,6 +199,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.start = cv.take<int>(S.c_tot + 1);
   C.tmp = cv.take<unsigned long long>(S.n_tot);
   C.perm = cv.take<int>(S.n_tot);
+  C.skey = cv.take<int>(S.n_tot);
+  C.sq = cv.take<double>(S.n_tot);
   const long long nbs = (S.c_tot + 4 * kBlock - 1) / (4 * kBlock);
   C.scan_part = cv.take<int>(nbs + 1);
   C.spec = cv.take<double2>(S.s_tot);
@@ -252,7 +256,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, int* 
   if (phi_rec && (e = hipMemcpyAsync(phi_rec, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
                                      h->stream)) != hipSuccess)
     return e;
-  if ((e = launch_push(h->C, in, out, perm_rec, h->stream)) != hipSuccess) return e;
+  if ((e = launch_push(h->C, h->G, in, out, perm_rec, h->stream)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -334,7 +338,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   layout(S, n_ens, traj_steps, flags, workspace, h);
 
   // host tables (same floating-point operations as the textbook definitions)
-  std::vector<double> yf(S.y_tot, 0.0), dy(S.y_tot, 0.0), vol(S.y_tot, 0.0), am(S.y_tot, 0.0),
+  std::vector<double> yf(S.y_tot, 0.0), dy(S.y_tot, 0.0), idy(S.y_tot, 0.0), vol(S.y_tot, 0.0), am(S.y_tot, 0.0),
       ap(S.y_tot, 0.0), beta(S.y_tot, 0.0), kx2(S.kx_tot), kz2(S.kz_tot);
   std::vector<double2> tw(S.tw_tot);
   for (auto& kv : S.tw_off) {
@@ -381,6 +385,14 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.gp1 = (1.0 - 1.0 / T.density_ratio) * T.g[1];
     E.gp2 = (1.0 - 1.0 / T.density_ratio) * T.g[2];
     E.un_bin = T.un_bin;
+    E.inv_dx = 1.0 / E.dx;
+    E.inv_dz = 1.0 / E.dz;
+    E.inv_2dx = 1.0 / (2.0 * E.dx);
+    E.inv_2dz = 1.0 / (2.0 * E.dz);
+    E.inv_nx = 1.0 / T.nx;
+    E.inv_nz = 1.0 / T.nz;
+    E.c18 = 18.0 / T.density_ratio;
+    E.fe = T.k_c * std::pow(1.0 + T.e, 0.4);
     E.U = T.u_nodes;
     radix_plan(T.nx, &E.fx);
     E.fx.tw_off = S.tw_off.at(T.nx);
@@ -392,6 +404,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     std::vector<double> yc(ny), hm(ny), hp(ny);
     for (int j = 0; j < ny; ++j) {
       dy[y_off + j] = Y[j + 1] - Y[j];
+      idy[y_off + j] = 1.0 / dy[y_off + j];
       yc[j] = 0.5 * (Y[j] + Y[j + 1]);
       vol[y_off + j] = (E.dx * dy[y_off + j]) * E.dz;
     }
@@ -430,6 +443,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->d_tri, S.tri_blk);
   UP(h->C.yf, yf);
   UP(h->C.dy, dy);
+  UP(h->C.idy, idy);
   UP(h->C.vol, vol);
   UP(h->C.am, am);
   UP(h->C.ap, ap);
@@ -467,6 +481,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.d_fx_blk = h->d_fx;
   h->G.d_fz_blk = h->d_fz;
   h->G.d_tri_blk = h->d_tri;
+  h->G.eh = h->eh.data();
   h->cur = h->A;
   h->cur_is_A = true;
   *out = h;
@@ -480,7 +495,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
     for (int s = 0; s < n_steps; ++s) {
       HIPCHK(launch_scan(h->C, h->stream));
       HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, h->cur.key, nullptr, 0, h->C.phi, 0, 1, h->stream));
-      HIPCHK(launch_push(h->C, h->cur, other(h), nullptr, h->stream));
+      HIPCHK(launch_push(h->C, h->G, h->cur, other(h), nullptr, h->stream));
     }
     return TF_OK;
   }
@@ -501,6 +516,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
           HIPCHK(hipMemcpyAsync(dst[f], src[f], n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(t.id, c.id, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(t.key, c.key, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(t.rank, c.rank, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         h->cur = t;
       }
       const PState in = h->cur;
@@ -599,6 +615,7 @@ int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
     if (nt) {
       HIPCHK(hipMemcpyAsync(t.id, c.id, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
       HIPCHK(hipMemcpyAsync(t.key, c.key, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(t.rank, c.rank, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
     }
     h->cur = h->A;
     h->cur_is_A = true;
@@ -625,9 +642,11 @@ int tf_set_params(tf_handle* h, const double* theta) {
     h->eh[e].kc = theta[3 * e];
     h->eh[e].dU = theta[3 * e + 1];
     h->eh[e].e = theta[3 * e + 2];
+    h->eh[e].fe = h->eh[e].kc * std::pow(1.0 + h->eh[e].e, 0.4);
   }
   HIPCHK(hipMemcpyAsync((void*)h->C.ens, h->eh.data(), sizeof(Ens) * h->n_ens, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  destroy_graphs(h);  // captured launches carry the old descriptor by value
   return TF_OK;
 }
 

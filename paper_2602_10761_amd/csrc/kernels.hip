@@ -75,7 +75,8 @@ __global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int 
   if (threadIdx.x == 0) part[nb] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cnt, long long n,
+// writes start and clears the counts for the next step's arrivals
+__global__ __launch_bounds__(kBlock) void k_scan_down(int* __restrict__ cnt, long long n,
                                                       const int* __restrict__ part, int nb,
                                                       int* __restrict__ start) {
   const long long base = (long long)blockIdx.x * kScanChunk + 4LL * threadIdx.x;
@@ -86,6 +87,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cn
     v[r] = (base + r < n) ? cnt[base + r] : 0;
     s += v[r];
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (base + r < n) cnt[base + r] = 0;
   int tot;
   int ex = block_excl_scan<kBlock / 64>(s, &tot) + part[blockIdx.x];
 #pragma unroll
@@ -99,17 +103,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cn
 // ---------------------------------------------------------------------------
 // counting sort by (cell, id)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_assign(Ctx C, const int* __restrict__ key,
-                                                   const int* __restrict__ id) {
-  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+// place each particle in its cell's run at its arrival rank (unordered within the run)
+__global__ __launch_bounds__(kBlock) void k_place(Ctx C, const int* __restrict__ key, const int* __restrict__ rank,
+                                                  const int* __restrict__ id) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= C.n_tot) return;
   const int c = key[p];
-  const int slot = C.start[c] + atomicSub(&C.count[c], 1) - 1;
-  if (slot < C.start[c] || slot >= C.start[c + 1]) return;  // counts inconsistent with keys: never by construction
+  const int a = C.start[c];
+  const int slot = a + rank[p];
+  if (slot < a || slot >= C.start[c + 1]) return;  // ranks inconsistent with counts: never by construction
   C.tmp[slot] = ((unsigned long long)(unsigned)id[p] << 32) | (unsigned long long)(unsigned)p;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rank(Ctx C, const int* __restrict__ key) {
+__global__ __launch_bounds__(kBlock) void k_rank(Ctx C, const int* __restrict__ key, const double* __restrict__ q) {
   const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (s >= C.n_tot) return;
   const unsigned long long v = C.tmp[s];
@@ -122,6 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_rank(Ctx C, const int* __restrict__ 
   if (b - a > 1)
     for (int t = a; t < b; ++t) r += ((unsigned)(C.tmp[t] >> 32) < idv) ? 1 : 0;
   C.perm[a + r] = p;
+  C.skey[a + r] = c;
+  C.sq[a + r] = q[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -182,11 +190,15 @@ __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2*
   const int nb = n / R;
   const int stride = n / (Ns * R);
   const int total = rows * nb;
+  const unsigned mnb = rows > 1 ? magic32(nb) : 0u;
+  const bool ns2 = (Ns & (Ns - 1)) == 0;
+  const unsigned mns = ns2 ? 0u : magic32(Ns);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int row = t / nb, jj = t - row * nb;
+    const int row = rows > 1 ? fdiv32(t, mnb, nb) : 0;
+    const int jj = t - row * nb;
     const double2* s = a + row * pitch;
     double2* d = b + row * pitch;
-    const int k = jj % Ns;
+    const int k = ns2 ? (jj & (Ns - 1)) : jj - fdiv32(jj, mns, Ns) * Ns;
     double2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = s[jj + r * nb];
@@ -197,7 +209,7 @@ __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2*
       v[r] = cmul(v[r], w);
     }
     butterfly<R, INV>(v);
-    const int base = (jj / Ns) * Ns * R + k;
+    const int base = (jj - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) d[base + r * Ns] = v[r];
   }
@@ -243,7 +255,7 @@ __device__ __forceinline__ long long wave_sum(long long v) {
 // are summed in integers (exact, order-free).  q source: particles
 // (q_in == nullptr) or a per-cell fixed-point array.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict__ q,
+__global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const double* __restrict__ q,
                                                  const int* __restrict__ blk_off, int blk0, int nmax,
                                                  const long long* __restrict__ q_in, long long q_shift,
                                                  int do_stats) {
@@ -251,14 +263,22 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict
   double2* buf0 = lds;
   double2* buf1 = lds + nmax;
   double2* tw = lds + 2 * nmax;
-  const int gb = blk0 + blockIdx.x;
-  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-  const Ens& E = C.ens[e];
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = blockIdx.x;
+  } else {
+    const int gb = blk0 + blockIdx.x;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
   const int nx = E.nx, nz = E.nz;
-  const int jk = gb - blk_off[e];
-  const int j = jk / nz;
+  const int jk = lb;
+  const int j = fdiv32(jk, magic32(nz), nz);
   const long long c0 = E.c_off + (long long)jk * nx;
-  const double vol = C.vol[E.y_off + j];
+  const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
 
   for (int t = threadIdx.x; t < nx; t += 64) tw[t] = C.tw[E.fx.tw_off + t];
   bool ovf = false;
@@ -271,7 +291,7 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict
       const int a = C.start[c0 + i], b = C.start[c0 + i + 1];
       long long Q32 = 0;
       for (int s = a; s < b; ++s) {
-        const double qv = q[C.perm[s]];
+        const double qv = C.sq[s];
         Q += fixed_round(qv, kFixDep, &ovf);
         Q32 += fixed_round(qv, kFixQcum, &ovf);
       }
@@ -279,7 +299,7 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict
       rq32 += Q32;
     }
     rq48 += Q;
-    buf0[i] = make_double2(((double)Q * (1.0 / 281474976710656.0)) / vol, 0.0);
+    buf0[i] = make_double2((double)Q * rsc, 0.0);
   }
   if (do_stats) {
     const int cnt = C.start[c0 + nx] - C.start[c0];
@@ -304,37 +324,45 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, const double* __restrict
 // FFT along z on the half spectrum: block = (ensemble, y plane, wz columns)
 // ---------------------------------------------------------------------------
 template <bool INV>
-__global__ __launch_bounds__(64) void k_fftz(Ctx C, const int* __restrict__ blk_off, int blk0, int wz,
-                                             int nmax) {
+__global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
+                                             int wz, int nmax) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
   double2* buf1 = lds + wz * (nmax + 1);
   double2* tw = lds + 2 * wz * (nmax + 1);
-  const int gb = blk0 + blockIdx.x;
-  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-  const Ens& E = C.ens[e];
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = blockIdx.x;
+  } else {
+    const int gb = blk0 + blockIdx.x;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
   const int nz = E.nz, nh = E.nh, nhp = E.nhp;
   const int pitch = nz + 1;  // odd pitch (in 16-byte units): no bank conflicts in the transposes
   const int nchunk = (nh + wz - 1) / wz;
-  const int lb = gb - blk_off[e];
-  const int j = lb / nchunk;
+    const int j = fdiv32(lb, magic32(nchunk), nchunk);
   const int m0 = (lb - j * nchunk) * wz;
   const int w = min(wz, nh - m0);
   for (int t = threadIdx.x; t < nz; t += blockDim.x) tw[t] = C.tw[E.fz.tw_off + t];
   double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
+  const unsigned mw = magic32(w);
   for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
-    const int c = t % w, k = t / w;
-    buf0[c * pitch + k] = sp[(long long)k * nhp + c];
+    const int k = fdiv32(t, mw, w), c = t - k * w;
+    buf0[c * pitch + k] = sp[k * nhp + c];
   }
   __syncthreads();
   FftPlan P = E.fz;
   double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw);
   const double sc = INV ? 1.0 / (double)nz : 1.0;
   for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
-    const int c = t % w, k = t / w;
+    const int k = fdiv32(t, mw, w), c = t - k * w;
     double2 v = res[c * pitch + k];
     if (INV) v = make_double2(v.x * sc, v.y * sc);
-    sp[(long long)k * nhp + c] = v;
+    sp[k * nhp + c] = v;
   }
 }
 
@@ -345,14 +373,23 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, const int* __restrict__ blk_
 // staged in LDS with coalesced loads; one thread per (mode, re/im) runs the
 // Thomas sweeps in LDS; coalesced stores.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, const int* __restrict__ blk_off, int blk0, int tm) {
+__global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
+                                                       int blk0, int tm) {
   extern __shared__ double2 lds[];
-  const int gb = blk0 + blockIdx.x;
-  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-  const Ens& E = C.ens[e];
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = blockIdx.x;
+  } else {
+    const int gb = blk0 + blockIdx.x;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
   const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
   const int nm = nh * nz;
-  const int mode0 = (gb - blk_off[e]) * tm;
+  const int mode0 = lb * tm;
   const int w = min(tm, nm - mode0);
   double2* col = lds;                          // [ny][tm]
   double* cps = (double*)(lds + ny * tm);      // [ny][2*tm]
@@ -415,17 +452,27 @@ __global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, const int* __restr
 // ---------------------------------------------------------------------------
 constexpr int kPcrEq = 8;  // equations per thread
 
-__global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict__ blk_off, int blk0, int tm) {
+__global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
+                                                    int blk0, int tm) {
   extern __shared__ double ldsd[];
-  const int gb = blk0 + blockIdx.x;
-  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-  const Ens& E = C.ens[e];
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = blockIdx.x;
+  } else {
+    const int gb = blk0 + blockIdx.x;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
   const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
   const int nm = nh * nz;
-  const int mode0 = (gb - blk_off[e]) * tm;
+  const int mode0 = lb * tm;
   const int w = min(tm, nm - mode0);
   const int neq = w * ny;
-  const int cap = tm * ny;
+  const int nyp = ny + 1;        // padded mode stride: no LDS bank conflicts
+  const int cap = tm * nyp;
   double* A = ldsd;
   double* B = A + cap;
   double* Cc = B + cap;
@@ -437,12 +484,13 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict
   double2* sp = C.spec + E.s_off;
   // coalesced load: consecutive threads take consecutive modes of one y row;
   // equation index q = c*ny + j (each mode's equations contiguous)
+  const unsigned mw = magic32(w), mnh = magic32(nh), mny = magic32(ny);
   for (int t = threadIdx.x; t < neq; t += blockDim.x) {
-    const int j = t / w, c = t - j * w;
+    const int j = fdiv32(t, mw, w), c = t - j * w;
     const int mode = mode0 + c;
-    const int mz = mode / nh, m = mode - mz * nh;
+    const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
     const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
-    const int qi = c * ny + j;
+    const int qi = c * nyp + j;
     const double2 r = sp[j * pitch + (long long)mz * nhp + m];
     A[qi] = (j > 0) ? -am[j] : 0.0;
     Cc[qi] = (j < ny - 1) ? -ap[j] : 0.0;
@@ -452,12 +500,21 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict
   }
   __syncthreads();
   double ra[kPcrEq], rb[kPcrEq], rc[kPcrEq], rdr[kPcrEq], rdi[kPcrEq];
+  int jj[kPcrEq];
+  int qq[kPcrEq];
+#pragma unroll
+  for (int u = 0; u < kPcrEq; ++u) {
+    const int t = threadIdx.x + u * kBlock;
+    const int c = fdiv32(t, mny, ny);
+    jj[u] = t - c * ny;
+    qq[u] = c * nyp + jj[u];  // padded index of the thread's u-th equation
+  }
   for (int delta = 1; delta < ny; delta <<= 1) {
 #pragma unroll
     for (int u = 0; u < kPcrEq; ++u) {
-      const int qi = threadIdx.x + u * kBlock;
-      if (qi < neq) {
-        const int j = qi % ny;
+      const int qi = qq[u];
+      if (threadIdx.x + u * kBlock < neq) {
+        const int j = jj[u];
         const double a = A[qi], b = B[qi], c = Cc[qi];
         double na = 0.0, nc = 0.0, nb = b, ndr = Dr[qi], ndi = Di[qi];
         if (j >= delta) {
@@ -486,8 +543,8 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPcrEq; ++u) {
-      const int qi = threadIdx.x + u * kBlock;
-      if (qi < neq) {
+      const int qi = qq[u];
+      if (threadIdx.x + u * kBlock < neq) {
         A[qi] = ra[u];
         B[qi] = rb[u];
         Cc[qi] = rc[u];
@@ -498,10 +555,10 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict
     __syncthreads();
   }
   for (int t = threadIdx.x; t < neq; t += blockDim.x) {
-    const int j = t / w, c = t - j * w;
+    const int j = fdiv32(t, mw, w), c = t - j * w;
     const int mode = mode0 + c;
-    const int mz = mode / nh, m = mode - mz * nh;
-    const int qi = c * ny + j;
+    const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
+    const int qi = c * nyp + j;
     const double b = B[qi];
     sp[j * pitch + (long long)mz * nhp + m] = make_double2(Dr[qi] / b, Di[qi] / b);
   }
@@ -510,17 +567,25 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, const int* __restrict
 // ---------------------------------------------------------------------------
 // inverse FFT along x (Hermitian half spectrum -> real): one wave per row
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_ifftx(Ctx C, const int* __restrict__ blk_off, int blk0, int nmax,
-                                              double* __restrict__ phi_out, long long phi_shift) {
+__global__ __launch_bounds__(64) void k_ifftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
+                                              int nmax, double* __restrict__ phi_out, long long phi_shift) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
   double2* buf1 = lds + nmax;
   double2* tw = lds + 2 * nmax;
-  const int gb = blk0 + blockIdx.x;
-  const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-  const Ens& E = C.ens[e];
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = blockIdx.x;
+  } else {
+    const int gb = blk0 + blockIdx.x;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
   const int nx = E.nx, nh = E.nh;
-  const int jk = gb - blk_off[e];
+  const int jk = lb;
   const double2* sp = C.spec + E.s_off + (long long)jk * E.nhp;
   for (int t = threadIdx.x; t < nx; t += 64) {
     tw[t] = C.tw[E.fx.tw_off + t];
@@ -549,49 +614,51 @@ __device__ __forceinline__ int clamp_floor(double v, int n) {
   return (f >= 0.0) ? (f < (double)(n - 1) ? (int)f : n - 1) : 0;
 }
 
-// local cell (j*nz + k)*nx + i holding (x, y, z): floor in x, z; face search in y
-__device__ __forceinline__ int locate_local(const Ens& E, const double* __restrict__ yf, double x, double y,
-                                            double z) {
-  const int i = clamp_floor(x / E.dx, E.nx);
-  const int k = clamp_floor(z / E.dz, E.nz);
-  int lo = 0, hi = E.ny - 1;
+// largest j in [0, ny-1] with yf[j] <= y (0 if none), searched from a guess
+__device__ __forceinline__ int y_cell_from(const double* __restrict__ yf, int ny, double y, int j) {
+  while (j > 0 && y < yf[j]) --j;
+  while (j < ny - 1 && y >= yf[j + 1]) ++j;
+  return j;
+}
+
+// largest j in [0, ny-1] with yf[j] <= y (0 if none), binary search
+__device__ __forceinline__ int y_cell(const double* __restrict__ yf, int ny, double y) {
+  int lo = 0, hi = ny - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (yf[mid] <= y) lo = mid; else hi = mid - 1;
   }
-  return (lo * E.nz + k) * E.nx + i;
+  return lo;
 }
 
+// initial binning; rank = arrival order in the cell (for the next sort)
 __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, long long n1) {
   const long long p = n0 + (long long)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n1) return;
   const int e = find_off(C.p_off, C.n_ens + 1, p);
   const Ens& E = C.ens[e];
-  const int c = (int)(E.c_off + locate_local(E, C.yf + E.y_off, S.x[p], S.y[p], S.z[p]));
+  const double x = S.x[p], y = S.y[p], z = S.z[p];
+  const int i = clamp_floor(x / E.dx, E.nx);
+  const int k = clamp_floor(z / E.dz, E.nz);
+  const int j = y_cell(C.yf + E.y_off, E.ny, y);
+  const int c = (int)(E.c_off + (long long)(j * E.nz + k) * E.nx + i);
   S.key[p] = c;
-  atomicAdd(&C.count[c], 1);
+  S.rank[p] = atomicAdd(&C.count[c], 1);
 }
 
 // ---------------------------------------------------------------------------
-// the particle push
+// the particle push: one thread per sorted slot s, E uniform over the lanes
+// that share an ensemble (scalar descriptor loads)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, int* __restrict__ perm_rec) {
-  const long long nblk = gridDim.x;
-  const long long s = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
-  if (s >= C.n_tot) return;
-  const int p = C.perm[s];
-  if (perm_rec) perm_rec[s] = p;
-  const int c = in.key[p];
-  const int e = find_off(C.c_off, C.n_ens + 1, c);
-  const Ens& E = C.ens[e];
+__device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
+                                         int p, int c) {
   const int nx = E.nx, ny = E.ny, nz = E.nz;
-  const int cl = (int)(c - E.c_off);
-  const int i = cl % nx;
-  const int jk = cl / nx;
-  const int k = jk % nz;
-  const int j = jk / nz;
+  const int cl = c - (int)E.c_off;
+  int jk, i, j, k;
+  divmod(cl, nx, E.inv_nx, &jk, &i);
+  divmod(jk, nz, E.inv_nz, &j, &k);
   const double* __restrict__ yf = C.yf + E.y_off;
-  const double* __restrict__ dyt = C.dy + E.y_off;
+  const double* __restrict__ idy = C.idy + E.y_off;
 
   const double x = in.x[p], y = in.y[p], z = in.z[p];
   const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
@@ -600,12 +667,13 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, i
   // carrier velocity: trilinear in the cell, linear in physical y
   const int i1 = (i + 1 == nx) ? 0 : i + 1;
   const int k1 = (k + 1 == nz) ? 0 : k + 1;
-  const double tx = (x - (double)i * E.dx) / E.dx;
-  const double ty = (y - yf[j]) / dyt[j];
-  const double tz = (z - (double)k * E.dz) / E.dz;
-  const long long plane = (long long)(ny + 1) * nz * nx;
-  const long long n00 = ((long long)j * nz + k) * nx, n01 = ((long long)j * nz + k1) * nx;
-  const long long n10 = ((long long)(j + 1) * nz + k) * nx, n11 = ((long long)(j + 1) * nz + k1) * nx;
+  const double tx = (x - (double)i * E.dx) * E.inv_dx;
+  const double ty = (y - yf[j]) * idy[j];
+  const double tz = (z - (double)k * E.dz) * E.inv_dz;
+  const int nxz = nz * nx;
+  const int plane = (ny + 1) * nxz;
+  const int n00 = (j * nz + k) * nx, n01 = (j * nz + k1) * nx;
+  const int n10 = n00 + nxz, n11 = n01 + nxz;
   double uc[3];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
@@ -624,18 +692,18 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, i
   const int im = (i == 0) ? nx - 1 : i - 1;
   const int km = (k == 0) ? nz - 1 : k - 1;
   const double pc = ph[cl];
-  const double Ex = -(ph[n00 + i1] - ph[n00 + im]) / (2.0 * E.dx);
-  const double Ez = -(ph[n01 + i] - ph[((long long)j * nz + km) * nx + i]) / (2.0 * E.dz);
+  const double Ex = -(ph[n00 + i1] - ph[n00 + im]) * E.inv_2dx;
+  const double Ez = -(ph[n01 + i] - ph[(j * nz + km) * nx + i]) * E.inv_2dz;
   double ftop = 0.0, fbot = 0.0;
   if (j < ny - 1) {
-    const double pn = ph[n10 + i];
+    const double pn = ph[n00 + nxz + i];
     ftop = pc + C.beta[E.y_off + j + 1] * (pn - pc);
   }
   if (j > 0) {
-    const double pm = ph[((long long)(j - 1) * nz + k) * nx + i];
+    const double pm = ph[n00 - nxz + i];
     fbot = pm + C.beta[E.y_off + j] * (pc - pm);
   }
-  const double Ey = -(ftop - fbot) / dyt[j];
+  const double Ey = -(ftop - fbot) * idy[j];
 
   // near field: Coulomb's law with the other particles of the cell, ascending id
   double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -647,29 +715,29 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, i
       const double rx = x - in.x[pj], ry = y - in.y[pj], rz = z - in.z[pj];
       const double r2 = (rx * rx + ry * ry) + rz * rz;
       if (r2 > 0.0) {
-        const double w = in.q[pj] / (r2 * sqrt(r2));
-        sx = sx + w * rx;
-        sy = sy + w * ry;
-        sz = sz + w * rz;
+        const double ri = rsqrt(r2);
+        const double w = in.q[pj] * (ri * ri * ri);
+        sx += w * rx;
+        sy += w * ry;
+        sz += w * rz;
       }
     }
   }
 
   // forces and semi-implicit Euler
-  const double ke = (E.cel * q) / ((d * d) * d);
+  const double d2 = d * d;
+  const double ke = (E.cel * q) / (d2 * d);
   const double ax = E.gp0 + ke * (Ex + sx * kInv4Pi);
   const double ay = E.gp1 + ke * (Ey + sy * kInv4Pi);
   const double az = E.gp2 + ke * (Ez + sz * kInv4Pi);
   const double dux = vx - uc[0], duy = vy - uc[1], duz = vz - uc[2];
-  const double rel = sqrt((dux * dux + duy * duy) + duz * duz);
-  const double re = rel * d;
-  const double phid = (re <= 1000.0) ? 1.0 + pow(re, 2.0 / 3.0) / 6.0 : 0.424 * re / 24.0;
-  const double taup = ((E.rr * d) * d) / 18.0;
-  const double sdr = phid / taup;
-  const double den = 1.0 + E.dt * sdr;
-  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) / den;
-  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) / den;
-  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) / den;
+  const double re = sqrt((dux * dux + duy * duy) + duz * duz) * d;
+  const double phid = (re <= 1000.0) ? 1.0 + cbrt(re * re) * (1.0 / 6.0) : 0.424 * re * (1.0 / 24.0);
+  const double sdr = phid * (E.c18 / d2);  // phi_D / tau_p
+  const double iden = 1.0 / (1.0 + E.dt * sdr);
+  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) * iden;
+  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) * iden;
+  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) * iden;
   double x1 = x + E.dt * v1x;
   const double y1 = y + E.dt * v1y;
   double z1 = z + E.dt * v1z;
@@ -691,7 +759,7 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, i
   long long* st = C.stats + E.st_off;
   if (wall >= 0) {
     vyr = -E.e * v1y;
-    const double f = (E.kc * pow(1.0 + E.e, 0.4)) * pow(un, 0.8);
+    const double f = E.fe * pow(un, 0.8);
     const double dq = -f * (E.dU + q);
     q1 = q + dq;
     bool ovf = false;
@@ -725,9 +793,36 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, PState in, PState out, i
   out.q[s] = q1;
   out.d[s] = d;
   out.id[s] = in.id[p];
-  const int key = (int)(E.c_off + locate_local(E, yf, x1, yr, z1));
+  // next cell: exact divisions in x, z; local face search in y from the old cell
+  const int ni = clamp_floor(x1 / E.dx, nx);
+  const int nk = clamp_floor(z1 / E.dz, nz);
+  const int nj = y_cell_from(yf, ny, yr, j);
+  const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
   out.key[s] = key;
-  atomicAdd(&C.count[key], 1);
+  out.rank[s] = atomicAdd(&C.count[key], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
+                                                 int* __restrict__ perm_rec) {
+  const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+  if (s >= C.n_tot) return;
+  const int p = C.perm[s];
+  if (perm_rec) perm_rec[s] = p;
+  const int c = C.skey[s];
+  if (one) {
+    push_one(C, Eone, in, out, s, p, c);
+    return;
+  }
+  const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
+  // waterfall over the ensembles present in this wave (usually one)
+  bool done = false;
+  while (!done) {
+    const int e = __builtin_amdgcn_readfirstlane(e_lane);
+    if (e_lane == e) {
+      push_one(C, C.ens[e], in, out, s, p, c);
+      done = true;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_put_state(PState S, PIn in, long lon
   S.d[p] = in.d[t];
   S.id[p] = t;
 }
+
 
 __global__ __launch_bounds__(kBlock) void k_get_state(PState S, PIn out, long long p0, int n) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -789,8 +885,8 @@ hipError_t launch_scan(const Ctx& C, hipStream_t st) {
 hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st) {
   const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
   if (nb == 0) return hipSuccess;
-  k_assign<<<nb, kBlock, 0, st>>>(C, cur.key, cur.id);
-  k_rank<<<nb, kBlock, 0, st>>>(C, cur.key);
+  k_place<<<nb, kBlock, 0, st>>>(C, cur.key, cur.rank, cur.id);
+  k_rank<<<nb, kBlock, 0, st>>>(C, cur.key, cur.q);
   return hipGetLastError();
 }
 
@@ -801,35 +897,39 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   auto mark = [&](int i) {
     if (ev) hipEventRecord(ev[i], st);
   };
+  const int one = (e1 - e0 == 1) ? 1 : 0;
+  const Ens Eone = G.eh[e0];
   const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
   const size_t lx = (size_t)3 * G.nx_max * sizeof(double2);
-  if (nb > 0) k_dep_fftx<<<nb, 64, lx, st>>>(C, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, do_stats);
+  if (nb > 0) k_dep_fftx<<<nb, 64, lx, st>>>(C, Eone, one, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, do_stats);
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
   const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);
-  if (nzb > 0) k_fftz<false><<<nzb, 64, lz, st>>>(C, G.d_fz_blk, z0, G.wz, G.nz_max);
+  if (nzb > 0) k_fftz<false><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
     if (G.tri_pcr) {
-      const size_t tl = (size_t)5 * G.ny_max * G.tri_m * sizeof(double);
-      k_tri_pcr<<<nt, kBlock, tl, st>>>(C, G.d_tri_blk, t0, G.tri_m);
+      const size_t tl = (size_t)5 * (G.ny_max + 1) * G.tri_m * sizeof(double);
+      k_tri_pcr<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
     } else {
       const size_t tl = (size_t)G.ny_max * G.tri_m * (sizeof(double2) + 2 * sizeof(double));
-      k_tri_thomas<<<nt, kBlock, tl, st>>>(C, G.d_tri_blk, t0, G.tri_m);
+      k_tri_thomas<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
     }
   }
   mark(2);
-  if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, G.d_fz_blk, z0, G.wz, G.nz_max);
+  if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(3);
-  if (nb > 0) k_ifftx<<<nb, 64, lx, st>>>(C, G.d_fx_blk, b0, G.nx_max, phi_out, phi_shift);
+  if (nb > 0) k_ifftx<<<nb, 64, lx, st>>>(C, Eone, one, G.d_fx_blk, b0, G.nx_max, phi_out, phi_shift);
   mark(4);
   return hipGetLastError();
 }
 
-hipError_t launch_push(const Ctx& C, const PState& in, const PState& out, int* perm_rec, hipStream_t st) {
+hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
+                       hipStream_t st) {
   const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
-  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, in, out, perm_rec);
+  const int one = (C.n_ens == 1) ? 1 : 0;
+  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec);
   return hipGetLastError();
 }
 

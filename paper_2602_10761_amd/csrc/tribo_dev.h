@@ -33,6 +33,11 @@ struct Ens {
   int st_off;        // first int64 of the statistics block
   double lx, ly, lz, dx, dz;
   double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
+  // derived on the host
+  double inv_dx, inv_dz, inv_2dx, inv_2dz;  // 1/dx, 1/dz, 1/(2dx), 1/(2dz)
+  double inv_nx, inv_nz;                    // 1/nx, 1/nz (index decomposition)
+  double c18;                               // 18 / rr  (1/tau_p = c18 / d^2)
+  double fe;                                // k_c (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
   FftPlan fx, fz;
 };
@@ -43,10 +48,11 @@ inline int stats_len(int ny) { return ST_Y + 2 * ny; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
 
-// Particle buffer (structure of arrays).  key = global cell of the position.
+// Particle buffer (structure of arrays).  key = global cell of the position,
+// rank = arrival order of the particle in that cell's counter (unordered).
 struct PState {
   double *x, *y, *z, *vx, *vy, *vz, *q, *d;
-  int *id, *key;
+  int *id, *key, *rank;
 };
 
 // Everything the kernels share (device pointers into the workspace).
@@ -61,6 +67,8 @@ struct Ctx {
   int* start;                // [c_tot+1] exclusive prefix of count
   unsigned long long* tmp;   // [n_tot]   (id << 32 | old slot), unordered within a cell
   int* perm;                 // [n_tot]   new slot -> old slot, ordered by (cell, id)
+  int* skey;                 // [n_tot]   cell of each new slot
+  double* sq;                // [n_tot]   charge of each new slot
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
   double* cp;                // Thomas scratch (same indexing as spec)
@@ -68,7 +76,7 @@ struct Ctx {
   long long* stats;          // statistics blocks
   long long* rowq;           // [sum ny*nz] sum rne(q 2^48) per (j,k) row, latest deposit
   long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
-  const double *yf, *dy, *vol, *am, *ap, *beta, *kx2, *kz2;
+  const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
 };
 
@@ -97,6 +105,32 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb) {
   long long q = nb / nx, r = nb % nx;
   long long x = b % nx, w = b / nx;
   return x * q + (x < r ? x : r) + w;
+}
+
+// floor(t / d) for 0 <= t, d < 2^16 by multiply-high with m = ceil(2^32 / d):
+// t*m/2^32 exceeds t/d by less than t*d/2^32 / d < 1/d, the gap to the next
+// integer.  2^32/d has a fractional part >= 1/d >= 2^-16 unless d | 2^32, so
+// ceil of its correctly rounded double is exact.
+__device__ __forceinline__ unsigned magic32(int d) {
+  return d > 1 ? (unsigned)ceil(4294967296.0 / (double)d) : 0u;
+}
+__device__ __forceinline__ int fdiv32(int t, unsigned m, int d) {
+  return d > 1 ? (int)__umulhi((unsigned)t, m) : t;
+}
+
+// quotient and remainder of a >= 0 (< 2^31) by d, with inv_d = 1/d
+__device__ __forceinline__ void divmod(int a, int d, double inv_d, int* q, int* r) {
+  int qq = (int)((double)a * inv_d);
+  int rr = a - qq * d;
+  if (rr < 0) {
+    qq -= 1;
+    rr += d;
+  } else if (rr >= d) {
+    qq += 1;
+    rr -= d;
+  }
+  *q = qq;
+  *r = rr;
 }
 
 __device__ __forceinline__ long long fixed_round(double v, int shift, bool* ovf) {
