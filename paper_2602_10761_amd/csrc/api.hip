@@ -130,7 +130,10 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
 struct TrajBuf {
   PState st;
   int* perm;
+  int* skey;
+  int* start;
   double* phi;
+  signed char* wall;
 };
 
 struct tf_handle {
@@ -212,8 +215,12 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     for (int t = 0; t <= traj_steps; ++t) {
       TrajBuf tb;
       tb.st = carve_state(cv, S.n_tot);
-      tb.perm = (t < traj_steps) ? cv.take<int>(S.n_tot) : nullptr;
-      tb.phi = (t < traj_steps) ? cv.take<double>(S.c_tot) : nullptr;
+      const bool last = (t == traj_steps);
+      tb.perm = last ? nullptr : cv.take<int>(S.n_tot);
+      tb.skey = last ? nullptr : cv.take<int>(S.n_tot);
+      tb.start = last ? nullptr : cv.take<int>(S.c_tot + 1);
+      tb.phi = last ? nullptr : cv.take<double>(S.c_tot);
+      tb.wall = last ? nullptr : cv.take<signed char>(S.n_tot);
       traj.push_back(tb);
     }
   }
@@ -242,21 +249,31 @@ void destroy_graphs(tf_handle* h) {
   h->g_ab = h->g_ba = nullptr;
 }
 
-hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, int* perm_rec, double* phi_rec) {
+hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const TrajBuf* rec) {
   hipError_t e;
   hipEvent_t* ev = nullptr;
   if (h->prof_n < h->prof_cap) ev = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
   if (ev && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
   if ((e = launch_scan(h->C, h->stream)) != hipSuccess) return e;
   if ((e = launch_sort(h->C, in, h->stream)) != hipSuccess) return e;
+  if (rec) {
+    if ((e = hipMemcpyAsync(rec->skey, h->C.skey, sizeof(int) * h->C.n_tot, hipMemcpyDeviceToDevice, h->stream)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(rec->start, h->C.start, sizeof(int) * (h->C.c_tot + 1), hipMemcpyDeviceToDevice,
+                            h->stream)) != hipSuccess)
+      return e;
+  }
   if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
   if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
                           ev ? ev + 2 : nullptr)) != hipSuccess)
     return e;
-  if (phi_rec && (e = hipMemcpyAsync(phi_rec, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
-                                     h->stream)) != hipSuccess)
+  if (rec && (e = hipMemcpyAsync(rec->phi, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
+                                 h->stream)) != hipSuccess)
     return e;
-  if ((e = launch_push(h->C, h->G, in, out, perm_rec, h->stream)) != hipSuccess) return e;
+  if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
+      hipSuccess)
+    return e;
   if (ev && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -264,7 +281,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, int* 
 int capture(tf_handle* h, const PState& in, const PState& out, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_step(h, in, out, nullptr, nullptr);
+  hipError_t e = enqueue_step(h, in, out, nullptr);
   hipError_t e2 = hipStreamEndCapture(h->stream, &g);
   if (e != hipSuccess) return fail(TF_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(TF_EHIP, std::string("graph capture end: ") + hipGetErrorString(e2));
@@ -393,6 +410,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.inv_nz = 1.0 / T.nz;
     E.c18 = 18.0 / T.density_ratio;
     E.fe = T.k_c * std::pow(1.0 + T.e, 0.4);
+    E.pe = std::pow(1.0 + T.e, 0.4);
     E.U = T.u_nodes;
     radix_plan(T.nx, &E.fx);
     E.fx.tw_off = S.tw_off.at(T.nx);
@@ -495,7 +513,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
     for (int s = 0; s < n_steps; ++s) {
       HIPCHK(launch_scan(h->C, h->stream));
       HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, h->cur.key, nullptr, 0, h->C.phi, 0, 1, h->stream));
-      HIPCHK(launch_push(h->C, h->G, h->cur, other(h), nullptr, h->stream));
+      HIPCHK(launch_push(h->C, h->G, h->cur, other(h), nullptr, nullptr, h->stream));
     }
     return TF_OK;
   }
@@ -521,7 +539,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
       }
       const PState in = h->cur;
       const PState out = h->traj[h->traj_len + 1].st;
-      HIPCHK(enqueue_step(h, in, out, tb.perm, tb.phi));
+      HIPCHK(enqueue_step(h, in, out, &tb));
       h->cur = out;
       h->traj_len++;
     }
@@ -531,7 +549,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   const bool in_traj = !(h->cur.x == h->A.x || h->cur.x == h->B.x);
   int s = 0;
   if (in_traj && n_steps > 0) {
-    HIPCHK(enqueue_step(h, h->cur, h->A, nullptr, nullptr));
+    HIPCHK(enqueue_step(h, h->cur, h->A, nullptr));
     h->cur = h->A;
     h->cur_is_A = true;
     s = 1;
@@ -549,7 +567,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
     if (graphs) {
       HIPCHK(hipGraphLaunch(h->cur_is_A ? h->g_ab : h->g_ba, h->stream));
     } else {
-      HIPCHK(enqueue_step(h, h->cur, other(h), nullptr, nullptr));
+      HIPCHK(enqueue_step(h, h->cur, other(h), nullptr));
     }
     h->cur = other(h);
     h->cur_is_A = !h->cur_is_A;
@@ -643,6 +661,7 @@ int tf_set_params(tf_handle* h, const double* theta) {
     h->eh[e].dU = theta[3 * e + 1];
     h->eh[e].e = theta[3 * e + 2];
     h->eh[e].fe = h->eh[e].kc * std::pow(1.0 + h->eh[e].e, 0.4);
+    h->eh[e].pe = std::pow(1.0 + h->eh[e].e, 0.4);
   }
   HIPCHK(hipMemcpyAsync((void*)h->C.ens, h->eh.data(), sizeof(Ens) * h->n_ens, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -689,11 +708,14 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
   for (int t = 0; t <= h->traj_len; ++t) {
     steps[t].st = h->traj[t].st;
     steps[t].perm = h->traj[t].perm;
+    steps[t].skey = h->traj[t].skey;
+    steps[t].start = h->traj[t].start;
     steps[t].phi = h->traj[t].phi;
+    steps[t].wall = h->traj[t].wall;
   }
   std::vector<double> dth(3 * (size_t)h->n_ens, 0.0);
-  hipError_t he = run_adjoint(h->C, h->G, h->adj, h->n_ens, h->eh.data(), h->p_off.data(), steps.data(),
-                              h->traj_len, lam.data(), w_wall, dth.data(), h->stream);
+  hipError_t he = run_adjoint(h->C, h->G, h->adj, h->n_ens, h->eh.data(), h->p_off.data(), h->c_off.data(),
+                              steps.data(), h->traj_len, lam.data(), w_wall, dth.data(), h->stream);
   if (he != hipSuccess) return fail(TF_EHIP, std::string("adjoint: ") + hipGetErrorString(he));
   for (size_t i = 0; i < dth.size(); ++i) dtheta[i] += dth[i];
   h->traj_len = 0;

@@ -15,6 +15,7 @@
 // Particle state is stored in the slot order of the previous step's sort; the
 // push gathers through perm (nearly coalesced) and writes in the new order.
 #include "tribo_dev.h"
+#include "particle.h"
 
 namespace tf {
 
@@ -258,7 +259,7 @@ __device__ __forceinline__ long long wave_sum(long long v) {
 __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const double* __restrict__ q,
                                                  const int* __restrict__ blk_off, int blk0, int nmax,
                                                  const long long* __restrict__ q_in, long long q_shift,
-                                                 int do_stats) {
+                                                 const double* __restrict__ r_in, int do_stats) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
   double2* buf1 = lds + nmax;
@@ -283,7 +284,11 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const
   for (int t = threadIdx.x; t < nx; t += 64) tw[t] = C.tw[E.fx.tw_off + t];
   bool ovf = false;
   long long rq48 = 0, rq32 = 0;
-  for (int i = threadIdx.x; i < nx; i += 64) {
+  if (r_in) {
+    const double iv = 1.0 / C.vol[E.y_off + j];
+    for (int i = threadIdx.x; i < nx; i += 64) buf0[i] = make_double2(r_in[c0 + i] * iv, 0.0);
+  }
+  for (int i = threadIdx.x; i < nx && !r_in; i += 64) {
     long long Q = 0;
     if (q_in) {
       Q = q_in[c0 + i - q_shift];
@@ -609,17 +614,6 @@ __global__ __launch_bounds__(64) void k_ifftx(Ctx C, Ens Eone, int one, const in
 // ---------------------------------------------------------------------------
 // particle helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int clamp_floor(double v, int n) {
-  const double f = floor(v);
-  return (f >= 0.0) ? (f < (double)(n - 1) ? (int)f : n - 1) : 0;
-}
-
-// largest j in [0, ny-1] with yf[j] <= y (0 if none), searched from a guess
-__device__ __forceinline__ int y_cell_from(const double* __restrict__ yf, int ny, double y, int j) {
-  while (j > 0 && y < yf[j]) --j;
-  while (j < ny - 1 && y >= yf[j + 1]) ++j;
-  return j;
-}
 
 // largest j in [0, ny-1] with yf[j] <= y (0 if none), binary search
 __device__ __forceinline__ int y_cell(const double* __restrict__ yf, int ny, double y) {
@@ -651,96 +645,16 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
 // that share an ensemble (scalar descriptor loads)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
-                                         int p, int c) {
+                                         int p, int c, signed char* __restrict__ wall_rec) {
+  Fwd F;
+  eval_particle(C, E, in, s, p, c, F);
   const int nx = E.nx, ny = E.ny, nz = E.nz;
-  const int cl = c - (int)E.c_off;
-  int jk, i, j, k;
-  divmod(cl, nx, E.inv_nx, &jk, &i);
-  divmod(jk, nz, E.inv_nz, &j, &k);
+  const int j = F.j;
+  const double q = F.q, d = F.d;
+  const double v1x = F.v1[0], v1y = F.v1[1], v1z = F.v1[2];
+  double x1 = F.x1, z1 = F.z1;
+  const double y1 = F.y1;
   const double* __restrict__ yf = C.yf + E.y_off;
-  const double* __restrict__ idy = C.idy + E.y_off;
-
-  const double x = in.x[p], y = in.y[p], z = in.z[p];
-  const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
-  const double q = in.q[p], d = in.d[p];
-
-  // carrier velocity: trilinear in the cell, linear in physical y
-  const int i1 = (i + 1 == nx) ? 0 : i + 1;
-  const int k1 = (k + 1 == nz) ? 0 : k + 1;
-  const double tx = (x - (double)i * E.dx) * E.inv_dx;
-  const double ty = (y - yf[j]) * idy[j];
-  const double tz = (z - (double)k * E.dz) * E.inv_dz;
-  const int nxz = nz * nx;
-  const int plane = (ny + 1) * nxz;
-  const int n00 = (j * nz + k) * nx, n01 = (j * nz + k1) * nx;
-  const int n10 = n00 + nxz, n11 = n01 + nxz;
-  double uc[3];
-#pragma unroll
-  for (int cc = 0; cc < 3; ++cc) {
-    const double* __restrict__ b = E.U + cc * plane;
-    const double c00 = b[n00 + i] * (1.0 - tx) + b[n00 + i1] * tx;
-    const double c01 = b[n01 + i] * (1.0 - tx) + b[n01 + i1] * tx;
-    const double c10 = b[n10 + i] * (1.0 - tx) + b[n10 + i1] * tx;
-    const double c11 = b[n11 + i] * (1.0 - tx) + b[n11 + i1] * tx;
-    const double c0 = c00 * (1.0 - tz) + c01 * tz;
-    const double c1 = c10 * (1.0 - tz) + c11 * tz;
-    uc[cc] = c0 * (1.0 - ty) + c1 * ty;
-  }
-
-  // Gauss part: cell-centred E = -grad(phi), Gauss-linear, phi = 0 on the walls
-  const double* __restrict__ ph = C.phi + E.c_off;
-  const int im = (i == 0) ? nx - 1 : i - 1;
-  const int km = (k == 0) ? nz - 1 : k - 1;
-  const double pc = ph[cl];
-  const double Ex = -(ph[n00 + i1] - ph[n00 + im]) * E.inv_2dx;
-  const double Ez = -(ph[n01 + i] - ph[(j * nz + km) * nx + i]) * E.inv_2dz;
-  double ftop = 0.0, fbot = 0.0;
-  if (j < ny - 1) {
-    const double pn = ph[n00 + nxz + i];
-    ftop = pc + C.beta[E.y_off + j + 1] * (pn - pc);
-  }
-  if (j > 0) {
-    const double pm = ph[n00 - nxz + i];
-    fbot = pm + C.beta[E.y_off + j] * (pc - pm);
-  }
-  const double Ey = -(ftop - fbot) * idy[j];
-
-  // near field: Coulomb's law with the other particles of the cell, ascending id
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-  {
-    const int a = C.start[c], b = C.start[c + 1];
-    for (int t = a; t < b; ++t) {
-      if (t == s) continue;
-      const int pj = C.perm[t];
-      const double rx = x - in.x[pj], ry = y - in.y[pj], rz = z - in.z[pj];
-      const double r2 = (rx * rx + ry * ry) + rz * rz;
-      if (r2 > 0.0) {
-        const double ri = rsqrt(r2);
-        const double w = in.q[pj] * (ri * ri * ri);
-        sx += w * rx;
-        sy += w * ry;
-        sz += w * rz;
-      }
-    }
-  }
-
-  // forces and semi-implicit Euler
-  const double d2 = d * d;
-  const double ke = (E.cel * q) / (d2 * d);
-  const double ax = E.gp0 + ke * (Ex + sx * kInv4Pi);
-  const double ay = E.gp1 + ke * (Ey + sy * kInv4Pi);
-  const double az = E.gp2 + ke * (Ez + sz * kInv4Pi);
-  const double dux = vx - uc[0], duy = vy - uc[1], duz = vz - uc[2];
-  const double re = sqrt((dux * dux + duy * duy) + duz * duz) * d;
-  const double phid = (re <= 1000.0) ? 1.0 + cbrt(re * re) * (1.0 / 6.0) : 0.424 * re * (1.0 / 24.0);
-  const double sdr = phid * (E.c18 / d2);  // phi_D / tau_p
-  const double iden = 1.0 / (1.0 + E.dt * sdr);
-  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) * iden;
-  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) * iden;
-  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) * iden;
-  double x1 = x + E.dt * v1x;
-  const double y1 = y + E.dt * v1y;
-  double z1 = z + E.dt * v1z;
 
   // wall impact: rebound with restitution e, condenser charge transfer
   const double r = 0.5 * d;
@@ -757,6 +671,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
     yr = top - E.e * (y1 - top);
   }
   long long* st = C.stats + E.st_off;
+  if (wall_rec) wall_rec[s] = (signed char)wall;
   if (wall >= 0) {
     vyr = -E.e * v1y;
     const double f = E.fe * pow(un, 0.8);
@@ -803,14 +718,14 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
 }
 
 __global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
-                                                 int* __restrict__ perm_rec) {
+                                                 int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
   if (s >= C.n_tot) return;
   const int p = C.perm[s];
   if (perm_rec) perm_rec[s] = p;
   const int c = C.skey[s];
   if (one) {
-    push_one(C, Eone, in, out, s, p, c);
+    push_one(C, Eone, in, out, s, p, c, wall_rec);
     return;
   }
   const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
@@ -819,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PStat
   while (!done) {
     const int e = __builtin_amdgcn_readfirstlane(e_lane);
     if (e_lane == e) {
-      push_one(C, C.ens[e], in, out, s, p, c);
+      push_one(C, C.ens[e], in, out, s, p, c, wall_rec);
       done = true;
     }
   }
@@ -892,7 +807,7 @@ hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st) {
 
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
-                          int do_stats, hipStream_t st, hipEvent_t* ev) {
+                          int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in) {
   (void)key;
   auto mark = [&](int i) {
     if (ev) hipEventRecord(ev[i], st);
@@ -901,7 +816,8 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   const Ens Eone = G.eh[e0];
   const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
   const size_t lx = (size_t)3 * G.nx_max * sizeof(double2);
-  if (nb > 0) k_dep_fftx<<<nb, 64, lx, st>>>(C, Eone, one, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, do_stats);
+  if (nb > 0)
+    k_dep_fftx<<<nb, 64, lx, st>>>(C, Eone, one, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, r_in, do_stats);
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
   const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);
@@ -926,10 +842,10 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
 }
 
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
-                       hipStream_t st) {
+                       signed char* wall_rec, hipStream_t st) {
   const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
   const int one = (C.n_ens == 1) ? 1 : 0;
-  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec);
+  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
   return hipGetLastError();
 }
 

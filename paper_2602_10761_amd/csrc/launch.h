@@ -40,9 +40,9 @@ hipError_t launch_scan(const Ctx& C, hipStream_t st);
 hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st);
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
-                          int do_stats, hipStream_t st, hipEvent_t* ev = nullptr);
+                          int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr);
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
-                       hipStream_t st);
+                       signed char* wall_rec, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);
 hipError_t launch_put_state(const PState& S, const double* const* in8, long long p0, int n, hipStream_t st);
 hipError_t launch_get_state(const PState& S, double* const* out8, long long p0, int n, hipStream_t st);

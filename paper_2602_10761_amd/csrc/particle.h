@@ -1,0 +1,136 @@
+// Per-particle forward evaluation of the step, shared by the push and its
+// reverse-mode derivative (internal).  Everything up to the wall impact:
+// carrier velocity, cell-centred E, same-cell Coulomb sum, forces and the
+// semi-implicit Euler update.
+#pragma once
+#include "tribo_dev.h"
+
+namespace tf {
+
+__device__ __forceinline__ int clamp_floor(double v, int n) {
+  const double f = floor(v);
+  return (f >= 0.0) ? (f < (double)(n - 1) ? (int)f : n - 1) : 0;
+}
+
+// largest j in [0, ny-1] with yf[j] <= y (0 if none), searched from a guess
+__device__ __forceinline__ int y_cell_from(const double* __restrict__ yf, int ny, double y, int j) {
+  while (j > 0 && y < yf[j]) --j;
+  while (j < ny - 1 && y >= yf[j + 1]) ++j;
+  return j;
+}
+
+struct Fwd {
+  int i, j, k, i1, k1, n00, n01, n10, n11, plane;
+  double x, y, z, vx, vy, vz, q, d;
+  double tx, ty, tz;
+  double u[3], Ep[3], S[3];
+  double ke, a[3], du[3], re, phid, sdr, iden, v1[3];
+  double x1, y1, z1;  // after the update, before rebound and wrap
+};
+
+__device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
+                                              Fwd& F) {
+  const int nx = E.nx, ny = E.ny, nz = E.nz;
+  const int cl = c - (int)E.c_off;
+  int jk, i, j, k;
+  divmod(cl, nx, E.inv_nx, &jk, &i);
+  divmod(jk, nz, E.inv_nz, &j, &k);
+  const double* __restrict__ yf = C.yf + E.y_off;
+  const double* __restrict__ idy = C.idy + E.y_off;
+
+  const double x = in.x[p], y = in.y[p], z = in.z[p];
+  const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
+  const double q = in.q[p], d = in.d[p];
+
+  // carrier velocity: trilinear in the cell, linear in physical y
+  const int i1 = (i + 1 == nx) ? 0 : i + 1;
+  const int k1 = (k + 1 == nz) ? 0 : k + 1;
+  const double tx = (x - (double)i * E.dx) * E.inv_dx;
+  const double ty = (y - yf[j]) * idy[j];
+  const double tz = (z - (double)k * E.dz) * E.inv_dz;
+  const int nxz = nz * nx;
+  const int plane = (ny + 1) * nxz;
+  const int n00 = (j * nz + k) * nx, n01 = (j * nz + k1) * nx;
+  const int n10 = n00 + nxz, n11 = n01 + nxz;
+  double uc[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const double* __restrict__ b = E.U + cc * plane;
+    const double c00 = b[n00 + i] * (1.0 - tx) + b[n00 + i1] * tx;
+    const double c01 = b[n01 + i] * (1.0 - tx) + b[n01 + i1] * tx;
+    const double c10 = b[n10 + i] * (1.0 - tx) + b[n10 + i1] * tx;
+    const double c11 = b[n11 + i] * (1.0 - tx) + b[n11 + i1] * tx;
+    const double c0 = c00 * (1.0 - tz) + c01 * tz;
+    const double c1 = c10 * (1.0 - tz) + c11 * tz;
+    uc[cc] = c0 * (1.0 - ty) + c1 * ty;
+  }
+
+  // Gauss part: cell-centred E = -grad(phi), Gauss-linear, phi = 0 on the walls
+  const double* __restrict__ ph = C.phi + E.c_off;
+  const int im = (i == 0) ? nx - 1 : i - 1;
+  const int km = (k == 0) ? nz - 1 : k - 1;
+  const double pc = ph[cl];
+  const double Ex = -(ph[n00 + i1] - ph[n00 + im]) * E.inv_2dx;
+  const double Ez = -(ph[n01 + i] - ph[(j * nz + km) * nx + i]) * E.inv_2dz;
+  double ftop = 0.0, fbot = 0.0;
+  if (j < ny - 1) {
+    const double pn = ph[n00 + nxz + i];
+    ftop = pc + C.beta[E.y_off + j + 1] * (pn - pc);
+  }
+  if (j > 0) {
+    const double pm = ph[n00 - nxz + i];
+    fbot = pm + C.beta[E.y_off + j] * (pc - pm);
+  }
+  const double Ey = -(ftop - fbot) * idy[j];
+
+  // near field: Coulomb's law with the other particles of the cell, ascending id
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  {
+    const int a = C.start[c], b = C.start[c + 1];
+    for (int t = a; t < b; ++t) {
+      if (t == s) continue;
+      const int pj = C.perm[t];
+      const double rx = x - in.x[pj], ry = y - in.y[pj], rz = z - in.z[pj];
+      const double r2 = (rx * rx + ry * ry) + rz * rz;
+      if (r2 > 0.0) {
+        const double ri = rsqrt(r2);
+        const double w = in.q[pj] * (ri * ri * ri);
+        sx += w * rx;
+        sy += w * ry;
+        sz += w * rz;
+      }
+    }
+  }
+
+  // forces and semi-implicit Euler
+  const double d2 = d * d;
+  const double ke = (E.cel * q) / (d2 * d);
+  const double ax = E.gp0 + ke * (Ex + sx * kInv4Pi);
+  const double ay = E.gp1 + ke * (Ey + sy * kInv4Pi);
+  const double az = E.gp2 + ke * (Ez + sz * kInv4Pi);
+  const double dux = vx - uc[0], duy = vy - uc[1], duz = vz - uc[2];
+  const double re = sqrt((dux * dux + duy * duy) + duz * duz) * d;
+  const double phid = (re <= 1000.0) ? 1.0 + cbrt(re * re) * (1.0 / 6.0) : 0.424 * re * (1.0 / 24.0);
+  const double sdr = phid * (E.c18 / d2);  // phi_D / tau_p
+  const double iden = 1.0 / (1.0 + E.dt * sdr);
+  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) * iden;
+  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) * iden;
+  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) * iden;
+  const double x1 = x + E.dt * v1x;
+  const double y1 = y + E.dt * v1y;
+  const double z1 = z + E.dt * v1z;
+  F.i = i; F.j = j; F.k = k; F.i1 = i1; F.k1 = k1;
+  F.n00 = n00; F.n01 = n01; F.n10 = n10; F.n11 = n11; F.plane = plane;
+  F.x = x; F.y = y; F.z = z; F.vx = vx; F.vy = vy; F.vz = vz; F.q = q; F.d = d;
+  F.tx = tx; F.ty = ty; F.tz = tz;
+  F.u[0] = uc[0]; F.u[1] = uc[1]; F.u[2] = uc[2];
+  F.Ep[0] = Ex; F.Ep[1] = Ey; F.Ep[2] = Ez;
+  F.S[0] = sx; F.S[1] = sy; F.S[2] = sz;
+  F.ke = ke; F.a[0] = ax; F.a[1] = ay; F.a[2] = az;
+  F.du[0] = dux; F.du[1] = duy; F.du[2] = duz;
+  F.re = re; F.phid = phid; F.sdr = sdr; F.iden = iden;
+  F.v1[0] = v1x; F.v1[1] = v1y; F.v1[2] = v1z;
+  F.x1 = x1; F.y1 = y1; F.z1 = z1;
+}
+
+}  // namespace tf

@@ -38,6 +38,7 @@ struct Ens {
   double inv_nx, inv_nz;                    // 1/nx, 1/nz (index decomposition)
   double c18;                               // 18 / rr  (1/tau_p = c18 / d^2)
   double fe;                                // k_c (1 + e)^(2/5)
+  double pe;                                // (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
   FftPlan fx, fz;
 };
