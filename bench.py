@@ -1,13 +1,16 @@
 """Throughput of the particle step on one MI355X.
 
-python bench.py [--steps K] [--warmup W] [--config C] [--no-cpu]
+python bench.py [--steps K] [--warmup W] [--config C] [--no-cpu] [--no-batched] [--no-adjoint]
 
 One step = the whole per-step particle phase (sort, deposit, Poisson solve,
-push with wall charging) over one ensemble with inputs resident in HBM.
-Prints one JSON line.  The metric is particle-steps per second with the
-Poisson solve every step.
+push with wall charging) with inputs resident in HBM.  Prints one JSON line:
+the headline is particle-steps/s on the 10^6-particle 128^3 channel with the
+Poisson solve every step; it also carries the batched-vs-plain time on 64
+independent ensembles, the adjoint/forward time ratio, the roofline of the
+dominant kernel and the CPU oracle baseline.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +27,9 @@ WORKLOAD_NAME = {
     2: "Re_tau=180 channel 128^3 (tanh y, 2.0), 1e6 particles d+ in {0.25,0.5,1}, rho_p/rho=1000, dt+=0.1",
     3: "Re_tau=550 channel 192x160x192 (tanh y, 2.0), 4e6 particles d+ in {0.5,1,2}, dt+=0.05",
 }
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_config2.txt")
+KERNEL_SOURCES = ["paper_2602_10761_amd/csrc/kernels.hip", "paper_2602_10761_amd/csrc/particle.h",
+                  "paper_2602_10761_amd/csrc/tribo_dev.h"]
 
 
 def algorithmic_bytes(phase, n_p, nx, ny, nz):
@@ -47,8 +53,31 @@ def algorithmic_bytes(phase, n_p, nx, ny, nz):
     }[phase]
 
 
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
+    was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    v = kv.get(f"{kernel}_bytes")
+    return float(v) if v else None
+
+
 def cpu_baseline(ens, n_steps):
-    import numpy as np  # noqa: F401
     import oracle as O
 
     g = O.Geo.from_mesh(ens.mesh)
@@ -61,14 +90,81 @@ def cpu_baseline(ens, n_steps):
     return ens.n * n_steps / dt, dt
 
 
+def timed_steps(torch, sim, k):
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    sim.synchronize()
+    ev0.record(sim.stream)
+    sim.step(k)
+    ev1.record(sim.stream)
+    sim.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def batched_vs_plain(torch, W, R, autotune, steps, log):
+    ens = W.make_workload(4)
+    n_tot = sum(E.n for E in ens)
+    autotune.ensure_tuned(autotune.meshes_of(ens))
+    log(f"batched: {len(ens)} ensembles, {n_tot} particles")
+    sim = R.TriboSim(ens, graphs=True)
+    sim.step(3)
+    ms_b = timed_steps(torch, sim, steps) / steps
+    sim.close()
+    del sim
+    ms_p = 0.0
+    for E in ens:
+        s1 = R.TriboSim([E], graphs=True)
+        s1.step(3)
+        ms_p += timed_steps(torch, s1, steps) / steps
+        s1.close()
+    return {"workload": "64 ensembles: N_p log-uniform in [1e4, 1e6], Re_tau in {180, 300, 395, 550} "
+                        "with meshes 64^3..160^3, d+ uniform in [0.25, 2]",
+            "n_particles": n_tot, "ms_per_step_batched": ms_b, "ms_per_step_plain_sum": ms_p,
+            "speedup_batched_vs_plain": ms_p / ms_b,
+            "particle_steps_per_s_batched": n_tot / (ms_b * 1e-3)}
+
+
+def adjoint_ratio(torch, W, R, autotune, seg, log):
+    ens = W.make_workload(5, v_jitter=3.0, precharge=0.02)[0]
+    autotune.ensure_tuned(autotune.meshes_of([ens]))
+    sim = R.TriboSim([ens], traj_steps=seg)
+    sim.step(3)
+    ms_fwd = timed_steps(torch, sim, seg)
+    init = sim.state(0)
+    sim.set_state(0, init)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    lam = [{k: torch.zeros(ens.n, dtype=torch.float64, device=sim.dev) for k in R.KEYS}]
+    lam[0]["q"].fill_(1.0 / ens.n)
+    import numpy as np
+    sim.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(seg, record=True)
+    sim.adjoint(lam, np.zeros((1, 2)))
+    ev1.record(sim.stream)
+    sim.synchronize()
+    ms_bwd = ev0.elapsed_time(ev1)
+    wall_bwd = (time.perf_counter() - t0) * 1e3
+    sim.close()
+    log(f"adjoint: fwd {ms_fwd:.2f} ms, record+reverse {ms_bwd:.2f} ms per {seg} steps")
+    return {"workload": "Re_tau=180 channel 64^3, 1e5 particles d+=0.5, segments of %d steps" % seg,
+            "ms_forward_segment": ms_fwd, "ms_record_plus_adjoint_segment": ms_bwd,
+            "adjoint_over_forward": ms_bwd / ms_fwd, "wall_ms_record_plus_adjoint": wall_bwd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -77,38 +173,44 @@ def main():
 
     import torch
 
+    from paper_2602_10761_amd import autotune
+    from paper_2602_10761_amd import runtime as R
     from paper_2602_10761_amd import workload as W
-    from paper_2602_10761_amd.runtime import TriboSim
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
 
     ens = W.make_workload(args.config)[0]
     m = ens.mesh
-    print(f"# workload config {args.config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}", file=sys.stderr,
-          flush=True)
-    sim = TriboSim([ens], device="cuda:0")
+    log(f"workload config {args.config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
+    tuned = autotune.ensure_tuned(autotune.meshes_of([ens]))
+    log(f"tiles: {tuned}")
+    sim = R.TriboSim([ens], device="cuda:0", graphs=args.graphs)
     sim.step(args.warmup)
     sim.synchronize()
     torch.cuda.synchronize()
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    sim.profile_begin(args.steps)
+    if not args.graphs:
+        sim.profile_begin(args.steps)
     ev0.record(sim.stream)
     sim.step(args.steps)
     ev1.record(sim.stream)
     sim.synchronize()
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
-    phase_ms, nprof = sim.profile_end()
+    per_launch = None
+    if not args.graphs:
+        phase_ms, nprof = sim.profile_end()
+        per_launch = {k: v / nprof for k, v in phase_ms.items()}
     st = sim.stats(0)
     sim.close()
+    del sim
+    log(f"timed {args.steps} steps: {total_ms / args.steps * 1e3:.1f} us/step")
 
     ms_step = total_ms / args.steps
     value = ens.n * args.steps / (total_ms * 1e-3)
-    per_launch = {k: v / nprof for k, v in phase_ms.items()}
-    dom = max(per_launch, key=per_launch.get)
-    ab = algorithmic_bytes(dom, ens.n, m.nx, m.ny, m.nz)
-    achieved = ab / (per_launch[dom] * 1e-3) / 1e9
-    step_bytes = sum(algorithmic_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_launch)
     out = {
         "metric": METRIC,
         "value": value,
@@ -124,18 +226,30 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAME[args.config], "n_particles": ens.n,
                    "mesh": [m.nx, m.ny, m.nz], "poisson_every": 1},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "phase_us": {k: 1e3 * v for k, v in per_launch.items()},
-        "step_algorithmic_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
-        "impacts": [int(v) for v in st["impacts"]],
-        "flags": int(st["flags"]),
     }
+    if per_launch:
+        dom = max(per_launch, key=per_launch.get)
+        ab = algorithmic_bytes(dom, ens.n, m.nx, m.ny, m.nz)
+        achieved = ab / (per_launch[dom] * 1e-3) / 1e9
+        tr = measured_traffic(dom) if args.config == 2 else None
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": None if tr is None else tr / (per_launch[dom] * 1e-3) / 1e9,
+                           "algorithmic_bytes_per_launch": ab, "avg_launch_us": 1e3 * per_launch[dom]}
+        out["phase_us"] = {k: 1e3 * v for k, v in per_launch.items()}
+        step_bytes = sum(algorithmic_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_launch)
+        out["step_algorithmic_GBs"] = step_bytes / (ms_step * 1e-3) / 1e9
+    out["impacts"] = [int(v) for v in st["impacts"]]
+    out["flags"] = int(st["flags"])
+    if not args.no_batched:
+        out["batched"] = batched_vs_plain(torch, W, R, autotune, args.batched_steps, log)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(torch, W, R, autotune, 50, log)
     if not args.no_cpu:
         v, secs = cpu_baseline(ens, args.cpu_steps)
         out["cpu_baseline"] = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {args.cpu_steps} steps of the same workload "
-                                         f"({secs:.1f} s, numpy single thread)"}
+                                         f"({secs:.1f} s, numpy, one thread)"}
     print(json.dumps(out), flush=True)
 
 

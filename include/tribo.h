@@ -203,7 +203,7 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
 /*
  * Tile shapes of the Poisson kernels, used by every later tf_init /
  * tf_workspace_size of the calling process (0 = built-in choice):
- *   fx_rows    (j, k) rows per block of the x transforms (1..256)
+ *   fx_rows    unused (the x transforms take one wavefront per (j, k) row)
  *   fz_cols    spectral columns per block of the z transforms (1..64)
  *   tri_modes  Fourier modes per block of the tridiagonal solves (1..64)
  * Values whose LDS need exceeds 64 KiB per block are rejected at tf_init.
@@ -213,6 +213,12 @@ typedef struct {
   int32_t fx_rows, fz_cols, tri_modes, reserved;
 } tf_tuning;
 int tf_set_tuning(const tf_tuning* t);
+
+/* Tile shapes for the ensembles of one mesh-size class (nx, ny, nz); they take
+ * precedence over tf_set_tuning for those ensembles (t == NULL removes the
+ * entry).  Ensembles of different classes in one handle keep their own tiles
+ * within the same launches. */
+int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t);
 
 void tf_destroy(tf_handle* h);
 const char* tf_error_string(int code);

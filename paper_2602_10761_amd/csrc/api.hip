@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,7 @@ namespace {
 
 thread_local std::string g_err;
 tf_tuning g_tune = {0, 0, 0, 0};
+std::map<std::tuple<int, int, int>, tf_tuning> g_class_tune;  // per (nx, ny, nz)
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -51,7 +53,8 @@ bool radix_plan(int n, FftPlan* P) {
 struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
-  int nx_max = 0, nz_max = 0, ny_max = 0, rpb = 1, wz = 8, tri_m = 16, tri_pcr = 1;
+  int nx_max = 0, nz_max = 0, ny_max = 0, rpb = 1, wz = 8, tri_m = 16, tri_pcr = 1, tri_eq_max = 0;
+  std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
   std::vector<int> fx_blk, fz_blk, tri_blk;
   std::map<int, int> tw_off;
 };
@@ -102,25 +105,44 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   }
   if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
   S->rpb = 1;  // x transforms: one wave per (j, k) row
-  S->wz = g_tune.fz_cols > 0 ? g_tune.fz_cols : 2;
-  // tridiagonal: cyclic reduction holds tri_m * ny equations (5 doubles each,
-  // at most 8 per thread); Thomas (ny > 256) holds tri_m columns (32 B per row)
+  // tridiagonal: cyclic reduction holds tm * ny equations (5 doubles each, at
+  // most 8 per thread); Thomas (some ny > 256) holds tm columns (32 B per row)
   S->tri_pcr = S->ny_max <= 256 ? 1 : 0;
-  if (S->tri_pcr)
-    S->tri_m = g_tune.tri_modes > 0 ? g_tune.tri_modes : std::max(1, 1024 / S->ny_max);
-  else
-    S->tri_m = g_tune.tri_modes > 0 ? g_tune.tri_modes : std::max(1, std::min(16, 65536 / (32 * S->ny_max)));
+  S->e_wz.assign(n_ens, 2);
+  S->e_tm.assign(n_ens, 1);
+  S->wz = 1;
+  S->tri_eq_max = 0;
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_ensemble& E = ens[e];
+    tf_tuning t = g_tune;
+    auto it = g_class_tune.find(std::make_tuple(E.nx, E.ny, E.nz));
+    if (it != g_class_tune.end()) {
+      if (it->second.fz_cols > 0) t.fz_cols = it->second.fz_cols;
+      if (it->second.tri_modes > 0) t.tri_modes = it->second.tri_modes;
+    }
+    const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
+    int tm;
+    if (S->tri_pcr)
+      tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, 1024 / E.ny);
+    else
+      tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, std::min(16, 65536 / (32 * E.ny)));
+    if (S->tri_pcr && tm * E.ny > 8 * kBlock) return fail(TF_ESIZE, "tri_modes * ny exceeds 2048");
+    S->e_wz[e] = wz;
+    S->e_tm[e] = tm;
+    S->wz = std::max(S->wz, wz);
+    S->tri_eq_max = std::max(S->tri_eq_max, S->tri_pcr ? tm * (E.ny + 1) : tm * E.ny);
+  }
+  S->tri_m = 0;
   const size_t lds_fx = (size_t)3 * S->nx_max * 16;
   const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
-  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * (S->ny_max + 1) * S->tri_m : (size_t)S->ny_max * S->tri_m * 32;
+  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * S->tri_eq_max : (size_t)S->tri_eq_max * 32;
   if (lds_fx > 65536 || lds_fz > 65536 || lds_tri > 65536) return fail(TF_ESIZE, "tile shapes exceed 64 KiB of LDS");
-  if (S->tri_pcr && S->tri_m * S->ny_max > 8 * kBlock) return fail(TF_ESIZE, "tri_modes * ny exceeds 2048");
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
     S->fx_blk[e + 1] = S->fx_blk[e] + (rows + S->rpb - 1) / S->rpb;
-    S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->wz - 1) / S->wz);
-    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + S->tri_m - 1) / S->tri_m;
+    S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->e_wz[e] - 1) / S->e_wz[e]);
+    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + S->e_tm[e] - 1) / S->e_tm[e];
   }
   return TF_OK;
 }
@@ -322,6 +344,19 @@ int tf_set_tuning(const tf_tuning* t) {
   return TF_OK;
 }
 
+int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(TF_EINVAL, "mesh sizes must be positive");
+  const auto key = std::make_tuple(nx, ny, nz);
+  if (!t) {
+    g_class_tune.erase(key);
+    return TF_OK;
+  }
+  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 64)
+    return fail(TF_EINVAL, "tuning value out of range");
+  g_class_tune[key] = *t;
+  return TF_OK;
+}
+
 size_t tf_workspace_size(const tf_ensemble* ens, int32_t n_ens, int32_t traj_steps) {
   Sizes S;
   if (check_config(ens, n_ens, &S) != TF_OK || traj_steps < 0) return 0;
@@ -387,6 +422,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.kx_off = kx_off;
     E.kz_off = kz_off;
     E.st_off = st_off;
+    E.wz = S.e_wz[e];
+    E.tm = S.e_tm[e];
     E.lx = T.lx;
     E.lz = T.lz;
     E.ly = T.y_faces[T.ny];
@@ -493,6 +530,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.ny_max = S.ny_max;
   h->G.tri_m = S.tri_m;
   h->G.tri_pcr = S.tri_pcr;
+  h->G.tri_eq_max = S.tri_eq_max;
   h->G.fx_blk = h->S.fx_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
   h->G.tri_blk = h->S.tri_blk.data();

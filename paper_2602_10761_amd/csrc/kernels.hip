@@ -330,11 +330,11 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const
 // ---------------------------------------------------------------------------
 template <bool INV>
 __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
-                                             int wz, int nmax) {
+                                             int wmax, int nmax) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
-  double2* buf1 = lds + wz * (nmax + 1);
-  double2* tw = lds + 2 * wz * (nmax + 1);
+  double2* buf1 = lds + wmax * (nmax + 1);
+  double2* tw = lds + 2 * wmax * (nmax + 1);
   Ens E;
   int lb;
   if (one) {
@@ -347,6 +347,7 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int
     lb = gb - blk_off[e];
   }
   const int nz = E.nz, nh = E.nh, nhp = E.nhp;
+  const int wz = E.wz;
   const int pitch = nz + 1;  // odd pitch (in 16-byte units): no bank conflicts in the transposes
   const int nchunk = (nh + wz - 1) / wz;
     const int j = fdiv32(lb, magic32(nchunk), nchunk);
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int
 // Thomas sweeps in LDS; coalesced stores.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
-                                                       int blk0, int tm) {
+                                                       int blk0, int tmax) {
   extern __shared__ double2 lds[];
   Ens E;
   int lb;
@@ -393,6 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, Ens Eone, int one,
     lb = gb - blk_off[e];
   }
   const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  const int tm = E.tm;
   const int nm = nh * nz;
   const int mode0 = lb * tm;
   const int w = min(tm, nm - mode0);
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, Ens Eone, int one,
 constexpr int kPcrEq = 8;  // equations per thread
 
 __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
-                                                    int blk0, int tm) {
+                                                    int blk0, int tmax) {
   extern __shared__ double ldsd[];
   Ens E;
   int lb;
@@ -472,17 +474,20 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, Ens Eone, int one, co
     lb = gb - blk_off[e];
   }
   const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  const int tm = E.tm;
   const int nm = nh * nz;
   const int mode0 = lb * tm;
   const int w = min(tm, nm - mode0);
   const int neq = w * ny;
   const int nyp = ny + 1;        // padded mode stride: no LDS bank conflicts
-  const int cap = tm * nyp;
+  const int cap = tmax * (E.ny + 1);
+  (void)cap;
+  const int cap2 = tm * nyp;
   double* A = ldsd;
-  double* B = A + cap;
-  double* Cc = B + cap;
-  double* Dr = Cc + cap;
-  double* Di = Dr + cap;
+  double* B = A + cap2;
+  double* Cc = B + cap2;
+  double* Dr = Cc + cap2;
+  double* Di = Dr + cap2;
   const double* __restrict__ am = C.am + E.y_off;
   const double* __restrict__ ap = C.ap + E.y_off;
   const long long pitch = (long long)nz * nhp;
@@ -820,16 +825,16 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
     k_dep_fftx<<<nb, 64, lx, st>>>(C, Eone, one, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, r_in, do_stats);
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
-  const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);
+  const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);  // wz: largest over ensembles
   if (nzb > 0) k_fftz<false><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
     if (G.tri_pcr) {
-      const size_t tl = (size_t)5 * (G.ny_max + 1) * G.tri_m * sizeof(double);
+      const size_t tl = (size_t)5 * G.tri_eq_max * sizeof(double);  // largest tm * (ny + 1)
       k_tri_pcr<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
     } else {
-      const size_t tl = (size_t)G.ny_max * G.tri_m * (sizeof(double2) + 2 * sizeof(double));
+      const size_t tl = (size_t)G.tri_eq_max * (sizeof(double2) + 2 * sizeof(double));
       k_tri_thomas<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
     }
   }

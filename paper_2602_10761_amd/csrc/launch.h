@@ -27,6 +27,7 @@ struct LaunchGeo {
   int ny_max;
   int tri_m;       // Fourier modes per block in the tridiagonal solves
   int tri_pcr;     // 1: cyclic reduction, 0: Thomas
+  int tri_eq_max;  // largest tm * (ny + 1) over the ensembles (LDS sizing)
   const int* fx_blk;
   const int* fz_blk;
   const int* tri_blk;

@@ -31,6 +31,7 @@ struct Ens {
   int y_off;         // first entry in the per-y tables (ny+1 reserved)
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
+  int wz, tm;        // tile shapes: z-transform columns, tridiagonal modes per block
   double lx, ly, lz, dx, dz;
   double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
   // derived on the host

@@ -75,6 +75,7 @@ def lib():
         L.tf_profile_begin.argtypes = [c_void_p, c_int32]
         L.tf_profile_end.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
         L.tf_set_tuning.argtypes = [POINTER(TfTuning)]
+        L.tf_set_tuning_class.argtypes = [c_int32, c_int32, c_int32, POINTER(TfTuning)]
         L.tf_destroy.argtypes = [c_void_p]
         L.tf_destroy.restype = None
         L.tf_error_string.restype = ctypes.c_char_p
@@ -92,6 +93,12 @@ def set_tuning(fx_rows: int = 0, fz_cols: int = 0, tri_modes: int = 0):
     """Tile shapes for every later TriboSim of this process (0 = built-in choice)."""
     t = TfTuning(fx_rows, fz_cols, tri_modes, 0)
     _check(lib().tf_set_tuning(ctypes.byref(t)))
+
+
+def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0):
+    """Tile shapes for ensembles of mesh size (nx, ny, nz) in later TriboSims."""
+    t = TfTuning(0, fz_cols, tri_modes, 0)
+    _check(lib().tf_set_tuning_class(nx, ny, nz, ctypes.byref(t)))
 
 
 def _check(rc: int):
