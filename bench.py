@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -180,6 +182,12 @@ def main():
     def log(msg):
         print("# " + msg, file=sys.stderr, flush=True)
 
+    if args.calibrate_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ens = W.make_workload(args.config)[0]
     m = ens.mesh
     log(f"workload config {args.config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
