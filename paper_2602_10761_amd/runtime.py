@@ -57,6 +57,9 @@ _LIB = None
 def lib():
     global _LIB
     if _LIB is None:
+        # torch first: the library then binds to the HIP runtime torch already loaded,
+        # so both share one device context
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built (python -m paper_2602_10761_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
