@@ -218,6 +218,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.tw = cv.take<double2>(S.tw_tot);
   C.stats = cv.take<long long>(S.st_tot);
   C.rowq = cv.take<long long>(S.rows);
+  C.rowacc = cv.take<longlong2>(S.rows);
   PState A = carve_state(cv, S.n_tot);
   PState B = carve_state(cv, S.n_tot);
   C.count = cv.take<int>(S.c_tot);
@@ -509,6 +510,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
 #undef UP
   if (he == hipSuccess) he = hipMemsetAsync(h->C.stats, 0, sizeof(long long) * S.st_tot, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.rowacc, 0, sizeof(longlong2) * S.rows, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.count, 0, sizeof(int) * S.c_tot, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.phi, 0, sizeof(double) * S.c_tot, h->stream);
   for (int e = 0; e < n_ens && he == hipSuccess; ++e) {
@@ -618,9 +620,11 @@ int tf_stats(tf_handle* h, int32_t e, tf_stats_out* out) {
   if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
   const Ens& E = h->eh[e];
   std::vector<long long> st(stats_len(E.ny)), rq((size_t)E.ny * E.nz);
+  std::vector<longlong2> ra((size_t)E.ny * E.nz);
   HIPCHK(hipStreamSynchronize(h->stream));
   HIPCHK(hipMemcpy(st.data(), h->C.stats + E.st_off, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(rq.data(), h->C.rowq + E.row_off, rq.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ra.data(), h->C.rowacc + E.row_off, ra.size() * sizeof(longlong2), hipMemcpyDeviceToHost));
   out->steps = st[ST_STEPS];
   out->flags = (int32_t)st[ST_FLAGS];
   out->ny = E.ny;
@@ -631,11 +635,16 @@ int tf_stats(tf_handle* h, int32_t e, tf_stats_out* out) {
   for (int b = 0; b < kNbin; ++b) out->un_hist[b] = st[ST_HIST + b];
   __int128 tot = 0;
   for (int j = 0; j < E.ny; ++j) {
-    long long qj = 0;
-    for (int k = 0; k < E.nz; ++k) qj += rq[(size_t)j * E.nz + k];
+    long long qj = 0, cj = 0, q32 = 0;
+    for (int k = 0; k < E.nz; ++k) {
+      const size_t r = (size_t)j * E.nz + k;
+      qj += rq[r];
+      cj += ra[r].x;
+      q32 += ra[r].y;
+    }
     tot += qj;
-    if (out->crel_y) out->crel_y[j] = st[ST_Y + j];
-    if (out->qcum_y) out->qcum_y[j] = st[ST_Y + E.ny + j];
+    if (out->crel_y) out->crel_y[j] = cj;
+    if (out->qcum_y) out->qcum_y[j] = q32;
     if (out->qnow_y) out->qnow_y[j] = qj;
   }
   out->q_sum = (double)(long double)tot * (1.0 / 281474976710656.0);

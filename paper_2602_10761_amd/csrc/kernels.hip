@@ -288,32 +288,44 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const
     const double iv = 1.0 / C.vol[E.y_off + j];
     for (int i = threadIdx.x; i < nx; i += 64) buf0[i] = make_double2(r_in[c0 + i] * iv, 0.0);
   }
-  for (int i = threadIdx.x; i < nx && !r_in; i += 64) {
-    long long Q = 0;
-    if (q_in) {
-      Q = q_in[c0 + i - q_shift];
-    } else {
-      const int a = C.start[c0 + i], b = C.start[c0 + i + 1];
-      long long Q32 = 0;
-      for (int s = a; s < b; ++s) {
-        const double qv = C.sq[s];
-        Q += fixed_round(qv, kFixDep, &ovf);
-        Q32 += fixed_round(qv, kFixQcum, &ovf);
-      }
-      if (C.qdep) C.qdep[c0 + i] = Q;
-      rq32 += Q32;
+  int cnt = 0;
+  if (q_in) {
+    for (int i = threadIdx.x; i < nx; i += 64) {
+      const long long Q = q_in[c0 + i - q_shift];
+      rq48 += Q;
+      buf0[i] = make_double2((double)Q * rsc, 0.0);
     }
-    rq48 += Q;
-    buf0[i] = make_double2((double)Q * rsc, 0.0);
+  } else if (!r_in) {
+    // particle-parallel over the row's sorted slots [start[c0], start[c0 + nx]):
+    // coalesced charge/key loads, per-cell integer sums in LDS (order-free, exact)
+    long long* bins = reinterpret_cast<long long*>(buf1);
+    for (int i = threadIdx.x; i < nx; i += 64) bins[i] = 0;
+    const int s0 = C.start[c0], s1 = C.start[c0 + nx];
+    cnt = s1 - s0;
+    __syncthreads();
+    for (int s = s0 + (int)threadIdx.x; s < s1; s += 64) {
+      const double qv = C.sq[s];
+      const unsigned i = (unsigned)(C.skey[s] - (int)c0);
+      const long long Q = fixed_round(qv, kFixDep, &ovf);
+      rq32 += fixed_round(qv, kFixQcum, &ovf);
+      if (i < (unsigned)nx) atomicAdd(reinterpret_cast<unsigned long long*>(&bins[i]), (unsigned long long)Q);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nx; i += 64) {
+      const long long Q = bins[i];
+      if (C.qdep) C.qdep[c0 + i] = Q;
+      rq48 += Q;
+      buf0[i] = make_double2((double)Q * rsc, 0.0);
+    }
   }
   if (do_stats) {
-    const int cnt = C.start[c0 + nx] - C.start[c0];
     rq48 = wave_sum(rq48);
     rq32 = wave_sum(rq32);
     if (threadIdx.x == 0) {
-      long long* st = C.stats + E.st_off;
-      atomicAdd((unsigned long long*)&st[ST_Y + j], (unsigned long long)cnt);
-      atomicAdd((unsigned long long*)&st[ST_Y + E.ny + j], (unsigned long long)rq32);
+      longlong2 acc = C.rowacc[E.row_off + jk];
+      acc.x += cnt;
+      acc.y += rq32;
+      C.rowacc[E.row_off + jk] = acc;
       C.rowq[E.row_off + jk] = rq48;
     }
   }

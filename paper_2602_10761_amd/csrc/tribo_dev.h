@@ -44,9 +44,11 @@ struct Ens {
   FftPlan fx, fz;
 };
 
-// statistics block (int64) of one ensemble: header, then crel_y[ny], qcum_y[ny]
-enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_Y = 6 + kNbin };
-inline int stats_len(int ny) { return ST_Y + 2 * ny; }
+// statistics block (int64) of one ensemble; the per-height sums live per (j,k)
+// row in Ctx::rowacc (each row owned by one deposit block: no atomics) and are
+// summed over k when read
+enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_END = 6 + kNbin };
+inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
 
@@ -77,6 +79,7 @@ struct Ctx {
   double* phi;               // [c_tot]   potential of the latest step
   long long* stats;          // statistics blocks
   long long* rowq;           // [sum ny*nz] sum rne(q 2^48) per (j,k) row, latest deposit
+  longlong2* rowacc;         // [sum ny*nz] (particle count, sum rne(q 2^32)) per row, summed over steps
   long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
