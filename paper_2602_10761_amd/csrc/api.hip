@@ -170,6 +170,7 @@ struct tf_handle {
   Ens* d_ens = nullptr;
   PState A{}, B{}, cur{};
   bool cur_is_A = true;
+  bool need_full = true;            // next sort from scratch (stored order is not a push's)
   int* d_fx = nullptr;
   int* d_fz = nullptr;
   int* d_tri = nullptr;
@@ -192,7 +193,6 @@ PState carve_state(Carver& cv, long long n) {
   for (auto* p : f) *p = cv.take<double>(n);
   s.id = cv.take<int>(n);
   s.key = cv.take<int>(n);
-  s.rank = cv.take<int>(n);
   return s;
 }
 
@@ -219,14 +219,24 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.stats = cv.take<long long>(S.st_tot);
   C.rowq = cv.take<long long>(S.rows);
   C.rowacc = cv.take<longlong2>(S.rows);
+  C.r_off = cv.take<long long>(n_ens + 1);
+  C.n_rows = S.rows;
+  C.row_cnt = cv.take<int>(S.rows);
+  C.rs_old = cv.take<int>(S.rows + 1);
+  C.rs_new = cv.take<int>(S.rows + 1);
+  C.far = cv.take<int>(S.n_tot);
+  C.far_n = cv.take<int>(2);
   PState A = carve_state(cv, S.n_tot);
   PState B = carve_state(cv, S.n_tot);
   C.count = cv.take<int>(S.c_tot);
   C.start = cv.take<int>(S.c_tot + 1);
-  C.tmp = cv.take<unsigned long long>(S.n_tot);
+  C.tmp = cv.take<int4>(S.n_tot);
   C.perm = cv.take<int>(S.n_tot);
   C.skey = cv.take<int>(S.n_tot);
   C.sq = cv.take<double>(S.n_tot);
+  C.sx = cv.take<double>(S.n_tot);
+  C.sy = cv.take<double>(S.n_tot);
+  C.sz = cv.take<double>(S.n_tot);
   const long long nbs = (S.c_tot + 4 * kBlock - 1) / (4 * kBlock);
   C.scan_part = cv.take<int>(nbs + 1);
   C.spec = cv.take<double2>(S.s_tot);
@@ -272,13 +282,12 @@ void destroy_graphs(tf_handle* h) {
   h->g_ab = h->g_ba = nullptr;
 }
 
-hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const TrajBuf* rec) {
+hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const TrajBuf* rec, bool full = false) {
   hipError_t e;
   hipEvent_t* ev = nullptr;
   if (h->prof_n < h->prof_cap) ev = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
   if (ev && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
-  if ((e = launch_scan(h->C, h->stream)) != hipSuccess) return e;
-  if ((e = launch_sort(h->C, in, h->stream)) != hipSuccess) return e;
+  if ((e = launch_sort(h->C, h->G, in, full, h->stream)) != hipSuccess) return e;
   if (rec) {
     if ((e = hipMemcpyAsync(rec->skey, h->C.skey, sizeof(int) * h->C.n_tot, hipMemcpyDeviceToDevice, h->stream)) !=
         hipSuccess)
@@ -406,6 +415,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->c_off.assign(n_ens + 1, 0);
   int y_off = 0, kx_off = 0, kz_off = 0, st_off = 0;
   long long s_off = 0, row_off = 0;
+  std::vector<long long> r_offs(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& T = ens[e];
     Ens& E = h->eh[e];
@@ -479,6 +489,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     h->c_off[e + 1] = h->c_off[e] + (long long)T.nx * T.ny * T.nz;
     s_off += (long long)ny * T.nz * E.nhp;
     row_off += (long long)ny * T.nz;
+    r_offs[e + 1] = row_off;
     y_off += ny + 1;
     kx_off += E.nh;
     kz_off += T.nz;
@@ -494,6 +505,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->C.ens, h->eh);
   UP(h->C.p_off, h->p_off);
   UP(h->C.c_off, h->c_off);
+  UP(h->C.r_off, r_offs);
   UP(h->d_fx, S.fx_blk);
   UP(h->d_fz, S.fz_blk);
   UP(h->d_tri, S.tri_blk);
@@ -512,6 +524,9 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowacc, 0, sizeof(longlong2) * S.rows, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.count, 0, sizeof(int) * S.c_tot, h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_old, 0, sizeof(int) * (S.rows + 1), h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_new, 0, sizeof(int) * (S.rows + 1), h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.far_n, 0, sizeof(int) * 2, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.phi, 0, sizeof(double) * S.c_tot, h->stream);
   for (int e = 0; e < n_ens && he == hipSuccess; ++e) {
     if (ens[e].n_particles == 0) continue;
@@ -551,7 +566,7 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   if (n_steps < 0) return fail(TF_EINVAL, "n_steps < 0");
   if (h->C.n_tot == 0) {
     for (int s = 0; s < n_steps; ++s) {
-      HIPCHK(launch_scan(h->C, h->stream));
+      HIPCHK(launch_sort(h->C, h->G, h->cur, false, h->stream));
       HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, h->cur.key, nullptr, 0, h->C.phi, 0, 1, h->stream));
       HIPCHK(launch_push(h->C, h->G, h->cur, other(h), nullptr, nullptr, h->stream));
     }
@@ -574,12 +589,12 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
           HIPCHK(hipMemcpyAsync(dst[f], src[f], n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(t.id, c.id, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(t.key, c.key, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(t.rank, c.rank, n * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         h->cur = t;
       }
       const PState in = h->cur;
       const PState out = h->traj[h->traj_len + 1].st;
-      HIPCHK(enqueue_step(h, in, out, &tb));
+      HIPCHK(enqueue_step(h, in, out, &tb, h->need_full));
+      h->need_full = false;
       h->cur = out;
       h->traj_len++;
     }
@@ -589,7 +604,8 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   const bool in_traj = !(h->cur.x == h->A.x || h->cur.x == h->B.x);
   int s = 0;
   if (in_traj && n_steps > 0) {
-    HIPCHK(enqueue_step(h, h->cur, h->A, nullptr));
+    HIPCHK(enqueue_step(h, h->cur, h->A, nullptr, h->need_full));
+    h->need_full = false;
     h->cur = h->A;
     h->cur_is_A = true;
     s = 1;
@@ -604,10 +620,12 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
     }
   }
   for (; s < n_steps; ++s) {
-    if (graphs) {
+    if (graphs && !h->need_full) {
       HIPCHK(hipGraphLaunch(h->cur_is_A ? h->g_ab : h->g_ba, h->stream));
     } else {
-      HIPCHK(enqueue_step(h, h->cur, other(h), nullptr));
+      // the graphs hold the incremental sort: a step after a state upload runs eagerly
+      HIPCHK(enqueue_step(h, h->cur, other(h), nullptr, h->need_full));
+      h->need_full = false;
     }
     h->cur = other(h);
     h->cur_is_A = !h->cur_is_A;
@@ -680,7 +698,6 @@ int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
     if (nt) {
       HIPCHK(hipMemcpyAsync(t.id, c.id, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
       HIPCHK(hipMemcpyAsync(t.key, c.key, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
-      HIPCHK(hipMemcpyAsync(t.rank, c.rank, nt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
     }
     h->cur = h->A;
     h->cur_is_A = true;
@@ -693,6 +710,7 @@ int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
   HIPCHK(hipMemsetAsync(h->C.count + h->c_off[e], 0, sizeof(int) * ncell, h->stream));
   HIPCHK(launch_put_state(h->cur, in8, h->p_off[e], n, h->stream));
   HIPCHK(launch_bin(h->C, h->cur, h->p_off[e], h->p_off[e] + n, h->stream));
+  h->need_full = true;
   return TF_OK;
 }
 

@@ -1,19 +1,22 @@
 // Forward-step kernels of libtribo.so (gfx950, FP64, wave64).
 //
 // Per step (launch order):
-//   scan_reduce / scan_part / scan_down   count -> start (exclusive prefix)
-//   assign                                unordered slot per particle in its cell run
-//   rank                                  order each cell run by particle id -> perm
-//   dep_fftx                              cell charge from the sorted runs (exact int64),
-//                                         rho = Q 2^-48 / V, forward FFT along x
-//   fftz<fwd>                             forward FFT along z
-//   tri                                   one tridiagonal y-solve per Fourier mode
-//   fftz<inv>, ifftx                      back to phi on the cells
-//   push                                  per particle: forces, integration, wall
-//                                         impact and charging, wrap, next cell key
+//   scan_reduce / [scan_part] / scan_down  count -> start (exclusive prefix)
+//   place                                  unordered slot per particle in its cell run
+//   rank                                   order each cell run by particle id -> perm,
+//                                          slot-ordered copies of charge and position
+//   dep_fftx                               cell charge from the sorted runs (exact int64),
+//                                          rho = Q 2^-48 / V, forward FFT along x
+//   fftz<fwd>                              forward FFT along z
+//   tri                                    one tridiagonal y-solve per Fourier mode
+//   fftz<inv>, ifftx                       back to phi on the cells
+//   push                                   per particle: forces, integration, wall
+//                                          impact and charging, wrap, next cell key
 //
 // Particle state is stored in the slot order of the previous step's sort; the
-// push gathers through perm (nearly coalesced) and writes in the new order.
+// push gathers velocity, diameter and id through perm (nearly coalesced) and
+// writes in the new order.  Device-scope atomics are kept out of contended
+// addresses: they are resolved beyond the per-XCD L2 and serialize there.
 #include "tribo_dev.h"
 #include "particle.h"
 
@@ -46,24 +49,54 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
   return off + incl - v;
 }
 
-constexpr int kScanChunk = 4 * kBlock;
+constexpr int kScanPer = 16;                   // counts per thread
+constexpr int kScanChunk = kScanPer * kBlock;  // counts per block
+constexpr int kScanFold = 4096;                // up to this many blocks, scan_down sums its own prefix
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ cnt, long long n,
+// n counts from cnt[base, base + kScanPer) (zero past n)
+__device__ __forceinline__ void scan_load(const int* __restrict__ cnt, long long base, long long n, int* v) {
+  if (base + kScanPer <= n) {
+    const int4* c4 = reinterpret_cast<const int4*>(cnt + base);
+#pragma unroll
+    for (int r = 0; r < kScanPer / 4; ++r) {
+      const int4 t = c4[r];
+      v[4 * r] = t.x;
+      v[4 * r + 1] = t.y;
+      v[4 * r + 2] = t.z;
+      v[4 * r + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) v[r] = (base + r < n) ? cnt[base + r] : 0;
+  }
+}
+
+// per-block totals of the counts; block 0 also counts the step of every
+// ensemble and hands the far list over (runs once per step, before placement)
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(Ctx C, const int* __restrict__ cnt, long long n,
                                                         int* __restrict__ part) {
-  const long long base = (long long)blockIdx.x * kScanChunk + 4LL * threadIdx.x;
+  if (blockIdx.x == 0) {
+    for (int e = threadIdx.x; e < C.n_ens; e += kBlock) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+    // the far list of the last push: snapshot for the placement, restart for the next push
+    if (threadIdx.x == 0) {
+      C.far_n[1] = C.far_n[0];
+      C.far_n[0] = 0;
+    }
+  }
+  const long long base = (long long)blockIdx.x * kScanChunk + (long long)kScanPer * threadIdx.x;
+  int v[kScanPer];
+  scan_load(cnt, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (base + r < n) s += cnt[base + r];
+  for (int r = 0; r < kScanPer; ++r) s += v[r];
   int tot;
   block_excl_scan<kBlock / 64>(s, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block of 1024 threads: exclusive scan of the block partials, total at
-// part[nb]; also counts the step of every ensemble (runs once per step)
-__global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int nb, Ctx C) {
-  for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+// single block of 1024 threads: exclusive scan of the block totals (only when
+// there are more than kScanFold blocks)
+__global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int nb) {
   int carry = 0;
   for (int base = 0; base < nb; base += 1024) {
     int i = base + threadIdx.x;
@@ -73,64 +106,455 @@ __global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int 
     if (i < nb) part[i] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) part[nb] = carry;
 }
 
-// writes start and clears the counts for the next step's arrivals
-__global__ __launch_bounds__(kBlock) void k_scan_down(int* __restrict__ cnt, long long n,
-                                                      const int* __restrict__ part, int nb,
+// writes start[0..n]; the block prefix is the sum of the preceding block totals
+// (fold) or the scanned total.  The placement then counts each cell back down
+// to zero.
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cnt, long long n,
+                                                      const int* __restrict__ part, int fold,
                                                       int* __restrict__ start) {
-  const long long base = (long long)blockIdx.x * kScanChunk + 4LL * threadIdx.x;
-  int v[4];
+  int pre;
+  if (fold) {
+    int acc = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kBlock) acc += part[i];
+    block_excl_scan<kBlock / 64>(acc, &pre);
+  } else {
+    pre = part[blockIdx.x];
+  }
+  const long long base = (long long)blockIdx.x * kScanChunk + (long long)kScanPer * threadIdx.x;
+  int v[kScanPer];
+  scan_load(cnt, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    v[r] = (base + r < n) ? cnt[base + r] : 0;
-    s += v[r];
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (base + r < n) cnt[base + r] = 0;
+  for (int r = 0; r < kScanPer; ++r) s += v[r];
   int tot;
-  int ex = block_excl_scan<kBlock / 64>(s, &tot) + part[blockIdx.x];
+  int ex = block_excl_scan<kBlock / 64>(s, &tot) + pre;
+  if (base + kScanPer <= n) {
+    int4* s4 = reinterpret_cast<int4*>(start + base);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (base + r < n) start[base + r] = ex;
-    ex += v[r];
+    for (int r = 0; r < kScanPer / 4; ++r) {
+      int4 t;
+      t.x = ex;
+      ex += v[4 * r];
+      t.y = ex;
+      ex += v[4 * r + 1];
+      t.z = ex;
+      ex += v[4 * r + 2];
+      t.w = ex;
+      ex += v[4 * r + 3];
+      s4[r] = t;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+      if (base + r < n) start[base + r] = ex;
+      ex += v[r];
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) start[n] = part[nb];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) start[n] = pre + tot;
 }
 
 // ---------------------------------------------------------------------------
-// counting sort by (cell, id)
+// counting sort by (cell, id); kIlp particles per thread keep several
+// independent memory chains in flight
 // ---------------------------------------------------------------------------
-// place each particle in its cell's run at its arrival rank (unordered within the run)
-__global__ __launch_bounds__(kBlock) void k_place(Ctx C, const int* __restrict__ key, const int* __restrict__ rank,
-                                                  const int* __restrict__ id) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= C.n_tot) return;
-  const int c = key[p];
-  const int a = C.start[c];
-  const int slot = a + rank[p];
-  if (slot < a || slot >= C.start[c + 1]) return;  // ranks inconsistent with counts: never by construction
-  C.tmp[slot] = ((unsigned long long)(unsigned)id[p] << 32) | (unsigned long long)(unsigned)p;
+constexpr int kIlp = 4;
+
+// place each particle in its cell's run (unordered within the run) as
+// (id, old slot, cell)
+__global__ __launch_bounds__(kBlock) void k_place(Ctx C, const int* __restrict__ key, const int* __restrict__ id) {
+  const long long p0 = (long long)blockIdx.x * (kBlock * kIlp) + threadIdx.x;
+  int c[kIlp], pid[kIlp];
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    const long long p = p0 + r * kBlock;
+    const bool ok = p < C.n_tot;
+    c[r] = ok ? key[p] : -1;
+    pid[r] = ok ? id[p] : 0;
+  }
+  int slot[kIlp], lo[kIlp], hi[kIlp];
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    if (c[r] >= 0) {
+      lo[r] = C.start[c[r]];
+      hi[r] = C.start[c[r] + 1];
+      // counting down the cell's arrivals leaves count[] zero for the next step
+      slot[r] = lo[r] + atomicSub(&C.count[c[r]], 1) - 1;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    // a slot outside the run means counts inconsistent with keys: never by construction
+    if (c[r] >= 0 && slot[r] >= lo[r] && slot[r] < hi[r])
+      C.tmp[slot[r]] = make_int4(pid[r], (int)(p0 + r * kBlock), c[r], 0);
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rank(Ctx C, const int* __restrict__ key, const double* __restrict__ q) {
-  const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (s >= C.n_tot) return;
-  const unsigned long long v = C.tmp[s];
-  const int p = (int)(v & 0xffffffffull);
-  const unsigned idv = (unsigned)(v >> 32);
-  if (p < 0 || p >= C.n_tot) return;
-  const int c = key[p];
-  const int a = C.start[c], b = C.start[c + 1];
-  int r = 0;
-  if (b - a > 1)
-    for (int t = a; t < b; ++t) r += ((unsigned)(C.tmp[t] >> 32) < idv) ? 1 : 0;
-  C.perm[a + r] = p;
-  C.skey[a + r] = c;
-  C.sq[a + r] = q[p];
+// order each run by id: the slot of a particle is its run start plus the
+// number of run members with a smaller id.  Writes perm, skey and the
+// slot-ordered copies of charge and position.
+__global__ __launch_bounds__(kBlock) void k_rank(Ctx C, PState in) {
+  const long long s0 = (long long)blockIdx.x * (kBlock * kIlp) + threadIdx.x;
+  int4 rec[kIlp];
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    const long long s = s0 + r * kBlock;
+    rec[r] = (s < C.n_tot) ? C.tmp[s] : make_int4(0, -1, 0, 0);
+  }
+  bool ok[kIlp];
+  int a[kIlp], b[kIlp];
+  double q[kIlp], x[kIlp], y[kIlp], z[kIlp];
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    const int p = rec[r].y, c = rec[r].z;
+    ok[r] = p >= 0 && p < C.n_tot && c >= 0 && c < C.c_tot;
+    if (ok[r]) {
+      a[r] = C.start[c];
+      b[r] = C.start[c + 1];
+      q[r] = in.q[p];
+      x[r] = in.x[p];
+      y[r] = in.y[p];
+      z[r] = in.z[p];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kIlp; ++r) {
+    if (!ok[r]) continue;
+    int rk = 0;
+    if (b[r] - a[r] > 1)
+      for (int t = a[r]; t < b[r]; ++t) rk += (C.tmp[t].x < rec[r].x) ? 1 : 0;
+    const int o = a[r] + rk;
+    C.perm[o] = rec[r].y;
+    C.skey[o] = rec[r].z;
+    C.sq[o] = q[r];
+    C.sx[o] = x[r];
+    C.sy[o] = y[r];
+    C.sz[o] = z[r];
+  }
+}
+
+// full sort (after init or a state upload): cell counts by atomics
+__global__ __launch_bounds__(kBlock) void k_count(Ctx C, const int* __restrict__ key) {
+  const long long p = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (p < C.n_tot) atomicAdd(&C.count[key[p]], 1);
+}
+
+// row slot ranges from the cell starts of a full sort
+__global__ __launch_bounds__(kBlock) void k_rows_from_start(Ctx C) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (r > C.n_rows) return;
+  if (r == C.n_rows) {
+    C.rs_new[r] = (int)C.n_tot;
+    return;
+  }
+  const int e = find_off(C.r_off, C.n_ens + 1, r);
+  const Ens& E = C.ens[e];
+  C.rs_new[r] = C.start[E.c_off + (r - C.r_off[e]) * E.nx];
+}
+
+// ---------------------------------------------------------------------------
+// incremental sort, one wave per (j, k) row of the new order.  Candidates are
+// the slots of rows (j + dj, k + dk), |dj|, |dk| <= 1 (k periodic), in the
+// stored order -- at most 6 contiguous slot ranges -- plus the far list.
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerBlock = kBlock / 64;
+
+struct RowSegs {
+  int a[6], off[7];  // segment u: slots [a[u], a[u] + off[u+1] - off[u])
+};
+
+// two segments per dj (the second one empty unless k is on the periodic seam);
+// all indices static so the segments stay in registers
+__device__ __forceinline__ void row_segments(const int* __restrict__ rs, long long rb, int ny, int nz, int j, int k,
+                                             RowSegs& S) {
+  S.off[0] = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int j2 = j + d - 1;
+    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    if (j2 >= 0 && j2 < ny) {
+      const long long base = rb + (long long)j2 * nz;
+      long long s0, e0, s1 = 0, e1 = 0;  // rows [s0, e0) and [s1, e1)
+      if (k >= 1 && k <= nz - 2) {
+        s0 = base + k - 1;
+        e0 = base + k + 2;
+      } else if (k == 0) {
+        s0 = base;
+        e0 = base + 2;
+        s1 = base + nz - 1;
+        e1 = base + nz;
+      } else {
+        s0 = base + nz - 2;
+        e0 = base + nz;
+        s1 = base;
+        e1 = base + 1;
+      }
+      a0 = rs[s0];
+      b0 = rs[e0];
+      if (e1 > s1) {
+        a1 = rs[s1];
+        b1 = rs[e1];
+      }
+    }
+    S.a[2 * d] = a0;
+    S.off[2 * d + 1] = S.off[2 * d] + max(b0 - a0, 0);
+    S.a[2 * d + 1] = a1;
+    S.off[2 * d + 2] = S.off[2 * d + 1] + max(b1 - a1, 0);
+  }
+}
+
+// slot of flattened candidate t < S.off[6]
+__device__ __forceinline__ int seg_slot(const RowSegs& S, int t) {
+  int s = S.a[0] + t;
+#pragma unroll
+  for (int u = 1; u < 6; ++u)
+    if (t >= S.off[u]) s = S.a[u] + (t - S.off[u]);
+  return s;
+}
+
+struct RowId {
+  long long r, c0, rb;
+  int nx, ny, nz, j, k;
+  bool ok;
+};
+
+__device__ __forceinline__ RowId row_of(const Ctx& C, const Ens& Eone, int one, long long r) {
+  RowId R;
+  R.r = r;
+  R.ok = r < C.n_rows;
+  if (!R.ok) r = 0;
+  long long coff;
+  if (one) {
+    R.nx = Eone.nx;
+    R.ny = Eone.ny;
+    R.nz = Eone.nz;
+    R.rb = 0;
+    coff = 0;
+  } else {
+    const int e = find_off(C.r_off, C.n_ens + 1, r);
+    const Ens& E = C.ens[e];
+    R.nx = E.nx;
+    R.ny = E.ny;
+    R.nz = E.nz;
+    R.rb = C.r_off[e];
+    coff = E.c_off;
+  }
+  const int jk = (int)(r - R.rb);
+  R.j = jk / R.nz;
+  R.k = jk - R.j * R.nz;
+  R.c0 = coff + (long long)jk * R.nx;
+  return R;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Candidates in batches of kCand per lane so that their key loads are in
+// flight together; the far list is a seventh segment after the six ranges.
+constexpr int kCand = 8;
+
+// members of each new row
+__global__ __launch_bounds__(kBlock) void k_row_count(Ctx C, Ens Eone, int one, const int* __restrict__ key) {
+  const int lane = threadIdx.x & 63;
+  const RowId R = row_of(C, Eone, one, (long long)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6));
+  if (!R.ok) return;  // no block-wide synchronisation in this kernel
+  RowSegs S;
+  row_segments(C.rs_old, R.rb, R.ny, R.nz, R.j, R.k, S);
+  const long long c1 = R.c0 + R.nx;
+  const int T = S.off[6];
+  const int TT = T + min(C.far_n[0], (int)C.n_tot);
+  int cnt = 0;
+  for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
+    int sl[kCand], c[kCand];
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) {
+      const int t = t0 + 64 * u;
+      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+    }
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? key[sl[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) cnt += (c[u] >= R.c0 && c[u] < c1) ? 1 : 0;
+  }
+  cnt = wave_sum_i(cnt);
+  if (lane == 0) C.row_cnt[R.r] = cnt;
+}
+
+// LDS of one row in k_row_place: member list A {id, old slot} and its cells
+// (bytes), member indices ordered by cell, cell counts / starts / cursors
+__host__ __device__ inline size_t row_lds_bytes(int nx_max, int cap) {
+  return ((size_t)cap * 8 + (size_t)cap * 2 + (size_t)cap + (size_t)nx_max * 12 + 16 + 15) & ~(size_t)15;
+}
+
+// after the row scan (rs_new): one pass over the candidates collects the row's
+// members in LDS (cell counts by LDS atomics), a per-cell scan gives the cell
+// starts, the members are bucketed by cell and each ranked by id inside its
+// cell.  Rows with more than `cap` members take a second candidate pass and
+// rank through C.tmp instead.  Writes start, perm, skey and the slot-ordered
+// copies of charge and position.
+__global__ __launch_bounds__(kBlock) void k_row_place(Ctx C, Ens Eone, int one, PState in, int nx_max, int cap) {
+  extern __shared__ __align__(16) unsigned char lds_b[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned char* base = lds_b + (size_t)w * row_lds_bytes(nx_max, cap);
+  int2* A = reinterpret_cast<int2*>(base);
+  int* cnt = reinterpret_cast<int*>(base + (size_t)cap * 8);
+  int* pre = cnt + nx_max;
+  int* cur = pre + nx_max;
+  int* nmem = cur + nx_max;
+  unsigned short* Bm = reinterpret_cast<unsigned short*>(nmem + 4);
+  unsigned char* Ai = reinterpret_cast<unsigned char*>(Bm + cap);
+
+  const RowId R = row_of(C, Eone, one, (long long)blockIdx.x * kRowsPerBlock + w);
+  const int nx = R.nx;
+  RowSegs S;
+  const long long c1 = R.c0 + nx;
+  int r0 = 0, r1 = 0, T = 0, TT = 0;
+  if (R.ok) {
+    row_segments(C.rs_old, R.rb, R.ny, R.nz, R.j, R.k, S);
+    r0 = C.rs_new[R.r];
+    r1 = C.rs_new[R.r + 1];
+    T = S.off[6];
+    TT = T + min(C.far_n[1], (int)C.n_tot);
+    for (int i = lane; i < nx; i += 64) cnt[i] = 0;
+    if (lane == 0) *nmem = 0;
+  }
+  const int M = r1 - r0;
+  const bool fast = M <= cap;  // wave-uniform
+  __syncthreads();
+  // pass 1: cell counts; the fast path also lists the members
+  for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
+    int sl[kCand], c[kCand], idv[kCand];
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) {
+      const int t = t0 + 64 * u;
+      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+    }
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= R.c0 && c[u] < c1) ? in.id[sl[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) {
+      if (c[u] >= R.c0 && c[u] < c1) {
+        const int i = c[u] - (int)R.c0;
+        atomicAdd(&cnt[i], 1);
+        if (fast) {
+          const int m = atomicAdd(nmem, 1);
+          if (m < cap) {
+            A[m] = make_int2(idv[u], sl[u]);
+            Ai[m] = (unsigned char)i;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (R.ok) {
+    // exclusive scan of the row's cell counts: lane owns cells [lane*m, lane*m + m)
+    const int m = (nx + 63) >> 6;
+    int v = 0;
+    for (int u = 0; u < m; ++u) {
+      const int i = lane * m + u;
+      if (i < nx) v += cnt[i];
+    }
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    int ex = incl - v;
+    for (int u = 0; u < m; ++u) {
+      const int i = lane * m + u;
+      if (i < nx) {
+        pre[i] = ex;
+        cur[i] = ex;
+        C.start[R.c0 + i] = r0 + ex;
+        ex += cnt[i];
+      }
+    }
+    if (R.r == C.n_rows - 1 && lane == 0) C.start[c1] = r1;
+  }
+  __syncthreads();
+  if (fast) {
+    // bucket the members by cell (unordered within a cell)
+    const int nm = min(*nmem, M);
+    for (int m = lane; m < nm; m += 64) {
+      const int pos = atomicAdd(&cur[Ai[m]], 1);
+      if (pos < M) Bm[pos] = (unsigned short)m;
+    }
+  } else {
+    // pass 2 (large rows): an unordered slot in the cell run, through C.tmp
+    for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
+      int sl[kCand], c[kCand], idv[kCand];
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        const int t = t0 + 64 * u;
+        sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+      }
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= R.c0 && c[u] < c1) ? in.id[sl[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        if (c[u] >= R.c0 && c[u] < c1) {
+          const int i = c[u] - (int)R.c0;
+          const int slot = r0 + pre[i] + (atomicAdd(&cur[i], 1) - pre[i]);
+          if (slot < r1) C.tmp[slot] = make_int4(idv[u], sl[u], c[u], 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // order each cell run by id and write the sorted arrays
+  const int nmv = fast ? min(*nmem, M) : M;
+  for (int t = lane; t < M; t += 64) {
+    int id, p, i;
+    if (fast) {
+      const int m = Bm[t];
+      if (m >= nmv) continue;  // members inconsistent with the row count: never by construction
+      const int2 e = A[m];
+      id = e.x;
+      p = e.y;
+      i = Ai[m];
+    } else {
+      const int4 rec = C.tmp[r0 + t];
+      id = rec.x;
+      p = rec.y;
+      i = rec.z - (int)R.c0;
+    }
+    if (p < 0 || p >= C.n_tot || i < 0 || i >= nx) continue;
+    const int a = pre[i], b = min(a + cnt[i], M);
+    const double q = in.q[p], x = in.x[p], y = in.y[p], z = in.z[p];
+    int rk = 0;
+    if (b - a > 1) {
+      if (fast) {
+        for (int u = a; u < b; ++u) rk += (A[Bm[u]].x < id) ? 1 : 0;
+      } else {
+        for (int u = a; u < b; u += 4) {
+          int idu[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) idu[v] = (u + v < b) ? C.tmp[r0 + u + v].x : 0x7fffffff;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) rk += (idu[v] < id) ? 1 : 0;
+        }
+      }
+    }
+    const int o = r0 + a + rk;
+    C.perm[o] = p;
+    C.skey[o] = (int)R.c0 + i;
+    C.sq[o] = q;
+    C.sx[o] = x;
+    C.sy[o] = y;
+    C.sz[o] = z;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -642,7 +1066,7 @@ __device__ __forceinline__ int y_cell(const double* __restrict__ yf, int ny, dou
   return lo;
 }
 
-// initial binning; rank = arrival order in the cell (for the next sort)
+// initial binning: cell key of every particle (the next sort is a full one)
 __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, long long n1) {
   const long long p = n0 + (long long)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n1) return;
@@ -654,7 +1078,6 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
   const int j = y_cell(C.yf + E.y_off, E.ny, y);
   const int c = (int)(E.c_off + (long long)(j * E.nz + k) * E.nx + i);
   S.key[p] = c;
-  S.rank[p] = atomicAdd(&C.count[c], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
                                          int p, int c, signed char* __restrict__ wall_rec) {
   Fwd F;
-  eval_particle(C, E, in, s, p, c, F);
+  eval_particle<true>(C, E, in, s, p, c, F);
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int j = F.j;
   const double q = F.q, d = F.d;
@@ -731,11 +1154,19 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   const int nj = y_cell_from(yf, ny, yr, j);
   const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
   out.key[s] = key;
-  out.rank[s] = atomicAdd(&C.count[key], 1);
+  // rows beyond the 3 x 3 neighbourhood (k periodic) go on the far list
+  const int dk = abs(nk - F.k);
+  if (abs(nj - j) > 1 || (dk > 1 && dk < nz - 1)) {
+    const int f = atomicAdd(&C.far_n[0], 1);
+    if (f < C.n_tot) C.far[f] = s;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
+  // the new row ranges become the stored order's (read by the next sort)
+  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
+    C.rs_old[r] = C.rs_new[r];
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
   if (s >= C.n_tot) return;
   const int p = C.perm[s];
@@ -805,20 +1236,40 @@ __global__ __launch_bounds__(kBlock) void k_get_state(PState S, PIn out, long lo
 
 namespace tf {
 
-hipError_t launch_scan(const Ctx& C, hipStream_t st) {
-  const long long n = C.c_tot;
+// exclusive prefix of cnt[0..n) into out[0..n]
+static void scan_into(const Ctx& C, const int* cnt, long long n, int* out, hipStream_t st) {
   const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
-  k_scan_reduce<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part);
-  k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb, C);
-  k_scan_down<<<nb, kBlock, 0, st>>>(C.count, n, C.scan_part, nb, C.start);
-  return hipGetLastError();
+  if (nb == 0) return;
+  const int fold = nb <= kScanFold ? 1 : 0;
+  k_scan_reduce<<<nb, kBlock, 0, st>>>(C, cnt, n, C.scan_part);
+  if (!fold) k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb);
+  k_scan_down<<<nb, kBlock, 0, st>>>(cnt, n, C.scan_part, fold, out);
 }
 
-hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st) {
-  const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
-  if (nb == 0) return hipSuccess;
-  k_place<<<nb, kBlock, 0, st>>>(C, cur.key, cur.rank, cur.id);
-  k_rank<<<nb, kBlock, 0, st>>>(C, cur.key, cur.q);
+hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool full, hipStream_t st) {
+  if (full) {
+    // counting sort from scratch: cell counts by atomics, cell prefix, placement, id order
+    const int nbp = (int)((C.n_tot + kBlock - 1) / kBlock);
+    if (nbp > 0) k_count<<<nbp, kBlock, 0, st>>>(C, cur.key);
+    scan_into(C, C.count, C.c_tot, C.start, st);
+    const int nb = (int)((C.n_tot + kBlock * kIlp - 1) / (kBlock * kIlp));
+    if (nb > 0) {
+      k_place<<<nb, kBlock, 0, st>>>(C, cur.key, cur.id);
+      k_rank<<<nb, kBlock, 0, st>>>(C, cur);
+    }
+    k_rows_from_start<<<(int)((C.n_rows + kBlock) / kBlock), kBlock, 0, st>>>(C);
+    return hipGetLastError();
+  }
+  const int one = (C.n_ens == 1) ? 1 : 0;
+  const int nbr = (int)((C.n_rows + kRowsPerBlock - 1) / kRowsPerBlock);
+  k_row_count<<<nbr, kBlock, 0, st>>>(C, G.eh[0], one, cur.key);
+  scan_into(C, C.row_cnt, C.n_rows, C.rs_new, st);
+  // member capacity per row in LDS: about four times the mean row size
+  const long long mean = C.n_rows > 0 ? (C.n_tot + C.n_rows - 1) / C.n_rows : 1;
+  int cap = 128;
+  while (cap < 4 * mean && cap < 1024) cap *= 2;
+  const size_t lds = (size_t)kRowsPerBlock * row_lds_bytes(G.nx_max, cap);
+  k_row_place<<<nbr, kBlock, lds, st>>>(C, G.eh[0], one, cur, G.nx_max, cap);
   return hipGetLastError();
 }
 

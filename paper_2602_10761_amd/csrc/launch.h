@@ -37,8 +37,9 @@ struct LaunchGeo {
   const Ens* eh;   // host copies of the ensemble descriptors
 };
 
-hipError_t launch_scan(const Ctx& C, hipStream_t st);
-hipError_t launch_sort(const Ctx& C, const PState& cur, hipStream_t st);
+// full: counting sort from scratch (after init or a state upload); otherwise
+// the incremental row sort, valid when `cur` was written by the last push
+hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool full, hipStream_t st);
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr);

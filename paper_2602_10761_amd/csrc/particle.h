@@ -28,6 +28,10 @@ struct Fwd {
   double x1, y1, z1;  // after the update, before rebound and wrap
 };
 
+// SORTED: positions and charges of slot s and of its cell mates come from the
+// slot-ordered copies C.sx, C.sy, C.sz, C.sq written by the sort (coalesced,
+// no dependent gather); otherwise they are gathered through C.perm from `in`.
+template <bool SORTED>
 __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
                                               Fwd& F) {
   const int nx = E.nx, ny = E.ny, nz = E.nz;
@@ -38,9 +42,12 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   const double* __restrict__ yf = C.yf + E.y_off;
   const double* __restrict__ idy = C.idy + E.y_off;
 
-  const double x = in.x[p], y = in.y[p], z = in.z[p];
+  const double x = SORTED ? C.sx[s] : in.x[p];
+  const double y = SORTED ? C.sy[s] : in.y[p];
+  const double z = SORTED ? C.sz[s] : in.z[p];
+  const double q = SORTED ? C.sq[s] : in.q[p];
   const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
-  const double q = in.q[p], d = in.d[p];
+  const double d = in.d[p];
 
   // carrier velocity: trilinear in the cell, linear in physical y
   const int i1 = (i + 1 == nx) ? 0 : i + 1;
@@ -89,12 +96,24 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
     const int a = C.start[c], b = C.start[c + 1];
     for (int t = a; t < b; ++t) {
       if (t == s) continue;
-      const int pj = C.perm[t];
-      const double rx = x - in.x[pj], ry = y - in.y[pj], rz = z - in.z[pj];
+      double ox, oy, oz, oq;
+      if (SORTED) {
+        ox = C.sx[t];
+        oy = C.sy[t];
+        oz = C.sz[t];
+        oq = C.sq[t];
+      } else {
+        const int pj = C.perm[t];
+        ox = in.x[pj];
+        oy = in.y[pj];
+        oz = in.z[pj];
+        oq = in.q[pj];
+      }
+      const double rx = x - ox, ry = y - oy, rz = z - oz;
       const double r2 = (rx * rx + ry * ry) + rz * rz;
       if (r2 > 0.0) {
         const double ri = rsqrt(r2);
-        const double w = in.q[pj] * (ri * ri * ri);
+        const double w = oq * (ri * ri * ri);
         sx += w * rx;
         sy += w * ry;
         sz += w * rz;

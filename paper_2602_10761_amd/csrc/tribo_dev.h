@@ -52,11 +52,10 @@ inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
 
-// Particle buffer (structure of arrays).  key = global cell of the position,
-// rank = arrival order of the particle in that cell's counter (unordered).
+// Particle buffer (structure of arrays).  key = global cell of the position.
 struct PState {
   double *x, *y, *z, *vx, *vy, *vz, *q, *d;
-  int *id, *key, *rank;
+  int *id, *key;
 };
 
 // Everything the kernels share (device pointers into the workspace).
@@ -67,12 +66,23 @@ struct Ctx {
   int n_ens;
   int pad0;
   long long n_tot, c_tot;
-  int* count;                // [c_tot]   particles per cell (built by atomics)
+  int* count;                // [c_tot]   particles per cell (built by atomics, consumed by the placement)
   int* start;                // [c_tot+1] exclusive prefix of count
-  unsigned long long* tmp;   // [n_tot]   (id << 32 | old slot), unordered within a cell
+  int4* tmp;                 // [n_tot]   (id, old slot, cell, 0), unordered within a cell
   int* perm;                 // [n_tot]   new slot -> old slot, ordered by (cell, id)
   int* skey;                 // [n_tot]   cell of each new slot
   double* sq;                // [n_tot]   charge of each new slot
+  double *sx, *sy, *sz;      // [n_tot]   position of each new slot
+  // incremental sort: the state is stored in the previous sort's order, so a
+  // (j, k) row's new members come from the 3 x 3 neighbouring rows of that
+  // order, except the particles listed in `far`
+  const long long* r_off;    // [n_ens+1] (j, k) row offsets
+  long long n_rows;
+  int* row_cnt;              // [n_rows]   members of each row after this step's sort
+  int* rs_old;               // [n_rows+1] slot range of each row in the stored order
+  int* rs_new;               // [n_rows+1] slot range of each row after this step's sort
+  int* far;                  // [n_tot]    slots of particles whose row moved by 2+ in j or k
+  int* far_n;                // [2]        live count (push appends), snapshot for the sort
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
   double* cp;                // Thomas scratch (same indexing as spec)

@@ -119,6 +119,42 @@ def test_multi_step_parity():
     sim.close()
 
 
+def test_far_movers_multi_step():
+    """Fast particles that cross two or more cell rows in y or z per step (the
+    sort's far list), over several steps, against the oracle."""
+    say("far movers")
+    ens = ens_small(nx=16, ny=16, nz=16, n=3000, re_tau=20.0, v_jitter=60.0, density_ratio=1000.0)
+    n = 6
+    g = O.Geo.from_mesh(ens.mesh)
+    s = O.state_of(ens)
+    st = O.Stats(g.ny)
+    far = 0
+    for _ in range(n):
+        _, j0, k0 = O.locate(g, s["x"], s["y"], s["z"])
+        s = O.step(g, ens.U, s, ens.params, st)
+        _, j1, k1 = O.locate(g, s["x"], s["y"], s["z"])
+        dk = np.abs(k1 - k0)
+        far += int(np.sum((np.abs(j1 - j0) > 1) | ((dk > 1) & (dk < g.nz - 1))))
+    sim = sim_of(ens)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    sim.close()
+    err = state_errors(gpu, s, ens.mesh)
+    say("  far moves", far, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert far > 500
+    # counts exact; the fixed-point charge sums take the charges of states that
+    # already differ by rounding after 1000+ impacts, so a charge sitting on a
+    # rounding boundary may land one unit apart
+    assert gst["steps"] == st.steps and gst["flags"] == st.flags
+    np.testing.assert_array_equal(gst["impacts"], st.impacts)
+    np.testing.assert_array_equal(gst["crel_y"], st.crel_y)
+    for k, ref in (("wallq", st.wallq), ("qcum_y", st.qcum_y), ("qnow_y", st.qnow_y)):
+        d = np.abs(np.asarray(gst[k], dtype=np.float64) - np.asarray(ref, dtype=np.float64))
+        assert d.max() <= 4 * n, (k, d.max())
+    assert max(err.values()) < 1e-10
+
+
 @pytest.mark.parametrize("cfg", [2, 3])
 def test_full_size_one_step(cfg):
     """The benchmark workloads at full size: one step, every particle compared."""
