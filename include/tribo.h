@@ -191,8 +191,10 @@ int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
  * tf_profile_begin, the next max_steps steps are launched eagerly with an
  * event at every phase boundary; tf_profile_end synchronises and returns the
  * summed milliseconds of each phase over the profiled steps.  Phases:
- *   0 sort (prefix sum, slot assignment, id ranking)
- *   1 deposit + forward FFT along x     2 forward FFT along z
+ *   0 sort: the row-count prefix sum (after init or tf_set_state: the full
+ *     counting sort)
+ *   1 deposit + forward FFT along x (the incremental sort runs fused here)
+ *   2 forward FFT along z
  *   3 tridiagonal y-solves              4 inverse FFT along z
  *   5 inverse FFT along x               6 particle push
  */
@@ -201,16 +203,19 @@ int tf_profile_begin(tf_handle* h, int32_t max_steps);
 int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_steps);
 
 /*
- * Tile shapes of the Poisson kernels, used by every later tf_init /
+ * Tile shapes of the sort and Poisson kernels, used by every later tf_init /
  * tf_workspace_size of the calling process (0 = built-in choice):
- *   fx_rows    unused (the x transforms take one wavefront per (j, k) row)
+ *   sort_cap   members per row pair held in LDS by the fused sort (pairs with
+ *              more take a second pass through global memory); 0 = about 2.5
+ *              times the mean pair, -1 = none (always two passes), else
+ *              1..4096 (clamped to what fits 64 KiB of LDS per block)
  *   fz_cols    spectral columns per block of the z transforms (1..64)
  *   tri_modes  Fourier modes per block of the tridiagonal solves (1..64)
  * Values whose LDS need exceeds 64 KiB per block are rejected at tf_init.
  * Results do not depend on the tiles (bitwise).
  */
 typedef struct {
-  int32_t fx_rows, fz_cols, tri_modes, reserved;
+  int32_t sort_cap, fz_cols, tri_modes, reserved;
 } tf_tuning;
 int tf_set_tuning(const tf_tuning* t);
 

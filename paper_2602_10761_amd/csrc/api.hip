@@ -53,15 +53,15 @@ bool radix_plan(int n, FftPlan* P) {
 struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
-  int nx_max = 0, nz_max = 0, ny_max = 0, rpb = 1, wz = 8, tri_m = 16, tri_pcr = 1, tri_eq_max = 0;
+  int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_m = 16, tri_pcr = 1, tri_eq_max = 0;
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
-  std::vector<int> fx_blk, fz_blk, tri_blk;
+  std::vector<int> fp_blk, fz_blk, tri_blk;
   std::map<int, int> tw_off;
 };
 
 int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   if (!ens || n_ens < 1 || n_ens > 4096) return fail(TF_EINVAL, "n_ens must be in [1, 4096]");
-  S->fx_blk.assign(n_ens + 1, 0);
+  S->fp_blk.assign(n_ens + 1, 0);
   S->fz_blk.assign(n_ens + 1, 0);
   S->tri_blk.assign(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
@@ -104,7 +104,6 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       }
   }
   if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
-  S->rpb = 1;  // x transforms: one wave per (j, k) row
   // tridiagonal: cyclic reduction holds tm * ny equations (5 doubles each, at
   // most 8 per thread); Thomas (some ny > 256) holds tm columns (32 B per row)
   S->tri_pcr = S->ny_max <= 256 ? 1 : 0;
@@ -133,14 +132,14 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->tri_eq_max = std::max(S->tri_eq_max, S->tri_pcr ? tm * (E.ny + 1) : tm * E.ny);
   }
   S->tri_m = 0;
-  const size_t lds_fx = (size_t)3 * S->nx_max * 16;
+  const size_t lds_fx = (size_t)9 * S->nx_max * 16;  // twiddles + 4 waves x 2 line buffers
   const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
   const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * S->tri_eq_max : (size_t)S->tri_eq_max * 32;
   if (lds_fx > 65536 || lds_fz > 65536 || lds_tri > 65536) return fail(TF_ESIZE, "tile shapes exceed 64 KiB of LDS");
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
-    S->fx_blk[e + 1] = S->fx_blk[e] + (rows + S->rpb - 1) / S->rpb;
+    S->fp_blk[e + 1] = S->fp_blk[e] + (rows / 2 + 3) / 4;  // row pairs, 4 per block
     S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->e_wz[e] - 1) / S->e_wz[e]);
     S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + S->e_tm[e] - 1) / S->e_tm[e];
   }
@@ -221,7 +220,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.rowacc = cv.take<longlong2>(S.rows);
   C.r_off = cv.take<long long>(n_ens + 1);
   C.n_rows = S.rows;
-  C.row_cnt = cv.take<int>(S.rows);
+  C.pair_cnt = cv.take<int>(S.rows / 2);
+  C.ps = cv.take<int>(S.rows / 2 + 1);
   C.rs_old = cv.take<int>(S.rows + 1);
   C.rs_new = cv.take<int>(S.rows + 1);
   C.far = cv.take<int>(S.n_tot);
@@ -287,22 +287,26 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   hipEvent_t* ev = nullptr;
   if (h->prof_n < h->prof_cap) ev = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
   if (ev && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
+  // full: counting sort, then deposit + x transform from the sorted runs;
+  // incremental: row scan, then the fused sort + deposit + x transform
   if ((e = launch_sort(h->C, h->G, in, full, h->stream)) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
+  if (!full && (e = launch_sort_dep(h->C, h->G, in, h->stream)) != hipSuccess) return e;
+  if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
+                          ev ? ev + 2 : nullptr, nullptr, !full)) != hipSuccess)
+    return e;
   if (rec) {
-    if ((e = hipMemcpyAsync(rec->skey, h->C.skey, sizeof(int) * h->C.n_tot, hipMemcpyDeviceToDevice, h->stream)) !=
+    const size_t n = h->C.n_tot, nc = h->C.c_tot;
+    if ((e = hipMemcpyAsync(rec->skey, h->C.skey, sizeof(int) * n, hipMemcpyDeviceToDevice, h->stream)) !=
         hipSuccess)
       return e;
-    if ((e = hipMemcpyAsync(rec->start, h->C.start, sizeof(int) * (h->C.c_tot + 1), hipMemcpyDeviceToDevice,
-                            h->stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(rec->start, h->C.start, sizeof(int) * (nc + 1), hipMemcpyDeviceToDevice, h->stream)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(rec->phi, h->C.phi, sizeof(double) * nc, hipMemcpyDeviceToDevice, h->stream)) !=
+        hipSuccess)
       return e;
   }
-  if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
-  if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
-                          ev ? ev + 2 : nullptr)) != hipSuccess)
-    return e;
-  if (rec && (e = hipMemcpyAsync(rec->phi, h->C.phi, sizeof(double) * h->C.c_tot, hipMemcpyDeviceToDevice,
-                                 h->stream)) != hipSuccess)
-    return e;
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)
     return e;
@@ -347,7 +351,7 @@ int tf_set_tuning(const tf_tuning* t) {
     g_tune = tf_tuning{0, 0, 0, 0};
     return TF_OK;
   }
-  if (t->fx_rows < 0 || t->fx_rows > 256 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
+  if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
       t->tri_modes > 64)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
@@ -506,7 +510,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->C.p_off, h->p_off);
   UP(h->C.c_off, h->c_off);
   UP(h->C.r_off, r_offs);
-  UP(h->d_fx, S.fx_blk);
+  UP(h->d_fx, S.fp_blk);
   UP(h->d_fz, S.fz_blk);
   UP(h->d_tri, S.tri_blk);
   UP(h->C.yf, yf);
@@ -524,6 +528,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowacc, 0, sizeof(longlong2) * S.rows, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.count, 0, sizeof(int) * S.c_tot, h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.pair_cnt, 0, sizeof(int) * (S.rows / 2), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_old, 0, sizeof(int) * (S.rows + 1), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_new, 0, sizeof(int) * (S.rows + 1), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.far_n, 0, sizeof(int) * 2, h->stream);
@@ -540,7 +545,6 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     delete h;
     return fail(TF_EHIP, std::string("tf_init: ") + hipGetErrorString(he));
   }
-  h->G.fx_rpb = S.rpb;
   h->G.nx_max = S.nx_max;
   h->G.nz_max = S.nz_max;
   h->G.wz = S.wz;
@@ -548,10 +552,11 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.tri_m = S.tri_m;
   h->G.tri_pcr = S.tri_pcr;
   h->G.tri_eq_max = S.tri_eq_max;
-  h->G.fx_blk = h->S.fx_blk.data();
+  h->G.sort_cap = g_tune.sort_cap;
+  h->G.fp_blk = h->S.fp_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
   h->G.tri_blk = h->S.tri_blk.data();
-  h->G.d_fx_blk = h->d_fx;
+  h->G.d_fp_blk = h->d_fx;
   h->G.d_fz_blk = h->d_fz;
   h->G.d_tri_blk = h->d_tri;
   h->G.eh = h->eh.data();
@@ -565,11 +570,8 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   if (!h) return fail(TF_EINVAL, "handle is NULL");
   if (n_steps < 0) return fail(TF_EINVAL, "n_steps < 0");
   if (h->C.n_tot == 0) {
-    for (int s = 0; s < n_steps; ++s) {
-      HIPCHK(launch_sort(h->C, h->G, h->cur, false, h->stream));
-      HIPCHK(launch_poisson(h->C, h->G, 0, h->n_ens, h->cur.q, h->cur.key, nullptr, 0, h->C.phi, 0, 1, h->stream));
-      HIPCHK(launch_push(h->C, h->G, h->cur, other(h), nullptr, nullptr, h->stream));
-    }
+    // no particles: the field of zero charge and the step counters
+    for (int s = 0; s < n_steps; ++s) HIPCHK(enqueue_step(h, h->cur, other(h), nullptr, false));
     return TF_OK;
   }
   const bool rec = (flags & TF_STEP_RECORD) != 0;

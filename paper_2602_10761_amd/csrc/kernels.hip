@@ -240,7 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_count(Ctx C, const int* __restrict__
   if (p < C.n_tot) atomicAdd(&C.count[key[p]], 1);
 }
 
-// row slot ranges from the cell starts of a full sort
+// row slot ranges from the cell starts of a full sort; the pair counts restart
+// from zero for this step's push
 __global__ __launch_bounds__(kBlock) void k_rows_from_start(Ctx C) {
   const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (r > C.n_rows) return;
@@ -251,310 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_from_start(Ctx C) {
   const int e = find_off(C.r_off, C.n_ens + 1, r);
   const Ens& E = C.ens[e];
   C.rs_new[r] = C.start[E.c_off + (r - C.r_off[e]) * E.nx];
-}
-
-// ---------------------------------------------------------------------------
-// incremental sort, one wave per (j, k) row of the new order.  Candidates are
-// the slots of rows (j + dj, k + dk), |dj|, |dk| <= 1 (k periodic), in the
-// stored order -- at most 6 contiguous slot ranges -- plus the far list.
-// ---------------------------------------------------------------------------
-constexpr int kRowsPerBlock = kBlock / 64;
-
-struct RowSegs {
-  int a[6], off[7];  // segment u: slots [a[u], a[u] + off[u+1] - off[u])
-};
-
-// two segments per dj (the second one empty unless k is on the periodic seam);
-// all indices static so the segments stay in registers
-__device__ __forceinline__ void row_segments(const int* __restrict__ rs, long long rb, int ny, int nz, int j, int k,
-                                             RowSegs& S) {
-  S.off[0] = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int j2 = j + d - 1;
-    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
-    if (j2 >= 0 && j2 < ny) {
-      const long long base = rb + (long long)j2 * nz;
-      long long s0, e0, s1 = 0, e1 = 0;  // rows [s0, e0) and [s1, e1)
-      if (k >= 1 && k <= nz - 2) {
-        s0 = base + k - 1;
-        e0 = base + k + 2;
-      } else if (k == 0) {
-        s0 = base;
-        e0 = base + 2;
-        s1 = base + nz - 1;
-        e1 = base + nz;
-      } else {
-        s0 = base + nz - 2;
-        e0 = base + nz;
-        s1 = base;
-        e1 = base + 1;
-      }
-      a0 = rs[s0];
-      b0 = rs[e0];
-      if (e1 > s1) {
-        a1 = rs[s1];
-        b1 = rs[e1];
-      }
-    }
-    S.a[2 * d] = a0;
-    S.off[2 * d + 1] = S.off[2 * d] + max(b0 - a0, 0);
-    S.a[2 * d + 1] = a1;
-    S.off[2 * d + 2] = S.off[2 * d + 1] + max(b1 - a1, 0);
-  }
-}
-
-// slot of flattened candidate t < S.off[6]
-__device__ __forceinline__ int seg_slot(const RowSegs& S, int t) {
-  int s = S.a[0] + t;
-#pragma unroll
-  for (int u = 1; u < 6; ++u)
-    if (t >= S.off[u]) s = S.a[u] + (t - S.off[u]);
-  return s;
-}
-
-struct RowId {
-  long long r, c0, rb;
-  int nx, ny, nz, j, k;
-  bool ok;
-};
-
-__device__ __forceinline__ RowId row_of(const Ctx& C, const Ens& Eone, int one, long long r) {
-  RowId R;
-  R.r = r;
-  R.ok = r < C.n_rows;
-  if (!R.ok) r = 0;
-  long long coff;
-  if (one) {
-    R.nx = Eone.nx;
-    R.ny = Eone.ny;
-    R.nz = Eone.nz;
-    R.rb = 0;
-    coff = 0;
-  } else {
-    const int e = find_off(C.r_off, C.n_ens + 1, r);
-    const Ens& E = C.ens[e];
-    R.nx = E.nx;
-    R.ny = E.ny;
-    R.nz = E.nz;
-    R.rb = C.r_off[e];
-    coff = E.c_off;
-  }
-  const int jk = (int)(r - R.rb);
-  R.j = jk / R.nz;
-  R.k = jk - R.j * R.nz;
-  R.c0 = coff + (long long)jk * R.nx;
-  return R;
-}
-
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Candidates in batches of kCand per lane so that their key loads are in
-// flight together; the far list is a seventh segment after the six ranges.
-constexpr int kCand = 8;
-
-// members of each new row
-__global__ __launch_bounds__(kBlock) void k_row_count(Ctx C, Ens Eone, int one, const int* __restrict__ key) {
-  const int lane = threadIdx.x & 63;
-  const RowId R = row_of(C, Eone, one, (long long)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6));
-  if (!R.ok) return;  // no block-wide synchronisation in this kernel
-  RowSegs S;
-  row_segments(C.rs_old, R.rb, R.ny, R.nz, R.j, R.k, S);
-  const long long c1 = R.c0 + R.nx;
-  const int T = S.off[6];
-  const int TT = T + min(C.far_n[0], (int)C.n_tot);
-  int cnt = 0;
-  for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
-    int sl[kCand], c[kCand];
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      const int t = t0 + 64 * u;
-      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
-    }
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? key[sl[u]] : -1;
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) cnt += (c[u] >= R.c0 && c[u] < c1) ? 1 : 0;
-  }
-  cnt = wave_sum_i(cnt);
-  if (lane == 0) C.row_cnt[R.r] = cnt;
-}
-
-// LDS of one row in k_row_place: member list A {id, old slot} and its cells
-// (bytes), member indices ordered by cell, cell counts / starts / cursors
-__host__ __device__ inline size_t row_lds_bytes(int nx_max, int cap) {
-  return ((size_t)cap * 8 + (size_t)cap * 2 + (size_t)cap + (size_t)nx_max * 12 + 16 + 15) & ~(size_t)15;
-}
-
-// after the row scan (rs_new): one pass over the candidates collects the row's
-// members in LDS (cell counts by LDS atomics), a per-cell scan gives the cell
-// starts, the members are bucketed by cell and each ranked by id inside its
-// cell.  Rows with more than `cap` members take a second candidate pass and
-// rank through C.tmp instead.  Writes start, perm, skey and the slot-ordered
-// copies of charge and position.
-__global__ __launch_bounds__(kBlock) void k_row_place(Ctx C, Ens Eone, int one, PState in, int nx_max, int cap) {
-  extern __shared__ __align__(16) unsigned char lds_b[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  unsigned char* base = lds_b + (size_t)w * row_lds_bytes(nx_max, cap);
-  int2* A = reinterpret_cast<int2*>(base);
-  int* cnt = reinterpret_cast<int*>(base + (size_t)cap * 8);
-  int* pre = cnt + nx_max;
-  int* cur = pre + nx_max;
-  int* nmem = cur + nx_max;
-  unsigned short* Bm = reinterpret_cast<unsigned short*>(nmem + 4);
-  unsigned char* Ai = reinterpret_cast<unsigned char*>(Bm + cap);
-
-  const RowId R = row_of(C, Eone, one, (long long)blockIdx.x * kRowsPerBlock + w);
-  const int nx = R.nx;
-  RowSegs S;
-  const long long c1 = R.c0 + nx;
-  int r0 = 0, r1 = 0, T = 0, TT = 0;
-  if (R.ok) {
-    row_segments(C.rs_old, R.rb, R.ny, R.nz, R.j, R.k, S);
-    r0 = C.rs_new[R.r];
-    r1 = C.rs_new[R.r + 1];
-    T = S.off[6];
-    TT = T + min(C.far_n[1], (int)C.n_tot);
-    for (int i = lane; i < nx; i += 64) cnt[i] = 0;
-    if (lane == 0) *nmem = 0;
-  }
-  const int M = r1 - r0;
-  const bool fast = M <= cap;  // wave-uniform
-  __syncthreads();
-  // pass 1: cell counts; the fast path also lists the members
-  for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
-    int sl[kCand], c[kCand], idv[kCand];
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      const int t = t0 + 64 * u;
-      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
-    }
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
-    if (fast) {
-#pragma unroll
-      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= R.c0 && c[u] < c1) ? in.id[sl[u]] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      if (c[u] >= R.c0 && c[u] < c1) {
-        const int i = c[u] - (int)R.c0;
-        atomicAdd(&cnt[i], 1);
-        if (fast) {
-          const int m = atomicAdd(nmem, 1);
-          if (m < cap) {
-            A[m] = make_int2(idv[u], sl[u]);
-            Ai[m] = (unsigned char)i;
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (R.ok) {
-    // exclusive scan of the row's cell counts: lane owns cells [lane*m, lane*m + m)
-    const int m = (nx + 63) >> 6;
-    int v = 0;
-    for (int u = 0; u < m; ++u) {
-      const int i = lane * m + u;
-      if (i < nx) v += cnt[i];
-    }
-    int incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    int ex = incl - v;
-    for (int u = 0; u < m; ++u) {
-      const int i = lane * m + u;
-      if (i < nx) {
-        pre[i] = ex;
-        cur[i] = ex;
-        C.start[R.c0 + i] = r0 + ex;
-        ex += cnt[i];
-      }
-    }
-    if (R.r == C.n_rows - 1 && lane == 0) C.start[c1] = r1;
-  }
-  __syncthreads();
-  if (fast) {
-    // bucket the members by cell (unordered within a cell)
-    const int nm = min(*nmem, M);
-    for (int m = lane; m < nm; m += 64) {
-      const int pos = atomicAdd(&cur[Ai[m]], 1);
-      if (pos < M) Bm[pos] = (unsigned short)m;
-    }
-  } else {
-    // pass 2 (large rows): an unordered slot in the cell run, through C.tmp
-    for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
-      int sl[kCand], c[kCand], idv[kCand];
-#pragma unroll
-      for (int u = 0; u < kCand; ++u) {
-        const int t = t0 + 64 * u;
-        sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
-      }
-#pragma unroll
-      for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
-#pragma unroll
-      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= R.c0 && c[u] < c1) ? in.id[sl[u]] : 0;
-#pragma unroll
-      for (int u = 0; u < kCand; ++u) {
-        if (c[u] >= R.c0 && c[u] < c1) {
-          const int i = c[u] - (int)R.c0;
-          const int slot = r0 + pre[i] + (atomicAdd(&cur[i], 1) - pre[i]);
-          if (slot < r1) C.tmp[slot] = make_int4(idv[u], sl[u], c[u], 0);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // order each cell run by id and write the sorted arrays
-  const int nmv = fast ? min(*nmem, M) : M;
-  for (int t = lane; t < M; t += 64) {
-    int id, p, i;
-    if (fast) {
-      const int m = Bm[t];
-      if (m >= nmv) continue;  // members inconsistent with the row count: never by construction
-      const int2 e = A[m];
-      id = e.x;
-      p = e.y;
-      i = Ai[m];
-    } else {
-      const int4 rec = C.tmp[r0 + t];
-      id = rec.x;
-      p = rec.y;
-      i = rec.z - (int)R.c0;
-    }
-    if (p < 0 || p >= C.n_tot || i < 0 || i >= nx) continue;
-    const int a = pre[i], b = min(a + cnt[i], M);
-    const double q = in.q[p], x = in.x[p], y = in.y[p], z = in.z[p];
-    int rk = 0;
-    if (b - a > 1) {
-      if (fast) {
-        for (int u = a; u < b; ++u) rk += (A[Bm[u]].x < id) ? 1 : 0;
-      } else {
-        for (int u = a; u < b; u += 4) {
-          int idu[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) idu[v] = (u + v < b) ? C.tmp[r0 + u + v].x : 0x7fffffff;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) rk += (idu[v] < id) ? 1 : 0;
-        }
-      }
-    }
-    const int o = r0 + a + rk;
-    C.perm[o] = p;
-    C.skey[o] = (int)R.c0 + i;
-    C.sq[o] = q;
-    C.sx[o] = x;
-    C.sy[o] = y;
-    C.sz[o] = z;
-  }
+  if ((r & 1) == 0) C.pair_cnt[r >> 1] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -611,14 +309,15 @@ __device__ __forceinline__ void butterfly(double2* v) {
 
 template <int R, bool INV>
 __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2* __restrict__ b, int rows,
-                                         int n, int pitch, int Ns, const double2* __restrict__ tw) {
+                                         int n, int pitch, int Ns, const double2* __restrict__ tw, int tid,
+                                         int nthr) {
   const int nb = n / R;
   const int stride = n / (Ns * R);
   const int total = rows * nb;
   const unsigned mnb = rows > 1 ? magic32(nb) : 0u;
   const bool ns2 = (Ns & (Ns - 1)) == 0;
   const unsigned mns = ns2 ? 0u : magic32(Ns);
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+  for (int t = tid; t < total; t += nthr) {
     const int row = rows > 1 ? fdiv32(t, mnb, nb) : 0;
     const int jj = t - row * nb;
     const double2* s = a + row * pitch;
@@ -641,19 +340,21 @@ __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2*
 }
 
 // Transforms `rows` lines of length P.n (row pitch `pitch`) held in a, with
-// scratch b; returns the buffer holding the result.  Caller must
-// __syncthreads() before the call.
+// scratch b, by threads tid = 0..nthr-1; returns the buffer holding the
+// result.  Every thread of the block calls it (block barrier between passes);
+// caller must __syncthreads() before the call.
 template <bool INV>
-__device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const FftPlan& P, const double2* tw) {
+__device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const FftPlan& P, const double2* tw,
+                            int tid, int nthr) {
   const int n = P.n;
   int Ns = 1;
   for (int ps = 0; ps < P.npass; ++ps) {
     const int R = (int)((P.rcode >> (3 * ps)) & 7u);
     switch (R) {
-      case 2: fft_pass<2, INV>(a, b, rows, n, pitch, Ns, tw); break;
-      case 3: fft_pass<3, INV>(a, b, rows, n, pitch, Ns, tw); break;
-      case 4: fft_pass<4, INV>(a, b, rows, n, pitch, Ns, tw); break;
-      default: fft_pass<5, INV>(a, b, rows, n, pitch, Ns, tw); break;
+      case 2: fft_pass<2, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
+      case 3: fft_pass<3, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
+      case 4: fft_pass<4, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
+      default: fft_pass<5, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
     }
     __syncthreads();
     double2* t = a;
@@ -674,22 +375,16 @@ __device__ __forceinline__ long long wave_sum(long long v) {
 }
 
 // ---------------------------------------------------------------------------
-// deposit + forward FFT along x: one wave per (j, k) row, no cross-wave sync.
-// Lane l owns cells i = l, l + 64, ... of the row; a cell's particles are the
-// contiguous sorted slots [start[c], start[c+1]); their fixed-point charges
-// are summed in integers (exact, order-free).  q source: particles
-// (q_in == nullptr) or a per-cell fixed-point array.
+// x transforms on row pairs: one wave per pair of rows (j, k), (j, k+1) with k
+// even (nz is even), kPairsPerBlock pairs per block.  The two real rows are
+// the real and imaginary parts of one complex transform; their half spectra
+// follow from the conjugate-symmetric and antisymmetric parts of the result.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const double* __restrict__ q,
-                                                 const int* __restrict__ blk_off, int blk0, int nmax,
-                                                 const long long* __restrict__ q_in, long long q_shift,
-                                                 const double* __restrict__ r_in, int do_stats) {
-  extern __shared__ double2 lds[];
-  double2* buf0 = lds;
-  double2* buf1 = lds + nmax;
-  double2* tw = lds + 2 * nmax;
-  Ens E;
-  int lb;
+constexpr int kPairsPerBlock = kBlock / 64;
+
+// block -> ensemble and local block (block tables per ensemble)
+__device__ __forceinline__ void block_ens(const Ctx& C, const Ens& Eone, int one, const int* __restrict__ blk_off,
+                                          int blk0, Ens& E, int& lb) {
   if (one) {
     E = Eone;
     lb = blockIdx.x;
@@ -699,66 +394,430 @@ __global__ __launch_bounds__(64) void k_dep_fftx(Ctx C, Ens Eone, int one, const
     E = C.ens[e];
     lb = gb - blk_off[e];
   }
-  const int nx = E.nx, nz = E.nz;
-  const int jk = lb;
-  const int j = fdiv32(jk, magic32(nz), nz);
-  const long long c0 = E.c_off + (long long)jk * nx;
-  const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
+}
 
-  for (int t = threadIdx.x; t < nx; t += 64) tw[t] = C.tw[E.fx.tw_off + t];
+// transform buf0 = rho_A + i rho_B forward and store the half spectra of rows
+// jkA and jkA + 1
+__device__ __forceinline__ void pair_forward_store(const Ctx& C, const Ens& E, int jkA, double2* buf0, double2* buf1,
+                                                   const double2* tw, int lane, bool ok) {
+  const int nx = E.nx;
+  double2* res = lds_fft<false>(buf0, buf1, 1, nx, E.fx, tw, lane, 64);
+  if (!ok) return;
+  double2* outA = C.spec + E.s_off + (long long)jkA * E.nhp;
+  double2* outB = outA + E.nhp;
+  for (int m = lane; m < E.nh; m += 64) {
+    const double2 zm = res[m];
+    const double2 zn = res[m == 0 ? 0 : nx - m];
+    outA[m] = make_double2(0.5 * (zm.x + zn.x), 0.5 * (zm.y - zn.y));
+    outB[m] = make_double2(0.5 * (zm.y + zn.y), -0.5 * (zm.x - zn.x));
+  }
+}
+
+// deposit (or given density) + forward FFT along x.  Sources of the cell
+// charge, per call: the sorted particle runs [start[c], start[c+1]) (exact
+// int64 fixed-point sums, order-free), a per-cell fixed-point array q_in, or
+// a density r_in (per unit volume after division by V).
+__global__ __launch_bounds__(kBlock) void k_pair_fftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
+                                                      int blk0, int nmax, const long long* __restrict__ q_in,
+                                                      long long q_shift, const double* __restrict__ r_in,
+                                                      int do_stats) {
+  extern __shared__ double2 lds[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2* tw = lds;
+  double2* buf0 = lds + nmax + (size_t)w * 2 * nmax;
+  double2* buf1 = buf0 + nmax;
+  Ens E;
+  int lb;
+  block_ens(C, Eone, one, blk_off, blk0, E, lb);
+  const int nx = E.nx, nz = E.nz, n2 = 2 * E.nx;
+  const int lp = lb * kPairsPerBlock + w;
+  const bool ok = lp < ((E.ny * nz) >> 1);
+  const int jkA = ok ? 2 * lp : 0;
+  const int j = jkA / nz;
+  const long long c0 = E.c_off + (long long)jkA * nx;
+  const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
+  for (int t = threadIdx.x; t < nx; t += kBlock) tw[t] = C.tw[E.fx.tw_off + t];
   bool ovf = false;
-  long long rq48 = 0, rq32 = 0;
-  if (r_in) {
-    const double iv = 1.0 / C.vol[E.y_off + j];
-    for (int i = threadIdx.x; i < nx; i += 64) buf0[i] = make_double2(r_in[c0 + i] * iv, 0.0);
+  long long rq48[2] = {0, 0}, rq32[2] = {0, 0};
+  int cnt[2] = {0, 0};
+  const bool parts = !q_in && !r_in;
+  long long* bins = reinterpret_cast<long long*>(buf1);  // 2 nx int64 in the scratch buffer
+  int s0 = 0, s1 = 0;
+  if (ok && parts) {
+    for (int i = lane; i < n2; i += 64) bins[i] = 0;
+    s0 = min(max(C.start[c0], 0), (int)C.n_tot);
+    const int sm = C.start[c0 + nx];
+    s1 = min(max(C.start[c0 + n2], s0), (int)C.n_tot);
+    cnt[0] = sm - s0;
+    cnt[1] = s1 - sm;
   }
-  int cnt = 0;
-  if (q_in) {
-    for (int i = threadIdx.x; i < nx; i += 64) {
-      const long long Q = q_in[c0 + i - q_shift];
-      rq48 += Q;
-      buf0[i] = make_double2((double)Q * rsc, 0.0);
-    }
-  } else if (!r_in) {
-    // particle-parallel over the row's sorted slots [start[c0], start[c0 + nx]):
-    // coalesced charge/key loads, per-cell integer sums in LDS (order-free, exact)
-    long long* bins = reinterpret_cast<long long*>(buf1);
-    for (int i = threadIdx.x; i < nx; i += 64) bins[i] = 0;
-    const int s0 = C.start[c0], s1 = C.start[c0 + nx];
-    cnt = s1 - s0;
-    __syncthreads();
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += 64) {
-      const double qv = C.sq[s];
-      const unsigned i = (unsigned)(C.skey[s] - (int)c0);
-      const long long Q = fixed_round(qv, kFixDep, &ovf);
-      rq32 += fixed_round(qv, kFixQcum, &ovf);
-      if (i < (unsigned)nx) atomicAdd(reinterpret_cast<unsigned long long*>(&bins[i]), (unsigned long long)Q);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nx; i += 64) {
-      const long long Q = bins[i];
-      if (C.qdep) C.qdep[c0 + i] = Q;
-      rq48 += Q;
-      buf0[i] = make_double2((double)Q * rsc, 0.0);
+  __syncthreads();
+  if (ok) {
+    if (r_in) {
+      const double iv = 1.0 / C.vol[E.y_off + j];
+      for (int i = lane; i < nx; i += 64) buf0[i] = make_double2(r_in[c0 + i] * iv, r_in[c0 + nx + i] * iv);
+    } else if (q_in) {
+      for (int i = lane; i < nx; i += 64) {
+        const long long QA = q_in[c0 + i - q_shift], QB = q_in[c0 + nx + i - q_shift];
+        rq48[0] += QA;
+        rq48[1] += QB;
+        buf0[i] = make_double2((double)QA * rsc, (double)QB * rsc);
+      }
+    } else {
+      // particle-parallel over the pair's sorted slots: coalesced charge/key
+      // loads, per-cell integer sums in LDS
+      for (int s = s0 + lane; s < s1; s += 64) {
+        const double qv = C.sq[s];
+        const unsigned i = (unsigned)(C.skey[s] - (int)c0);
+        const long long Q = fixed_round(qv, kFixDep, &ovf);
+        const long long Q32 = fixed_round(qv, kFixQcum, &ovf);
+        if (i < (unsigned)nx) rq32[0] += Q32; else rq32[1] += Q32;
+        if (i < (unsigned)n2) atomicAdd(reinterpret_cast<unsigned long long*>(&bins[i]), (unsigned long long)Q);
+      }
     }
   }
-  if (do_stats) {
-    rq48 = wave_sum(rq48);
-    rq32 = wave_sum(rq32);
-    if (threadIdx.x == 0) {
-      longlong2 acc = C.rowacc[E.row_off + jk];
-      acc.x += cnt;
-      acc.y += rq32;
-      C.rowacc[E.row_off + jk] = acc;
-      C.rowq[E.row_off + jk] = rq48;
+  __syncthreads();
+  if (ok && parts) {
+    for (int i = lane; i < nx; i += 64) {
+      const long long QA = bins[i], QB = bins[nx + i];
+      if (C.qdep) {
+        C.qdep[c0 + i] = QA;
+        C.qdep[c0 + nx + i] = QB;
+      }
+      rq48[0] += QA;
+      rq48[1] += QB;
+      buf0[i] = make_double2((double)QA * rsc, (double)QB * rsc);
+    }
+  }
+  if (ok && do_stats) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const long long a48 = wave_sum(rq48[h]), a32 = wave_sum(rq32[h]);
+      if (lane == 0) {
+        const long long r = E.row_off + jkA + h;
+        longlong2 acc = C.rowacc[r];
+        acc.x += cnt[h];
+        acc.y += a32;
+        C.rowacc[r] = acc;
+        C.rowq[r] = a48;
+      }
     }
   }
   if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
   __syncthreads();
-  FftPlan P = E.fx;
-  double2* res = lds_fft<false>(buf0, buf1, 1, nx, P, tw);
-  double2* out = C.spec + E.s_off + (long long)jk * E.nhp;
-  for (int m = threadIdx.x; m < E.nh; m += 64) out[m] = res[m];
+  pair_forward_store(C, E, jkA, buf0, buf1, tw, lane, ok);
+}
+
+// ---------------------------------------------------------------------------
+// incremental sort fused with the deposit and the x transform, one wave per
+// row pair (j, k), (j, k+1) of the new order (2 nx consecutive cells).  The
+// state is stored in the previous sort's order, so the pair's members are
+// among the slots of rows (j + dj, k + dk), |dj| <= 1, dk in [-1, 2] (k
+// periodic) -- at most 6 contiguous slot ranges -- plus the far list.  The
+// push counted the members of every row pair (pair_cnt); their scan is ps.
+// ---------------------------------------------------------------------------
+struct RowSegs {
+  int a[6], off[7];  // segment u: slots [a[u], a[u] + off[u+1] - off[u])
+};
+
+// two segments per dj (the second one empty unless the k range wraps); all
+// indices static so that the segments stay in registers
+// (slot bounds clamped to [0, n_tot]: memory-safe even for inconsistent ranges)
+__device__ __forceinline__ void pair_segments(const int* __restrict__ rs, long long rb, int ny, int nz, int j,
+                                              int k, int n_tot, RowSegs& S) {
+  S.off[0] = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int j2 = j + d - 1;
+    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    if (j2 >= 0 && j2 < ny) {
+      const long long base = rb + (long long)j2 * nz;
+      long long s0, e0, s1 = 0, e1 = 0;  // rows [s0, e0) and [s1, e1)
+      if (k >= 1 && k + 2 <= nz - 1) {
+        s0 = base + k - 1;
+        e0 = base + k + 3;
+      } else if (k == 0) {
+        s0 = base;
+        e0 = base + 3;
+        s1 = base + nz - 1;
+        e1 = base + nz;
+      } else {  // k == nz - 2
+        s0 = base + nz - 3;
+        e0 = base + nz;
+        s1 = base;
+        e1 = base + 1;
+      }
+      a0 = min(max(rs[s0], 0), n_tot);
+      b0 = min(max(rs[e0], 0), n_tot);
+      if (e1 > s1) {
+        a1 = min(max(rs[s1], 0), n_tot);
+        b1 = min(max(rs[e1], 0), n_tot);
+      }
+    }
+    S.a[2 * d] = a0;
+    S.off[2 * d + 1] = S.off[2 * d] + max(b0 - a0, 0);
+    S.a[2 * d + 1] = a1;
+    S.off[2 * d + 2] = S.off[2 * d + 1] + max(b1 - a1, 0);
+  }
+}
+
+// slot of flattened candidate t < S.off[6]
+__device__ __forceinline__ int seg_slot(const RowSegs& S, int t) {
+  int s = S.a[0] + t;
+#pragma unroll
+  for (int u = 1; u < 6; ++u)
+    if (t >= S.off[u]) s = S.a[u] + (t - S.off[u]);
+  return s;
+}
+
+constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight together)
+
+// LDS of one wave: member list {id, old slot} (8 B), member index by cell
+// position (u16), member cell (u16) -- later the first FFT buffer -- then the
+// int64 cell charges (later the second FFT buffer), cell counts, cell
+// starts/cursors
+__host__ __device__ inline size_t sortdep_lists_bytes(int nx_max, int cap) {
+  const size_t lists = (size_t)cap * 12, buf = (size_t)nx_max * 16;
+  return ((lists > buf ? lists : buf) + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t sortdep_wave_bytes(int nx_max, int cap) {
+  return sortdep_lists_bytes(nx_max, cap) + (size_t)nx_max * 32 + 16;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int one, PState in,
+                                                         const int* __restrict__ blk_off, int nmax, int cap) {
+  extern __shared__ __align__(16) unsigned char lds_b[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2* tw = reinterpret_cast<double2*>(lds_b);
+  unsigned char* base = lds_b + (size_t)nmax * 16 + (size_t)w * sortdep_wave_bytes(nmax, cap);
+  const size_t ub = sortdep_lists_bytes(nmax, cap);
+  int2* A = reinterpret_cast<int2*>(base);
+  unsigned short* Bm = reinterpret_cast<unsigned short*>(base + (size_t)cap * 8);
+  unsigned short* Ai = Bm + cap;
+  double2* buf0 = reinterpret_cast<double2*>(base);
+  long long* Q = reinterpret_cast<long long*>(base + ub);  // 2 nx int64, read into buf0 before buf1 is used
+  double2* buf1 = reinterpret_cast<double2*>(Q);
+  int* cnt = reinterpret_cast<int*>(Q + 2 * nmax);
+  int* pre = cnt + 2 * nmax;
+  int* nmem = pre + 2 * nmax;
+
+  Ens E;
+  int lb;
+  block_ens(C, Eone, one, blk_off, 0, E, lb);
+  const int nx = E.nx, ny = E.ny, nz = E.nz, n2 = 2 * E.nx;
+  const int lp = lb * kPairsPerBlock + w;
+  const bool ok = lp < ((ny * nz) >> 1);
+  const int jkA = ok ? 2 * lp : 0;
+  const int j = jkA / nz, k = jkA - j * nz;
+  const long long rA = E.row_off + jkA;
+  const long long c0 = E.c_off + (long long)jkA * nx, c1 = c0 + n2;
+  for (int t = threadIdx.x; t < nx; t += kBlock) tw[t] = C.tw[E.fx.tw_off + t];
+  RowSegs S;
+  int r0 = 0, rm = 0, r1 = 0, T = 0, TT = 0;
+  if (ok) {
+    pair_segments(C.rs_old, E.row_off, ny, nz, j, k, (int)C.n_tot, S);
+    // the pair's slot range (clamped: writes stay inside the arrays whatever the counts)
+    r0 = min(max(C.ps[rA >> 1], 0), (int)C.n_tot);
+    r1 = min(max(C.ps[(rA >> 1) + 1], r0), (int)C.n_tot);
+    T = S.off[6];
+    TT = T + min(C.far_n[1], (int)C.n_tot);
+    for (int i = lane; i < n2; i += 64) {
+      cnt[i] = 0;
+      Q[i] = 0;
+    }
+    if (lane == 0) {
+      *nmem = 0;
+      // consumed by the pair scan: restart the count for this step's push
+      C.pair_cnt[rA >> 1] = 0;
+    }
+  }
+  const int M = r1 - r0;
+  const bool fast = M <= cap;  // wave-uniform
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int nlist = 0;               // wave-uniform length of the member list
+  __syncthreads();
+  // pass 1: cell counts; the fast path also lists the members (positions by
+  // ballot: no same-address LDS atomics); the loop is wave-uniform
+  for (int tb = 0; tb < TT; tb += 64 * kCand) {
+    const int t0 = tb + lane;
+    int sl[kCand], c[kCand], idv[kCand];
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) {
+      const int t = t0 + 64 * u;
+      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+    }
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
+    if (fast) {
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= c0 && c[u] < c1) ? in.id[sl[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kCand; ++u) {
+      const bool hit = c[u] >= c0 && c[u] < c1;
+      const unsigned long long mask = __ballot(hit);
+      if (hit) {
+        const int i = c[u] - (int)c0;
+        atomicAdd(&cnt[i], 1);
+        if (fast) {
+          const int m = nlist + __popcll(mask & below);
+          if (m < cap) {
+            A[m] = make_int2(idv[u], sl[u]);
+            Ai[m] = (unsigned short)i;
+          }
+        }
+      }
+      nlist += __popcll(mask);
+    }
+  }
+  if (lane == 0) *nmem = nlist;
+  __syncthreads();
+  if (ok) {
+    // exclusive scan of the pair's cell counts: lane owns cells [lane*mm, lane*mm + mm)
+    const int mm = (n2 + 63) >> 6;
+    int v = 0;
+    for (int u = 0; u < mm; ++u) {
+      const int i = lane * mm + u;
+      if (i < n2) v += cnt[i];
+    }
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    int ex = incl - v;
+    for (int u = 0; u < mm; ++u) {
+      const int i = lane * mm + u;
+      if (i < n2) {
+        pre[i] = ex;
+        C.start[c0 + i] = r0 + min(ex, M);
+        ex += cnt[i];
+      }
+    }
+    if (rA + 2 == C.n_rows && lane == 0) C.start[c1] = r1;
+  }
+  __syncthreads();
+  if (ok) {
+    // row slot ranges of the new order (the stored order of the next step)
+    rm = r0 + min(pre[nx], M);
+    if (lane == 0) {
+      C.rs_new[rA] = r0;
+      C.rs_new[rA + 1] = rm;
+      if (rA + 2 == C.n_rows) C.rs_new[rA + 2] = r1;
+    }
+  }
+  // members bucketed by cell (unordered within a cell); pre[] becomes the cell ends
+  if (fast) {
+    const int nm = min(*nmem, M);
+    for (int m = lane; m < nm; m += 64) {
+      const int pos = atomicAdd(&pre[Ai[m]], 1);
+      if (pos < M) Bm[pos] = (unsigned short)m;
+    }
+  } else {
+    // more members than the LDS list holds: a second candidate pass through C.tmp
+    for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
+      int sl[kCand], c[kCand], idv[kCand];
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        const int t = t0 + 64 * u;
+        sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+      }
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= c0 && c[u] < c1) ? in.id[sl[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        if (c[u] >= c0 && c[u] < c1) {
+          const int slot = r0 + atomicAdd(&pre[c[u] - (int)c0], 1);
+          if (slot < r1) C.tmp[slot] = make_int4(idv[u], sl[u], c[u], 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // rank each member by id inside its cell; write the sorted arrays; deposit
+  bool ovf = false;
+  long long rq32[2] = {0, 0};
+  const int nmv = fast ? min(*nmem, M) : M;
+  for (int t = lane; t < M; t += 64) {
+    int id, p, i;
+    if (fast) {
+      const int m = Bm[t];
+      if (m >= nmv) continue;  // members inconsistent with the row counts: never by construction
+      const int2 e = A[m];
+      id = e.x;
+      p = e.y;
+      i = Ai[m];
+    } else {
+      const int4 rec = C.tmp[r0 + t];
+      id = rec.x;
+      p = rec.y;
+      i = rec.z - (int)c0;
+    }
+    if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
+    const int b = min(pre[i], M), a = max(pre[i] - cnt[i], 0);
+    const double q = in.q[p], x = in.x[p], y = in.y[p], z = in.z[p];
+    int rk = 0;
+    if (b - a > 1) {
+      if (fast) {
+        for (int u = a; u < b; ++u) {
+          const int mu = Bm[u];
+          rk += (mu < nmv && A[mu].x < id) ? 1 : 0;
+        }
+      } else {
+        for (int u = a; u < b; u += 4) {
+          int idu[4];
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) idu[vv] = (u + vv < b) ? C.tmp[r0 + u + vv].x : 0x7fffffff;
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) rk += (idu[vv] < id) ? 1 : 0;
+        }
+      }
+    }
+    const int o = r0 + a + rk;
+    C.perm[o] = p;
+    C.skey[o] = (int)c0 + i;
+    C.sq[o] = q;
+    C.sx[o] = x;
+    C.sy[o] = y;
+    C.sz[o] = z;
+    const long long Qd = fixed_round(q, kFixDep, &ovf);
+    const long long Q32 = fixed_round(q, kFixQcum, &ovf);
+    if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&Q[i]), (unsigned long long)Qd);
+  }
+  __syncthreads();  // member lists read: the FFT buffers may overwrite them
+  const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
+  long long rq48[2] = {0, 0};
+  if (ok) {
+    for (int i = lane; i < nx; i += 64) {
+      const long long QA = Q[i], QB = Q[nx + i];
+      if (C.qdep) {
+        C.qdep[c0 + i] = QA;
+        C.qdep[c0 + nx + i] = QB;
+      }
+      rq48[0] += QA;
+      rq48[1] += QB;
+      buf0[i] = make_double2((double)QA * rsc, (double)QB * rsc);
+    }
+    const int cntr[2] = {rm - r0, r1 - rm};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const long long a48 = wave_sum(rq48[h]), a32 = wave_sum(rq32[h]);
+      if (lane == 0) {
+        longlong2 acc = C.rowacc[rA + h];
+        acc.x += cntr[h];
+        acc.y += a32;
+        C.rowacc[rA + h] = acc;
+        C.rowq[rA + h] = a48;
+      }
+    }
+  }
+  if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+  __syncthreads();
+  pair_forward_store(C, E, jkA, buf0, buf1, tw, lane, ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,7 +857,7 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int
   }
   __syncthreads();
   FftPlan P = E.fz;
-  double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw);
+  double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw, threadIdx.x, blockDim.x);
   const double sc = INV ? 1.0 / (double)nz : 1.0;
   for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
     const int k = fdiv32(t, mw, w), c = t - k * w;
@@ -1011,45 +1070,51 @@ __global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, Ens Eone, int one, co
 }
 
 // ---------------------------------------------------------------------------
-// inverse FFT along x (Hermitian half spectrum -> real): one wave per row
+// inverse FFT along x on row pairs: Z = X_A + i X_B over the full line (each
+// half spectrum extended by conjugate symmetry, the imaginary parts of its
+// mean and Nyquist terms dropped), one inverse complex transform, phi_A and
+// phi_B are the real and imaginary parts
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_ifftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
-                                              int nmax, double* __restrict__ phi_out, long long phi_shift) {
+__global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
+                                                       int blk0, int nmax, double* __restrict__ phi_out,
+                                                       long long phi_shift) {
   extern __shared__ double2 lds[];
-  double2* buf0 = lds;
-  double2* buf1 = lds + nmax;
-  double2* tw = lds + 2 * nmax;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2* tw = lds;
+  double2* buf0 = lds + nmax + (size_t)w * 2 * nmax;
+  double2* buf1 = buf0 + nmax;
   Ens E;
   int lb;
-  if (one) {
-    E = Eone;
-    lb = blockIdx.x;
-  } else {
-    const int gb = blk0 + blockIdx.x;
-    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-    E = C.ens[e];
-    lb = gb - blk_off[e];
-  }
-  const int nx = E.nx, nh = E.nh;
-  const int jk = lb;
-  const double2* sp = C.spec + E.s_off + (long long)jk * E.nhp;
-  for (int t = threadIdx.x; t < nx; t += 64) {
-    tw[t] = C.tw[E.fx.tw_off + t];
-    double2 v;
-    if (t < nh) {
-      v = sp[t];
-    } else {
-      v = sp[nx - t];
-      v.y = -v.y;
+  block_ens(C, Eone, one, blk_off, blk0, E, lb);
+  const int nx = E.nx, nz = E.nz, half = E.nx >> 1;
+  const int lp = lb * kPairsPerBlock + w;
+  const bool ok = lp < ((E.ny * nz) >> 1);
+  const int jkA = ok ? 2 * lp : 0;
+  for (int t = threadIdx.x; t < nx; t += kBlock) tw[t] = C.tw[E.fx.tw_off + t];
+  if (ok) {
+    const double2* sa = C.spec + E.s_off + (long long)jkA * E.nhp;
+    const double2* sb = sa + E.nhp;
+    for (int t = lane; t < nx; t += 64) {
+      const int m = t <= half ? t : nx - t;
+      const double2 a = sa[m], b = sb[m];
+      double2 z;
+      if (t == 0 || t == half) z = make_double2(a.x, b.x);
+      else if (t < half) z = make_double2(a.x - b.y, a.y + b.x);
+      else z = make_double2(a.x + b.y, b.x - a.y);
+      buf0[t] = z;
     }
-    buf0[t] = v;
   }
   __syncthreads();
-  FftPlan P = E.fx;
-  double2* res = lds_fft<true>(buf0, buf1, 1, nx, P, tw);
+  double2* res = lds_fft<true>(buf0, buf1, 1, nx, E.fx, tw, lane, 64);
+  if (!ok) return;
   const double sc = 1.0 / (double)nx;
-  double* out = phi_out + (E.c_off - phi_shift) + (long long)jk * nx;
-  for (int t = threadIdx.x; t < nx; t += 64) out[t] = res[t].x * sc;
+  double* outA = phi_out + (E.c_off - phi_shift) + (long long)jkA * nx;
+  double* outB = outA + nx;
+  for (int t = lane; t < nx; t += 64) {
+    const double2 v = res[t];
+    outA[t] = v.x * sc;
+    outB[t] = v.y * sc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,6 +1149,21 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
 // the particle push: one thread per sorted slot s, E uniform over the lanes
 // that share an ensemble (scalar descriptor loads)
 // ---------------------------------------------------------------------------
+// counts the particle's new row pair for the next sort.  The active lanes of
+// the wave merge runs of equal keys first (lanes are in slot order, so
+// neighbours mostly share a pair): one device atomic per run.
+__device__ __forceinline__ void pair_count(int* __restrict__ pair_cnt, int key) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long act = __ballot(1);
+  const int prevk = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || !((act >> (lane - 1)) & 1ull) || prevk != key;
+  const unsigned long long heads = __ballot(head);
+  if (!head) return;
+  const unsigned long long after = heads & ~((2ull << lane) - 1ull);  // later heads
+  const unsigned long long upto = after ? ((after & (~after + 1ull)) - 1ull) : ~0ull;
+  atomicAdd(&pair_cnt[key], __popcll(act & upto & ~((1ull << lane) - 1ull)));
+}
+
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
                                          int p, int c, signed char* __restrict__ wall_rec) {
   Fwd F;
@@ -1154,12 +1234,18 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   const int nj = y_cell_from(yf, ny, yr, j);
   const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
   out.key[s] = key;
-  // rows beyond the 3 x 3 neighbourhood (k periodic) go on the far list
-  const int dk = abs(nk - F.k);
-  if (abs(nj - j) > 1 || (dk > 1 && dk < nz - 1)) {
+  // the next sort gathers row pair (nj, kb), (nj, kb + 1), kb = nk & ~1, from
+  // rows nj + [-1, 1] x kb + [-1, 2] (k periodic); a particle outside goes on
+  // the far list
+  const int kb = nk & ~1;
+  int dk = F.k - kb + 1;  // position of the old k in kb - 1 ... kb + 2 (mod nz)
+  if (dk < 0) dk += nz;
+  else if (dk >= nz) dk -= nz;
+  if (abs(nj - j) > 1 || dk > 3) {
     const int f = atomicAdd(&C.far_n[0], 1);
     if (f < C.n_tot) C.far[f] = s;
   }
+  pair_count(C.pair_cnt, (int)((E.row_off + (long long)nj * nz + nk) >> 1));
 }
 
 __global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
@@ -1168,22 +1254,23 @@ __global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PStat
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
     C.rs_old[r] = C.rs_new[r];
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
-  if (s >= C.n_tot) return;
-  const int p = C.perm[s];
-  if (perm_rec) perm_rec[s] = p;
-  const int c = C.skey[s];
-  if (one) {
-    push_one(C, Eone, in, out, s, p, c, wall_rec);
-    return;
-  }
-  const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
-  // waterfall over the ensembles present in this wave (usually one)
-  bool done = false;
-  while (!done) {
-    const int e = __builtin_amdgcn_readfirstlane(e_lane);
-    if (e_lane == e) {
-      push_one(C, C.ens[e], in, out, s, p, c, wall_rec);
-      done = true;
+  if (s < C.n_tot) {
+    const int p = C.perm[s];
+    if (perm_rec) perm_rec[s] = p;
+    const int c = C.skey[s];
+    if (one) {
+      push_one(C, Eone, in, out, s, p, c, wall_rec);
+    } else {
+      const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
+      // waterfall over the ensembles present in this wave (usually one)
+      bool done = false;
+      while (!done) {
+        const int e = __builtin_amdgcn_readfirstlane(e_lane);
+        if (e_lane == e) {
+          push_one(C, C.ens[e], in, out, s, p, c, wall_rec);
+          done = true;
+        }
+      }
     }
   }
 }
@@ -1232,6 +1319,8 @@ __global__ __launch_bounds__(kBlock) void k_get_state(PState S, PIn out, long lo
 // ---------------------------------------------------------------------------
 }  // namespace tf
 
+#include <algorithm>
+
 #include "launch.h"
 
 namespace tf {
@@ -1260,32 +1349,47 @@ hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool
     k_rows_from_start<<<(int)((C.n_rows + kBlock) / kBlock), kBlock, 0, st>>>(C);
     return hipGetLastError();
   }
+  // incremental: the row slot ranges from the push's row counts
+  scan_into(C, C.pair_cnt, C.n_rows / 2, C.ps, st);
+  return hipGetLastError();
+}
+
+int sortdep_cap(const Ctx& C, int nx_max, int want) {
+  // member list per row pair: at least what the FFT buffer it shares leaves
+  // free, by default about 2.5 times the mean pair size, within 64 KiB of LDS
+  // per block
+  if (want < 0) return 0;
+  const long long mean = C.n_rows > 0 ? (2 * C.n_tot + C.n_rows - 1) / C.n_rows : 0;
+  long long cap = want > 0 ? want : std::max<long long>((16LL * nx_max) / 12, ((5 * mean / 2 + 63) / 64) * 64);
+  const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
+  cap = std::min(cap, lim);
+  return (int)std::max<long long>(cap, 0) & ~7;
+}
+
+hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, hipStream_t st) {
+  const int nb = G.fp_blk[C.n_ens];
+  if (nb == 0) return hipSuccess;
   const int one = (C.n_ens == 1) ? 1 : 0;
-  const int nbr = (int)((C.n_rows + kRowsPerBlock - 1) / kRowsPerBlock);
-  k_row_count<<<nbr, kBlock, 0, st>>>(C, G.eh[0], one, cur.key);
-  scan_into(C, C.row_cnt, C.n_rows, C.rs_new, st);
-  // member capacity per row in LDS: about four times the mean row size
-  const long long mean = C.n_rows > 0 ? (C.n_tot + C.n_rows - 1) / C.n_rows : 1;
-  int cap = 128;
-  while (cap < 4 * mean && cap < 1024) cap *= 2;
-  const size_t lds = (size_t)kRowsPerBlock * row_lds_bytes(G.nx_max, cap);
-  k_row_place<<<nbr, kBlock, lds, st>>>(C, G.eh[0], one, cur, G.nx_max, cap);
+  const int cap = sortdep_cap(C, G.nx_max, G.sort_cap);
+  const size_t lds = (size_t)G.nx_max * 16 + (size_t)kPairsPerBlock * sortdep_wave_bytes(G.nx_max, cap);
+  k_row_sort_dep<<<nb, kBlock, lds, st>>>(C, G.eh[0], one, cur, G.d_fp_blk, G.nx_max, cap);
   return hipGetLastError();
 }
 
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
-                          int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in) {
+                          int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in, bool x_done) {
   (void)key;
+  (void)q;
   auto mark = [&](int i) {
     if (ev) hipEventRecord(ev[i], st);
   };
   const int one = (e1 - e0 == 1) ? 1 : 0;
   const Ens Eone = G.eh[e0];
-  const int b0 = G.fx_blk[e0], nb = G.fx_blk[e1] - b0;
-  const size_t lx = (size_t)3 * G.nx_max * sizeof(double2);
-  if (nb > 0)
-    k_dep_fftx<<<nb, 64, lx, st>>>(C, Eone, one, q, G.d_fx_blk, b0, G.nx_max, q_in, q_shift, r_in, do_stats);
+  const int b0 = G.fp_blk[e0], nb = G.fp_blk[e1] - b0;
+  const size_t lx = (size_t)(1 + 2 * kPairsPerBlock) * G.nx_max * sizeof(double2);
+  if (nb > 0 && !x_done)
+    k_pair_fftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, q_in, q_shift, r_in, do_stats);
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
   const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);  // wz: largest over ensembles
@@ -1304,7 +1408,7 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   mark(2);
   if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(3);
-  if (nb > 0) k_ifftx<<<nb, 64, lx, st>>>(C, Eone, one, G.d_fx_blk, b0, G.nx_max, phi_out, phi_shift);
+  if (nb > 0) k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift);
   mark(4);
   return hipGetLastError();
 }

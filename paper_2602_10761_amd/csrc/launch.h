@@ -21,28 +21,32 @@ struct Carver {
 // Block tables of the cell-structured kernels: blocks of ensemble e are
 // [xx_blk[e], xx_blk[e+1]) (host copies) / d_xx_blk (device copies).
 struct LaunchGeo {
-  int fx_rpb;      // unused (one wave per row)
   int nx_max, nz_max;
   int wz;          // spectral columns per block in the z transforms
   int ny_max;
   int tri_m;       // Fourier modes per block in the tridiagonal solves
   int tri_pcr;     // 1: cyclic reduction, 0: Thomas
   int tri_eq_max;  // largest tm * (ny + 1) over the ensembles (LDS sizing)
-  const int* fx_blk;
+  int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
+  const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block
   const int* fz_blk;
   const int* tri_blk;
-  const int* d_fx_blk;
+  const int* d_fp_blk;
   const int* d_fz_blk;
   const int* d_tri_blk;
   const Ens* eh;   // host copies of the ensemble descriptors
 };
 
 // full: counting sort from scratch (after init or a state upload); otherwise
-// the incremental row sort, valid when `cur` was written by the last push
+// the row scan of the incremental sort, valid when `cur` was written by the
+// last push (the sort itself then runs fused with the deposit: launch_sort_dep)
 hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool full, hipStream_t st);
+hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, hipStream_t st);
+// x_done: the deposit and x transform already ran (launch_sort_dep)
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
-                          int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr);
+                          int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr,
+                          bool x_done = false);
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);

@@ -78,9 +78,10 @@ struct Ctx {
   // order, except the particles listed in `far`
   const long long* r_off;    // [n_ens+1] (j, k) row offsets
   long long n_rows;
-  int* row_cnt;              // [n_rows]   members of each row after this step's sort
-  int* rs_old;               // [n_rows+1] slot range of each row in the stored order
-  int* rs_new;               // [n_rows+1] slot range of each row after this step's sort
+  int* pair_cnt;             // [n_rows/2]   members of each row pair (rows 2p, 2p+1) after this step's sort
+  int* ps;                   // [n_rows/2+1] slot range of each row pair after this step's sort
+  int* rs_old;               // [n_rows+1]   slot range of each row in the stored order
+  int* rs_new;               // [n_rows+1]   slot range of each row after this step's sort
   int* far;                  // [n_tot]    slots of particles whose row moved by 2+ in j or k
   int* far_n;                // [2]        live count (push appends), snapshot for the sort
   int* scan_part;            // scan block partials

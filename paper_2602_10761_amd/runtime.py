@@ -42,7 +42,7 @@ class TfParticles(Structure):
 
 
 class TfTuning(Structure):
-    _fields_ = [("fx_rows", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("reserved", c_int32)]
+    _fields_ = [("sort_cap", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("reserved", c_int32)]
 
 
 class TfStatsOut(Structure):
@@ -92,9 +92,9 @@ class TriboError(RuntimeError):
     pass
 
 
-def set_tuning(fx_rows: int = 0, fz_cols: int = 0, tri_modes: int = 0):
+def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0):
     """Tile shapes for every later TriboSim of this process (0 = built-in choice)."""
-    t = TfTuning(fx_rows, fz_cols, tri_modes, 0)
+    t = TfTuning(sort_cap, fz_cols, tri_modes, 0)
     _check(lib().tf_set_tuning(ctypes.byref(t)))
 
 
