@@ -19,6 +19,8 @@ from . import workload as W
 CACHE = os.environ.get("TRIBO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                         "tune_cache.json"))
 FZ_COLS = (1, 2, 4, 8)
+# bumped whenever the tiled kernels change shape semantics (older entries are ignored)
+KERNEL_REV = 3
 
 
 def _arch() -> str:
@@ -27,11 +29,14 @@ def _arch() -> str:
 
 
 def _key(arch: str, mesh: Tuple[int, int, int]) -> str:
-    return f"{arch}/{mesh[0]}x{mesh[1]}x{mesh[2]}"
+    return f"{arch}/r{KERNEL_REV}/{mesh[0]}x{mesh[1]}x{mesh[2]}"
 
 
 def tri_candidates(ny: int):
-    out = [m for m in (1, 2, 4, 6, 8, 12, 16, 24, 32) if m * ny <= 2048 and 5 * 8 * m * (ny + 1) <= 65536]
+    """Modes per tridiagonal tile: the tile (32 B per mode and padded row) fits the
+    160 KiB of LDS of a block."""
+    nyp = (ny + 15) // 16 * 16
+    out = [m for m in (4, 6, 8, 10, 12, 15, 16, 20, 24, 32, 40, 48, 64) if 32 * m * nyp + 8 * nyp <= 163840]
     return out or [1]
 
 

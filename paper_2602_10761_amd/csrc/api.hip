@@ -53,7 +53,8 @@ bool radix_plan(int n, FftPlan* P) {
 struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
-  int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_m = 16, tri_pcr = 1, tri_eq_max = 0;
+  int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_eq_max = 0;
+  long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
   std::vector<int> fp_blk, fz_blk, tri_blk;
   std::map<int, int> tw_off;
@@ -89,6 +90,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->n_tot += E.n_particles;
     S->c_tot += ncell;
     S->s_tot += (long long)E.ny * E.nz * nhp;
+    S->tf_tot += (long long)E.ny * E.nz * nh;
     S->rows += (long long)E.ny * E.nz;
     S->y_tot += E.ny + 1;
     S->kx_tot += nh;
@@ -106,7 +108,6 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
   // tridiagonal: cyclic reduction holds tm * ny equations (5 doubles each, at
   // most 8 per thread); Thomas (some ny > 256) holds tm columns (32 B per row)
-  S->tri_pcr = S->ny_max <= 256 ? 1 : 0;
   S->e_wz.assign(n_ens, 2);
   S->e_tm.assign(n_ens, 1);
   S->wz = 1;
@@ -121,21 +122,21 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     }
     const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
     int tm;
-    if (S->tri_pcr)
-      tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, 1024 / E.ny);
-    else
-      tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, std::min(16, 65536 / (32 * E.ny)));
-    if (S->tri_pcr && tm * E.ny > 8 * kBlock) return fail(TF_ESIZE, "tri_modes * ny exceeds 2048");
+    // tridiagonal tile: tm modes x padded ny rows of spectrum and factors in LDS
+    // (32 B each); default about 64 KiB per block
+    const int nyp = tri_pad(E.ny);
+    tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, std::min(kBlock / 2, (65536 - 8 * nyp) / (32 * nyp)));
+    tm = std::min(tm, kBlock / 2);
     S->e_wz[e] = wz;
     S->e_tm[e] = tm;
     S->wz = std::max(S->wz, wz);
-    S->tri_eq_max = std::max(S->tri_eq_max, S->tri_pcr ? tm * (E.ny + 1) : tm * E.ny);
+    S->tri_eq_max = std::max(S->tri_eq_max, tm * tri_pad(E.ny));
   }
-  S->tri_m = 0;
   const size_t lds_fx = (size_t)9 * S->nx_max * 16;  // twiddles + 4 waves x 2 line buffers
   const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
-  const size_t lds_tri = S->tri_pcr ? (size_t)5 * 8 * S->tri_eq_max : (size_t)S->tri_eq_max * 32;
-  if (lds_fx > 65536 || lds_fz > 65536 || lds_tri > 65536) return fail(TF_ESIZE, "tile shapes exceed 64 KiB of LDS");
+  const size_t lds_tri = (size_t)S->tri_eq_max * 32 + (size_t)tri_pad(S->ny_max) * 8;
+  if (lds_fx > 65536 || lds_fz > (size_t)kLdsMax || lds_tri > (size_t)kLdsMax)
+    return fail(TF_ESIZE, "tile shapes exceed the LDS of a block");
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
@@ -215,6 +216,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.kx2 = cv.take<double>(S.kx_tot);
   C.kz2 = cv.take<double>(S.kz_tot);
   C.tw = cv.take<double2>(S.tw_tot);
+  C.tfac = cv.take<double2>(S.tf_tot);
   C.stats = cv.take<long long>(S.st_tot);
   C.rowq = cv.take<long long>(S.rows);
   C.rowacc = cv.take<longlong2>(S.rows);
@@ -240,7 +242,6 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   const long long nbs = (S.c_tot + 4 * kBlock - 1) / (4 * kBlock);
   C.scan_part = cv.take<int>(nbs + 1);
   C.spec = cv.take<double2>(S.s_tot);
-  C.cp = cv.take<double>(S.s_tot);
   C.phi = cv.take<double>(S.c_tot);
   C.qdep = (flags & TF_INIT_KEEP_DEPOSIT) ? cv.take<long long>(S.c_tot) : nullptr;
   std::vector<TrajBuf> traj;
@@ -352,7 +353,7 @@ int tf_set_tuning(const tf_tuning* t) {
     return TF_OK;
   }
   if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 64)
+      t->tri_modes > 128)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
   return TF_OK;
@@ -365,7 +366,7 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     g_class_tune.erase(key);
     return TF_OK;
   }
-  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 64)
+  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 128)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -418,7 +419,10 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->p_off.assign(n_ens + 1, 0);
   h->c_off.assign(n_ens + 1, 0);
   int y_off = 0, kx_off = 0, kz_off = 0, st_off = 0;
-  long long s_off = 0, row_off = 0;
+  long long s_off = 0, row_off = 0, tf_off = 0;
+  // Thomas factors of the y-systems, per Fourier mode (fixed by the mesh):
+  // tfac[tf_off + mode * ny + j] = (1 / pivot_j, c'_j)
+  std::vector<double2> tfac(S.tf_tot);
   std::vector<long long> r_offs(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& T = ens[e];
@@ -432,6 +436,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.p_off = h->p_off[e];
     E.c_off = h->c_off[e];
     E.s_off = s_off;
+    E.tf_off = tf_off;
     E.row_off = row_off;
     E.y_off = y_off;
     E.kx_off = kx_off;
@@ -492,6 +497,25 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     h->p_off[e + 1] = h->p_off[e] + T.n_particles;
     h->c_off[e + 1] = h->c_off[e] + (long long)T.nx * T.ny * T.nz;
     s_off += (long long)ny * T.nz * E.nhp;
+    {
+      const int nm = E.nh * T.nz;
+      const double* AM = &am[y_off];
+      const double* AP = &ap[y_off];
+      for (int mz = 0; mz < T.nz; ++mz)
+        for (int m = 0; m < E.nh; ++m) {
+          const int mode = mz * E.nh + m;
+          const double K2 = kz2[kz_off + mz] + kx2[kx_off + m];
+          double cprev = 0.0;
+          for (int j = 0; j < ny; ++j) {
+            // -am_j phi_{j-1} + (am_j + ap_j + K2) phi_j - ap_j phi_{j+1} = rho_j
+            const double piv = ((AM[j] + AP[j]) + K2) + (j > 0 ? AM[j] * cprev : 0.0);
+            const double cp = (-AP[j]) / piv;
+            tfac[tf_off + (size_t)mode * ny + j] = make_double2(1.0 / piv, cp);
+            cprev = cp;
+          }
+        }
+      tf_off += (long long)ny * nm;
+    }
     row_off += (long long)ny * T.nz;
     r_offs[e + 1] = row_off;
     y_off += ny + 1;
@@ -523,6 +547,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->C.kx2, kx2);
   UP(h->C.kz2, kz2);
   UP(h->C.tw, tw);
+  UP(h->C.tfac, tfac);
 #undef UP
   if (he == hipSuccess) he = hipMemsetAsync(h->C.stats, 0, sizeof(long long) * S.st_tot, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
@@ -549,8 +574,6 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.nz_max = S.nz_max;
   h->G.wz = S.wz;
   h->G.ny_max = S.ny_max;
-  h->G.tri_m = S.tri_m;
-  h->G.tri_pcr = S.tri_pcr;
   h->G.tri_eq_max = S.tri_eq_max;
   h->G.sort_cap = g_tune.sort_cap;
   h->G.fp_blk = h->S.fp_blk.data();

@@ -366,6 +366,27 @@ __device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const F
 }
 
 // ---------------------------------------------------------------------------
+// strided copy global -> LDS with U loads per thread in flight before the
+// first store (a plain strided loop waits for every load in turn)
+// ---------------------------------------------------------------------------
+template <int U, class Ld, class St>
+__device__ __forceinline__ void staged_copy(int total, int tid, int nthr, Ld ld, St st) {
+  for (int t0 = tid; t0 < total; t0 += nthr * U) {
+    decltype(ld(0)) r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * nthr;
+      if (t < total) r[u] = ld(t);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * nthr;
+      if (t < total) st(t, r[u]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // wave-wide integer sum
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ long long wave_sum(long long v) {
@@ -848,13 +869,20 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int
     const int j = fdiv32(lb, magic32(nchunk), nchunk);
   const int m0 = (lb - j * nchunk) * wz;
   const int w = min(wz, nh - m0);
-  for (int t = threadIdx.x; t < nz; t += blockDim.x) tw[t] = C.tw[E.fz.tw_off + t];
+  const double2* __restrict__ twg = C.tw + E.fz.tw_off;
+  staged_copy<4>(nz, threadIdx.x, blockDim.x, [&](int t) { return twg[t]; }, [&](int t, double2 v) { tw[t] = v; });
   double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
   const unsigned mw = magic32(w);
-  for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
-    const int k = fdiv32(t, mw, w), c = t - k * w;
-    buf0[c * pitch + k] = sp[k * nhp + c];
-  }
+  staged_copy<8>(
+      w * nz, threadIdx.x, blockDim.x,
+      [&](int t) {
+        const int k = fdiv32(t, mw, w), c = t - k * w;
+        return sp[k * nhp + c];
+      },
+      [&](int t, double2 v) {
+        const int k = fdiv32(t, mw, w), c = t - k * w;
+        buf0[c * pitch + k] = v;
+      });
   __syncthreads();
   FftPlan P = E.fz;
   double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw, threadIdx.x, blockDim.x);
@@ -870,202 +898,107 @@ __global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int
 // ---------------------------------------------------------------------------
 // tridiagonal solve in y for a tile of `tm` Fourier modes (mz, mx):
 //   -am_j phi_{j-1} + (am_j + ap_j + k^2) phi_j - ap_j phi_{j+1} = rho_j
-// (FV Laplacian times -1, phi = 0 on both walls).  The tile's columns are
-// staged in LDS with coalesced loads; one thread per (mode, re/im) runs the
-// Thomas sweeps in LDS; coalesced stores.
+// (FV Laplacian times -1, phi = 0 on both walls) by the Thomas algorithm with
+// the factors (1 / pivot_j, c'_j) of every mode precomputed from the mesh
+// (stored mode-major: a tile's factors are one contiguous range): the sweeps
+// carry no division.  The tile's columns and factors are staged in LDS, padded
+// with zero rows to a multiple of kTriChunk (the padding solves to zero, so
+// the sweeps run whole chunks without guards); one thread per (mode, re/im)
+// sweeps, kTriChunk rows at a time read ahead of the dependent chain.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_tri_thomas(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
-                                                       int blk0, int tmax) {
+__global__ __launch_bounds__(kBlock) void k_tri(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
+                                                int blk0, int eq_max) {
   extern __shared__ double2 lds[];
   Ens E;
   int lb;
-  if (one) {
-    E = Eone;
-    lb = blockIdx.x;
-  } else {
-    const int gb = blk0 + blockIdx.x;
-    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-    E = C.ens[e];
-    lb = gb - blk_off[e];
-  }
-  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  block_ens(C, Eone, one, blk_off, blk0, E, lb);
+  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp, nyp = tri_pad(E.ny);
   const int tm = E.tm;
+  double2* col = lds;                         // [nyp][tm] right-hand side -> solution
+  double2* fac = lds + eq_max;                // [nyp][tm] (1 / pivot, c')
+  double* ams = reinterpret_cast<double*>(lds + 2 * (size_t)eq_max);  // [nyp] lower couplings
   const int nm = nh * nz;
   const int mode0 = lb * tm;
   const int w = min(tm, nm - mode0);
-  double2* col = lds;                          // [ny][tm]
-  double* cps = (double*)(lds + ny * tm);      // [ny][2*tm]
-  const double2* sp = C.spec + E.s_off;
-  const long long pitch = (long long)nz * nhp;
-  for (int t = threadIdx.x; t < ny * w; t += blockDim.x) {
-    const int j = t / w, c = t - j * w;
-    const int mode = mode0 + c;
-    const int mz = mode / nh, m = mode - mz * nh;
-    col[j * tm + c] = sp[j * pitch + (long long)mz * nhp + m];
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * tm) {
-    const int c = threadIdx.x % tm, comp = threadIdx.x / tm;
-    if (c < w) {
-      const int mode = mode0 + c;
-      const int mz = mode / nh, m = mode - mz * nh;
-      const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
-      const double* __restrict__ am = C.am + E.y_off;
-      const double* __restrict__ ap = C.ap + E.y_off;
-      double* v = (double*)col + 2 * c + comp;   // element j at v[j * 2 * tm]
-      double* cp = cps + threadIdx.x;            // element j at cp[j * 2 * tm]
-      const int vs = 2 * tm;
-      double diag = (am[0] + ap[0]) + K2;
-      double cpv = (-ap[0]) / diag;
-      double dp = v[0] / diag;
-      v[0] = dp;
-      cp[0] = cpv;
-      for (int j = 1; j < ny; ++j) {
-        const double lo = -am[j];
-        const double dg = (am[j] + ap[j]) + K2;
-        const double piv = dg - lo * cpv;
-        cpv = (-ap[j]) / piv;
-        dp = (v[j * vs] - lo * dp) / piv;
-        v[j * vs] = dp;
-        cp[j * vs] = cpv;
-      }
-      double x = dp;
-      for (int j = ny - 2; j >= 0; --j) {
-        x = v[j * vs] - cp[j * vs] * x;
-        v[j * vs] = x;
-      }
-    }
-  }
-  __syncthreads();
-  double2* spo = C.spec + E.s_off;
-  for (int t = threadIdx.x; t < ny * w; t += blockDim.x) {
-    const int j = t / w, c = t - j * w;
-    const int mode = mode0 + c;
-    const int mz = mode / nh, m = mode - mz * nh;
-    spo[j * pitch + (long long)mz * nhp + m] = col[j * tm + c];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// tridiagonal solve in y by parallel cyclic reduction (ny <= kPcrEq*256/tm):
-// every equation of a tile of tm modes lives in LDS; each of ceil(log2 ny)
-// steps eliminates the couplings at distance delta from all equations at
-// once.  Same system as the Thomas variant; different rounding order.
-// ---------------------------------------------------------------------------
-constexpr int kPcrEq = 8;  // equations per thread
-
-__global__ __launch_bounds__(kBlock) void k_tri_pcr(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
-                                                    int blk0, int tmax) {
-  extern __shared__ double ldsd[];
-  Ens E;
-  int lb;
-  if (one) {
-    E = Eone;
-    lb = blockIdx.x;
-  } else {
-    const int gb = blk0 + blockIdx.x;
-    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-    E = C.ens[e];
-    lb = gb - blk_off[e];
-  }
-  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
-  const int tm = E.tm;
-  const int nm = nh * nz;
-  const int mode0 = lb * tm;
-  const int w = min(tm, nm - mode0);
-  const int neq = w * ny;
-  const int nyp = ny + 1;        // padded mode stride: no LDS bank conflicts
-  const int cap = tmax * (E.ny + 1);
-  (void)cap;
-  const int cap2 = tm * nyp;
-  double* A = ldsd;
-  double* B = A + cap2;
-  double* Cc = B + cap2;
-  double* Dr = Cc + cap2;
-  double* Di = Dr + cap2;
-  const double* __restrict__ am = C.am + E.y_off;
-  const double* __restrict__ ap = C.ap + E.y_off;
-  const long long pitch = (long long)nz * nhp;
   double2* sp = C.spec + E.s_off;
-  // coalesced load: consecutive threads take consecutive modes of one y row;
-  // equation index q = c*ny + j (each mode's equations contiguous)
+  const double2* __restrict__ tf = C.tfac + E.tf_off + (long long)mode0 * ny;  // [mode][ny]
+  const long long pitch = (long long)nz * nhp;
   const unsigned mw = magic32(w), mnh = magic32(nh), mny = magic32(ny);
-  for (int t = threadIdx.x; t < neq; t += blockDim.x) {
-    const int j = fdiv32(t, mw, w), c = t - j * w;
-    const int mode = mode0 + c;
-    const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
-    const double K2 = C.kz2[E.kz_off + mz] + C.kx2[E.kx_off + m];
-    const int qi = c * nyp + j;
-    const double2 r = sp[j * pitch + (long long)mz * nhp + m];
-    A[qi] = (j > 0) ? -am[j] : 0.0;
-    Cc[qi] = (j < ny - 1) ? -ap[j] : 0.0;
-    B[qi] = (am[j] + ap[j]) + K2;
-    Dr[qi] = r.x;
-    Di[qi] = r.y;
+  staged_copy<8>(
+      ny * w, threadIdx.x, kBlock,
+      [&](int t) {
+        const int j = fdiv32(t, mw, w), c = t - j * w;
+        const int mode = mode0 + c;
+        const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
+        return sp[j * pitch + (long long)mz * nhp + m];
+      },
+      [&](int t, double2 v) {
+        const int j = fdiv32(t, mw, w), c = t - j * w;
+        col[j * tm + c] = v;
+      });
+  staged_copy<8>(
+      ny * w, threadIdx.x, kBlock, [&](int t) { return tf[t]; },
+      [&](int t, double2 v) {
+        const int c = fdiv32(t, mny, ny), j = t - c * ny;
+        fac[j * tm + c] = v;
+      });
+  // zero padding rows (and the columns past w of a partial tile)
+  for (int t = threadIdx.x; t < nyp * tm; t += kBlock) {
+    const int j = t / tm, c = t - j * tm;
+    if (j >= ny || c >= w) {
+      col[t] = make_double2(0.0, 0.0);
+      fac[t] = make_double2(0.0, 0.0);
+    }
+  }
+  for (int j = threadIdx.x; j < nyp; j += kBlock) ams[j] = (j > 0 && j < ny) ? C.am[E.y_off + j] : 0.0;
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * w) {
+    const int c = threadIdx.x >> 1, comp = threadIdx.x & 1;
+    double* v = reinterpret_cast<double*>(col + c) + comp;  // row j at v[j * vs]
+    const double2* fc = fac + c;                             // row j at fc[j * tm]
+    const int vs = 2 * tm;
+    double dp = 0.0;
+    for (int j0 = 0; j0 < nyp; j0 += kTriChunk) {
+      double rv[kTriChunk], ra[kTriChunk], rp[kTriChunk];
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) {
+        rv[u] = v[(j0 + u) * vs];
+        ra[u] = ams[j0 + u];
+        rp[u] = fc[(j0 + u) * tm].x;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) {
+        dp = (rv[u] + ra[u] * dp) * rp[u];
+        rv[u] = dp;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) v[(j0 + u) * vs] = rv[u];
+    }
+    // back substitution from the top (padding rows give x = 0)
+    double x = 0.0;
+    for (int j0 = nyp - kTriChunk; j0 >= 0; j0 -= kTriChunk) {
+      double rv[kTriChunk], rc[kTriChunk];
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) {
+        const int j = j0 + kTriChunk - 1 - u;
+        rv[u] = v[j * vs];
+        rc[u] = fc[j * tm].y;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) {
+        x = rv[u] - rc[u] * x;
+        rv[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriChunk; ++u) v[(j0 + kTriChunk - 1 - u) * vs] = rv[u];
+    }
   }
   __syncthreads();
-  double ra[kPcrEq], rb[kPcrEq], rc[kPcrEq], rdr[kPcrEq], rdi[kPcrEq];
-  int jj[kPcrEq];
-  int qq[kPcrEq];
-#pragma unroll
-  for (int u = 0; u < kPcrEq; ++u) {
-    const int t = threadIdx.x + u * kBlock;
-    const int c = fdiv32(t, mny, ny);
-    jj[u] = t - c * ny;
-    qq[u] = c * nyp + jj[u];  // padded index of the thread's u-th equation
-  }
-  for (int delta = 1; delta < ny; delta <<= 1) {
-#pragma unroll
-    for (int u = 0; u < kPcrEq; ++u) {
-      const int qi = qq[u];
-      if (threadIdx.x + u * kBlock < neq) {
-        const int j = jj[u];
-        const double a = A[qi], b = B[qi], c = Cc[qi];
-        double na = 0.0, nc = 0.0, nb = b, ndr = Dr[qi], ndi = Di[qi];
-        if (j >= delta) {
-          const int qm = qi - delta;
-          const double al = -a / B[qm];
-          na = al * A[qm];
-          nb = nb + al * Cc[qm];
-          ndr = ndr + al * Dr[qm];
-          ndi = ndi + al * Di[qm];
-        }
-        if (j + delta < ny) {
-          const int qp = qi + delta;
-          const double ga = -c / B[qp];
-          nc = ga * Cc[qp];
-          nb = nb + ga * A[qp];
-          ndr = ndr + ga * Dr[qp];
-          ndi = ndi + ga * Di[qp];
-        }
-        ra[u] = na;
-        rb[u] = nb;
-        rc[u] = nc;
-        rdr[u] = ndr;
-        rdi[u] = ndi;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kPcrEq; ++u) {
-      const int qi = qq[u];
-      if (threadIdx.x + u * kBlock < neq) {
-        A[qi] = ra[u];
-        B[qi] = rb[u];
-        Cc[qi] = rc[u];
-        Dr[qi] = rdr[u];
-        Di[qi] = rdi[u];
-      }
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < neq; t += blockDim.x) {
+  for (int t = threadIdx.x; t < ny * w; t += kBlock) {
     const int j = fdiv32(t, mw, w), c = t - j * w;
     const int mode = mode0 + c;
     const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
-    const int qi = c * nyp + j;
-    const double b = B[qi];
-    sp[j * pitch + (long long)mz * nhp + m] = make_double2(Dr[qi] / b, Di[qi] / b);
+    sp[j * pitch + (long long)mz * nhp + m] = col[j * tm + c];
   }
 }
 
@@ -1094,15 +1027,22 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
   if (ok) {
     const double2* sa = C.spec + E.s_off + (long long)jkA * E.nhp;
     const double2* sb = sa + E.nhp;
-    for (int t = lane; t < nx; t += 64) {
-      const int m = t <= half ? t : nx - t;
-      const double2 a = sa[m], b = sb[m];
-      double2 z;
-      if (t == 0 || t == half) z = make_double2(a.x, b.x);
-      else if (t < half) z = make_double2(a.x - b.y, a.y + b.x);
-      else z = make_double2(a.x + b.y, b.x - a.y);
-      buf0[t] = z;
-    }
+    struct AB {
+      double2 a, b;
+    };
+    staged_copy<4>(
+        nx, lane, 64,
+        [&](int t) {
+          const int m = t <= half ? t : nx - t;
+          return AB{sa[m], sb[m]};
+        },
+        [&](int t, AB v) {
+          double2 z;
+          if (t == 0 || t == half) z = make_double2(v.a.x, v.b.x);
+          else if (t < half) z = make_double2(v.a.x - v.b.y, v.a.y + v.b.x);
+          else z = make_double2(v.a.x + v.b.y, v.b.x - v.a.y);
+          buf0[t] = z;
+        });
   }
   __syncthreads();
   double2* res = lds_fft<true>(buf0, buf1, 1, nx, E.fx, tw, lane, 64);
@@ -1355,13 +1295,27 @@ hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool
 }
 
 int sortdep_cap(const Ctx& C, int nx_max, int want) {
-  // member list per row pair: at least what the FFT buffer it shares leaves
-  // free, by default about 2.5 times the mean pair size, within 64 KiB of LDS
-  // per block
+  // member list per row pair.  Default: at least the mean pair size and what
+  // the FFT buffer it shares leaves free, then as large as possible without
+  // lowering the number of blocks that fit in a CU's 160 KiB of LDS (pairs
+  // above the capacity take the two-pass path).  Always within 64 KiB per block.
   if (want < 0) return 0;
-  const long long mean = C.n_rows > 0 ? (2 * C.n_tot + C.n_rows - 1) / C.n_rows : 0;
-  long long cap = want > 0 ? want : std::max<long long>((16LL * nx_max) / 12, ((5 * mean / 2 + 63) / 64) * 64);
+  auto block_bytes = [&](long long cap) {
+    return 16LL * nx_max + kPairsPerBlock * (long long)sortdep_wave_bytes(nx_max, (int)cap);
+  };
   const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
+  long long cap;
+  if (want > 0) {
+    cap = want;
+  } else {
+    const long long mean = C.n_rows > 0 ? (2 * C.n_tot + C.n_rows - 1) / C.n_rows : 0;
+    cap = std::min(std::max<long long>((16LL * nx_max) / 12, ((mean + 63) / 64) * 64), lim);
+    const long long per_cu = 163840 / std::max<long long>(block_bytes(cap), 1);
+    if (per_cu > 0) {
+      const long long grow = ((163840 / per_cu - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
+      cap = std::max(cap, grow);
+    }
+  }
   cap = std::min(cap, lim);
   return (int)std::max<long long>(cap, 0) & ~7;
 }
@@ -1397,13 +1351,9 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
-    if (G.tri_pcr) {
-      const size_t tl = (size_t)5 * G.tri_eq_max * sizeof(double);  // largest tm * (ny + 1)
-      k_tri_pcr<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
-    } else {
-      const size_t tl = (size_t)G.tri_eq_max * (sizeof(double2) + 2 * sizeof(double));
-      k_tri_thomas<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_m);
-    }
+    // columns + factors of the largest tile (tm * ny entries each)
+    const size_t tl = (size_t)2 * G.tri_eq_max * sizeof(double2) + (size_t)tri_pad(G.ny_max) * sizeof(double);
+    k_tri<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_eq_max);
   }
   mark(2);
   if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);

@@ -24,9 +24,7 @@ struct LaunchGeo {
   int nx_max, nz_max;
   int wz;          // spectral columns per block in the z transforms
   int ny_max;
-  int tri_m;       // Fourier modes per block in the tridiagonal solves
-  int tri_pcr;     // 1: cyclic reduction, 0: Thomas
-  int tri_eq_max;  // largest tm * (ny + 1) over the ensembles (LDS sizing)
+  int tri_eq_max;  // largest tm * ny over the ensembles (LDS sizing)
   int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
   const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block
   const int* fz_blk;

@@ -28,6 +28,7 @@ struct Ens {
   long long c_off;   // first cell (global cell index = c_off + (j*nz + k)*nx + i)
   long long s_off;   // first spectrum entry ([ny][nz][nhp] complex)
   long long row_off; // first (j, k) row
+  long long tf_off;  // first tridiagonal factor ([nz * nh][ny], mode-major)
   int y_off;         // first entry in the per-y tables (ny+1 reserved)
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
@@ -51,6 +52,12 @@ enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_END = 
 inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
+
+// rows per register chunk of the tridiagonal sweeps; tiles are padded to it
+constexpr int kTriChunk = 16;
+__host__ __device__ inline int tri_pad(int ny) { return (ny + kTriChunk - 1) / kTriChunk * kTriChunk; }
+// LDS per block available on gfx950
+constexpr int kLdsMax = 163840;
 
 // Particle buffer (structure of arrays).  key = global cell of the position.
 struct PState {
@@ -86,7 +93,6 @@ struct Ctx {
   int* far_n;                // [2]        live count (push appends), snapshot for the sort
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
-  double* cp;                // Thomas scratch (same indexing as spec)
   double* phi;               // [c_tot]   potential of the latest step
   long long* stats;          // statistics blocks
   long long* rowq;           // [sum ny*nz] sum rne(q 2^48) per (j,k) row, latest deposit
@@ -94,6 +100,7 @@ struct Ctx {
   long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
+  const double2* tfac;       // Thomas factors per ensemble: [modes][ny] (1 / pivot, c')
 };
 
 __device__ __forceinline__ int find_off(const long long* off, int n, long long v) {
