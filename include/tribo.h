@@ -188,9 +188,11 @@ int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
 
 /*
  * Per-phase timing with HIP events on the handle's stream.  After
- * tf_profile_begin, the next max_steps steps are launched eagerly with an
- * event at every phase boundary; tf_profile_end synchronises and returns the
- * summed milliseconds of each phase over the profiled steps.  Phases:
+ * tf_profile_begin, the next max_steps steps are launched eagerly with events
+ * at the boundaries of the phases in phase_mask (bit p = phase p; 0 = all);
+ * tf_profile_end synchronises and returns the summed milliseconds of each
+ * bracketed phase over the profiled steps (0 for the others).  Every event
+ * costs a few microseconds of the step.  Phases:
  *   0 sort: the row-count prefix sum (after init or tf_set_state: the full
  *     counting sort)
  *   1 deposit + forward FFT along x (the incremental sort runs fused here)
@@ -199,7 +201,7 @@ int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
  *   5 inverse FFT along x               6 particle push
  */
 #define TF_NPHASE 7
-int tf_profile_begin(tf_handle* h, int32_t max_steps);
+int tf_profile_begin(tf_handle* h, int32_t max_steps, uint32_t phase_mask);
 int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_steps);
 
 /*

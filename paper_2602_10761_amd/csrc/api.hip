@@ -182,6 +182,7 @@ struct tf_handle {
   hipGraphExec_t g_ab = nullptr, g_ba = nullptr;
   // phase timing: TF_NPHASE + 1 events per profiled step
   int prof_cap = 0, prof_n = 0;
+  uint32_t prof_mask = 0;           // phases bracketed by events
   std::vector<hipEvent_t> prof_ev;
 };
 
@@ -285,16 +286,27 @@ void destroy_graphs(tf_handle* h) {
 
 hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const TrajBuf* rec, bool full = false) {
   hipError_t e;
-  hipEvent_t* ev = nullptr;
-  if (h->prof_n < h->prof_cap) ev = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
-  if (ev && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
+  // phase-boundary events of a profiled step: boundary b opens phase b and
+  // closes phase b - 1; only the boundaries of the bracketed phases are recorded
+  hipEvent_t ev[TF_NPHASE + 1] = {};
+  bool prof = false;
+  if (h->prof_n < h->prof_cap) {
+    hipEvent_t* all = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
+    for (int b = 0; b <= TF_NPHASE; ++b) {
+      const bool opens = b < TF_NPHASE && ((h->prof_mask >> b) & 1u);
+      const bool closes = b > 0 && ((h->prof_mask >> (b - 1)) & 1u);
+      if (opens || closes) ev[b] = all[b];
+    }
+    prof = true;
+  }
+  if (ev[0] && (e = hipEventRecord(ev[0], h->stream)) != hipSuccess) return e;
   // full: counting sort, then deposit + x transform from the sorted runs;
   // incremental: row scan, then the fused sort + deposit + x transform
   if ((e = launch_sort(h->C, h->G, in, full, h->stream)) != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
+  if (ev[1] && (e = hipEventRecord(ev[1], h->stream)) != hipSuccess) return e;
   if (!full && (e = launch_sort_dep(h->C, h->G, in, h->stream)) != hipSuccess) return e;
   if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
-                          ev ? ev + 2 : nullptr, nullptr, !full)) != hipSuccess)
+                          prof ? ev + 2 : nullptr, nullptr, !full, h->C.far_n)) != hipSuccess)
     return e;
   if (rec) {
     const size_t n = h->C.n_tot, nc = h->C.c_tot;
@@ -311,7 +323,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)
     return e;
-  if (ev && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
+  if (ev[TF_NPHASE] && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -812,10 +824,13 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
   return TF_OK;
 }
 
-int tf_profile_begin(tf_handle* h, int32_t max_steps) {
+int tf_profile_begin(tf_handle* h, int32_t max_steps, uint32_t phase_mask) {
   if (!h) return fail(TF_EINVAL, "handle is NULL");
   if (max_steps < 1 || max_steps > 100000) return fail(TF_EINVAL, "max_steps out of range");
   if (h->prof_cap) return fail(TF_ESTATE, "profiling already active");
+  const uint32_t all = (1u << TF_NPHASE) - 1u;
+  if (phase_mask & ~all) return fail(TF_EINVAL, "phase_mask has bits beyond the phases");
+  h->prof_mask = phase_mask ? phase_mask : all;
   h->prof_ev.assign((size_t)max_steps * (TF_NPHASE + 1), nullptr);
   for (auto& e : h->prof_ev) HIPCHK(hipEventCreate(&e));
   h->prof_cap = max_steps;
@@ -831,6 +846,7 @@ int tf_profile_end(tf_handle* h, double* phase_ms, int32_t* n_steps) {
   for (int s = 0; s < h->prof_n; ++s) {
     hipEvent_t* ev = &h->prof_ev[(size_t)s * (TF_NPHASE + 1)];
     for (int p = 0; p < TF_NPHASE; ++p) {
+      if (!((h->prof_mask >> p) & 1u)) continue;
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ev[p], ev[p + 1]));
       phase_ms[p] += ms;

@@ -71,18 +71,9 @@ __device__ __forceinline__ void scan_load(const int* __restrict__ cnt, long long
   }
 }
 
-// per-block totals of the counts; block 0 also counts the step of every
-// ensemble and hands the far list over (runs once per step, before placement)
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(Ctx C, const int* __restrict__ cnt, long long n,
+// per-block totals of the counts
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ cnt, long long n,
                                                         int* __restrict__ part) {
-  if (blockIdx.x == 0) {
-    for (int e = threadIdx.x; e < C.n_ens; e += kBlock) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
-    // the far list of the last push: snapshot for the placement, restart for the next push
-    if (threadIdx.x == 0) {
-      C.far_n[1] = C.far_n[0];
-      C.far_n[0] = 0;
-    }
-  }
   const long long base = (long long)blockIdx.x * kScanChunk + (long long)kScanPer * threadIdx.x;
   int v[kScanPer];
   scan_load(cnt, base, n, v);
@@ -106,6 +97,27 @@ __global__ __launch_bounds__(1024) void k_scan_part(int* __restrict__ part, int 
     if (i < nb) part[i] = carry + ex;
     carry += tot;
   }
+}
+
+// the whole exclusive prefix of n <= kSmallScan counts in one block of 1024
+// threads, kScanPer consecutive counts per thread
+constexpr int kSmallScan = kScanPer * 1024;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ cnt, int n, int* __restrict__ out) {
+  const long long base = (long long)kScanPer * threadIdx.x;
+  int v[kScanPer];
+  scan_load(cnt, base, n, v);
+  int s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanPer; ++r) s += v[r];
+  int tot;
+  int ex = block_excl_scan<16>(s, &tot);
+#pragma unroll
+  for (int r = 0; r < kScanPer; ++r) {
+    if (base + r < n) out[base + r] = ex;
+    ex += v[r];
+  }
+  if (threadIdx.x == 0) out[n] = tot;
 }
 
 // writes start[0..n]; the block prefix is the sum of the preceding block totals
@@ -367,17 +379,15 @@ __device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const F
 
 // ---------------------------------------------------------------------------
 // strided copy global -> LDS with U loads per thread in flight before the
-// first store (a plain strided loop waits for every load in turn)
+// first store (a plain strided loop waits for every load in turn); loads past
+// the end re-read the last element instead of branching around the load
 // ---------------------------------------------------------------------------
 template <int U, class Ld, class St>
 __device__ __forceinline__ void staged_copy(int total, int tid, int nthr, Ld ld, St st) {
   for (int t0 = tid; t0 < total; t0 += nthr * U) {
     decltype(ld(0)) r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * nthr;
-      if (t < total) r[u] = ld(t);
-    }
+    for (int u = 0; u < U; ++u) r[u] = ld(min(t0 + u * nthr, total - 1));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * nthr;
@@ -641,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     r0 = min(max(C.ps[rA >> 1], 0), (int)C.n_tot);
     r1 = min(max(C.ps[(rA >> 1) + 1], r0), (int)C.n_tot);
     T = S.off[6];
-    TT = T + min(C.far_n[1], (int)C.n_tot);
+    TT = T + min(C.far_n[0], (int)C.n_tot);
     for (int i = lane; i < n2; i += 64) {
       cnt[i] = 0;
       Q[i] = 0;
@@ -659,19 +669,31 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   __syncthreads();
   // pass 1: cell counts; the fast path also lists the members (positions by
   // ballot: no same-address LDS atomics); the loop is wave-uniform
+  // loads are unconditional from a clamped slot (no branches around them)
+  const int last = (int)C.n_tot - 1;
   for (int tb = 0; tb < TT; tb += 64 * kCand) {
     const int t0 = tb + lane;
     int sl[kCand], c[kCand], idv[kCand];
 #pragma unroll
     for (int u = 0; u < kCand; ++u) {
       const int t = t0 + 64 * u;
-      sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+      sl[u] = t < T ? seg_slot(S, t) : -1;
+    }
+    if (tb + 64 * kCand > T && TT > T) {  // the batch reaches the far list
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        const int t = t0 + 64 * u;
+        if (t >= T && t < TT) sl[u] = C.far[t - T];
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
+    for (int u = 0; u < kCand; ++u) {
+      const int kv = in.key[min(max(sl[u], 0), last)];
+      c[u] = sl[u] >= 0 ? kv : -1;
+    }
     if (fast) {
 #pragma unroll
-      for (int u = 0; u < kCand; ++u) idv[u] = (c[u] >= c0 && c[u] < c1) ? in.id[sl[u]] : 0;
+      for (int u = 0; u < kCand; ++u) idv[u] = in.id[min(max(sl[u], 0), last)];
     }
 #pragma unroll
     for (int u = 0; u < kCand; ++u) {
@@ -845,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
 // FFT along z on the half spectrum: block = (ensemble, y plane, wz columns)
 // ---------------------------------------------------------------------------
 template <bool INV>
-__global__ __launch_bounds__(64) void k_fftz(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
+__global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
                                              int wmax, int nmax) {
   extern __shared__ double2 lds[];
   double2* buf0 = lds;
@@ -1010,7 +1032,9 @@ __global__ __launch_bounds__(kBlock) void k_tri(Ctx C, Ens Eone, int one, const 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
                                                        int blk0, int nmax, double* __restrict__ phi_out,
-                                                       long long phi_shift) {
+                                                       long long phi_shift, int* __restrict__ far_reset) {
+  // the sort of this step has read the far list: empty it for this step's push
+  if (far_reset && blockIdx.x == 0 && threadIdx.x == 0) *far_reset = 0;
   extern __shared__ double2 lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double2* tw = lds;
@@ -1188,11 +1212,15 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   pair_count(C.pair_cnt, (int)((E.row_off + (long long)nj * nz + nk) >> 1));
 }
 
-__global__ __launch_bounds__(kBlock) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
+// four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat
+// the few spilled registers
+__global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   // the new row ranges become the stored order's (read by the next sort)
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
     C.rs_old[r] = C.rs_new[r];
+  if (blockIdx.x == 0)  // the step counter of every ensemble (one push per step)
+    for (int e = threadIdx.x; e < C.n_ens; e += kBlock) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
   if (s < C.n_tot) {
     const int p = C.perm[s];
@@ -1267,10 +1295,14 @@ namespace tf {
 
 // exclusive prefix of cnt[0..n) into out[0..n]
 static void scan_into(const Ctx& C, const int* cnt, long long n, int* out, hipStream_t st) {
+  if (n > 0 && n <= kSmallScan) {
+    k_scan_small<<<1, 1024, 0, st>>>(cnt, (int)n, out);
+    return;
+  }
   const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
   if (nb == 0) return;
   const int fold = nb <= kScanFold ? 1 : 0;
-  k_scan_reduce<<<nb, kBlock, 0, st>>>(C, cnt, n, C.scan_part);
+  k_scan_reduce<<<nb, kBlock, 0, st>>>(cnt, n, C.scan_part);
   if (!fold) k_scan_part<<<1, 1024, 0, st>>>(C.scan_part, nb);
   k_scan_down<<<nb, kBlock, 0, st>>>(cnt, n, C.scan_part, fold, out);
 }
@@ -1332,11 +1364,12 @@ hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, 
 
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
-                          int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in, bool x_done) {
+                          int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in, bool x_done,
+                          int* far_reset) {
   (void)key;
   (void)q;
-  auto mark = [&](int i) {
-    if (ev) hipEventRecord(ev[i], st);
+  auto mark = [&](int i) {  // ev: 5 phase-boundary events, null entries skipped
+    if (ev && ev[i]) hipEventRecord(ev[i], st);
   };
   const int one = (e1 - e0 == 1) ? 1 : 0;
   const Ens Eone = G.eh[e0];
@@ -1347,7 +1380,7 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
   const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);  // wz: largest over ensembles
-  if (nzb > 0) k_fftz<false><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
+  if (nzb > 0) k_fftz<false><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
@@ -1356,18 +1389,20 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
     k_tri<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_eq_max);
   }
   mark(2);
-  if (nzb > 0) k_fftz<true><<<nzb, 64, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
+  if (nzb > 0) k_fftz<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(3);
-  if (nb > 0) k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift);
+  if (nb > 0)
+    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset);
   mark(4);
   return hipGetLastError();
 }
 
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st) {
-  const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
+  // at least one block: the step counters are kept by block 0
+  const int nb = std::max(1, (int)((C.n_tot + kBlock - 1) / kBlock));
   const int one = (C.n_ens == 1) ? 1 : 0;
-  if (nb > 0) k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
   return hipGetLastError();
 }
 

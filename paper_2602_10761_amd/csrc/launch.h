@@ -44,7 +44,7 @@ hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, 
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr,
-                          bool x_done = false);
+                          bool x_done = false, int* far_reset = nullptr);
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);

@@ -90,7 +90,7 @@ struct Ctx {
   int* rs_old;               // [n_rows+1]   slot range of each row in the stored order
   int* rs_new;               // [n_rows+1]   slot range of each row after this step's sort
   int* far;                  // [n_tot]    slots of particles whose row moved by 2+ in j or k
-  int* far_n;                // [2]        live count (push appends), snapshot for the sort
+  int* far_n;                // [2]        [0]: entries (the push appends; reset before the next push)
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
   double* phi;               // [c_tot]   potential of the latest step
