@@ -98,7 +98,8 @@ typedef struct tf_handle tf_handle;
  *   un_bin      bin width of the wall-normal impact-velocity histogram
  *   u_nodes     device pointer, carrier velocity at the mesh nodes,
  *               layout [3][ny+1][nz][nx] (component, y face, z, x), node
- *               (i, j, k) at (i dx, y_faces[j], k dz); borrowed
+ *               (i, j, k) at (i dx, y_faces[j], k dz); borrowed (read by
+ *               every step) until tf_set_carrier replaces it
  *   n_particles 1..2^30
  */
 typedef struct {
@@ -155,6 +156,12 @@ int tf_stats(tf_handle* h, int32_t ens, tf_stats_out* out);
  * tf_set_state also clears the recorded trajectory. */
 int tf_get_state(tf_handle* h, int32_t ens, const tf_particles* out);
 int tf_set_state(tf_handle* h, int32_t ens, const tf_particles* in);
+
+/* Make ensemble `ens` read its carrier velocity from u_nodes (same layout
+ * as tf_ensemble.u_nodes, device memory, borrowed) from the next step on: a
+ * time-dependent carrier field.  Synchronises the handle's stream.  Errors:
+ * TF_EINVAL (NULL, ensemble out of range), TF_EHIP. */
+int tf_set_carrier(tf_handle* h, int32_t ens, const double* u_nodes);
 
 /* Replace (k_c, delta_u, e) of every ensemble: host array [n_ens][3]. */
 int tf_set_params(tf_handle* h, const double* theta);

@@ -751,6 +751,17 @@ int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
   return TF_OK;
 }
 
+int tf_set_carrier(tf_handle* h, int32_t e, const double* u_nodes) {
+  if (!h || !u_nodes) return fail(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  h->eh[e].U = u_nodes;
+  // the descriptors live on the device and, by value, in the captured graphs
+  HIPCHK(hipMemcpyAsync(h->d_ens + e, &h->eh[e], sizeof(Ens), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  destroy_graphs(h);
+  return TF_OK;
+}
+
 int tf_set_params(tf_handle* h, const double* theta) {
   if (!h || !theta) return fail(TF_EINVAL, "NULL argument");
   for (int e = 0; e < h->n_ens; ++e) {

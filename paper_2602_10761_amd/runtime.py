@@ -72,6 +72,7 @@ def lib():
         L.tf_get_state.argtypes = [c_void_p, c_int32, POINTER(TfParticles)]
         L.tf_set_state.argtypes = [c_void_p, c_int32, POINTER(TfParticles)]
         L.tf_set_params.argtypes = [c_void_p, POINTER(c_double)]
+        L.tf_set_carrier.argtypes = [c_void_p, c_int32, c_void_p]
         L.tf_adjoint_step.argtypes = [c_void_p, POINTER(TfParticles), POINTER(c_double), POINTER(c_double)]
         L.tf_poisson.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
@@ -216,6 +217,16 @@ class TriboSim:
     def set_params(self, theta: np.ndarray):
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.n_ens, 3)
         _check(self.L.tf_set_params(self.h, th.ctypes.data_as(POINTER(c_double))))
+
+    def set_carrier(self, e: int, U):
+        """Replace the carrier velocity of ensemble e (array [3][ny+1][nz][nx])."""
+        u = self.torch.as_tensor(U, dtype=self.torch.float64).to(self.dev).contiguous()
+        E = self.ens[e].mesh
+        if u.numel() != 3 * (E.ny + 1) * E.nz * E.nx:
+            raise ValueError("carrier field has the wrong size")
+        self._sync_in()
+        _check(self.L.tf_set_carrier(self.h, e, u.data_ptr()))
+        self.U[e] = u  # borrowed by the library: keep it alive
 
     def poisson(self, e: int, q_fixed) -> "object":
         E = self.ens[e].mesh

@@ -119,6 +119,29 @@ def test_multi_step_parity():
     sim.close()
 
 
+def test_carrier_replacement():
+    """tf_set_carrier: steps after a new carrier field follow the oracle with
+    that field; the field is copied, so the caller's buffer may change."""
+    say("carrier replacement")
+    ens = ens_small(n=3000, v_jitter=2.0, precharge=0.2, c_el=5.0)
+    sim = sim_of(ens)
+    sim.step(2)
+    mid = sim.state_np(0)
+    rng = np.random.default_rng(7)
+    U2 = ens.U * 0.5 + 0.1 * rng.standard_normal(ens.U.shape)
+    sim.set_carrier(0, U2)
+    sim.step(2)
+    gpu = sim.state_np(0)
+    sim.close()
+    g = O.Geo.from_mesh(ens.mesh)
+    s = {k: np.array(mid[k], dtype=np.float64) for k in KEYS}
+    for _ in range(2):
+        s = O.step(g, U2, s, ens.params, None)
+    err = state_errors(gpu, s, ens.mesh)
+    say("  state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert max(err.values()) < 1e-10
+
+
 def test_far_movers_multi_step():
     """Fast particles that cross two or more cell rows in y or z per step (the
     sort's far list), over several steps, against the oracle."""
