@@ -219,9 +219,13 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  *              times the mean pair, -1 = none (always two passes), else
  *              1..4096 (clamped to what fits 64 KiB of LDS per block)
  *   fz_cols    spectral columns per block of the z transforms (1..64)
- *   tri_modes  Fourier modes per block of the tridiagonal solves (1..64)
- * Values whose LDS need exceeds 64 KiB per block are rejected at tf_init.
- * Results do not depend on the tiles (bitwise).
+ *   tri_modes  Fourier modes per block of the tridiagonal solves: 4, 8, 16
+ *              or 32 (the block's 256 threads split evenly among them; a
+ *              mode's lanes must cover ny with at most 16 rows each)
+ * Values whose LDS need exceeds a block's LDS are rejected at tf_init.
+ * Results do not depend on sort_cap or fz_cols (bitwise); tri_modes sets the
+ * association order of the tridiagonal scans, so it changes results at the
+ * rounding level only.
  */
 typedef struct {
   int32_t sort_cap, fz_cols, tri_modes, reserved;

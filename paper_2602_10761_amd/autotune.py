@@ -20,7 +20,7 @@ CACHE = os.environ.get("TRIBO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.
                                                         "tune_cache.json"))
 FZ_COLS = (2, 4, 5, 8, 13, 16, 22, 33)
 # bumped whenever the tiled kernels change shape semantics (older entries are ignored)
-KERNEL_REV = 4
+KERNEL_REV = 5
 
 
 def _arch() -> str:
@@ -33,11 +33,9 @@ def _key(arch: str, mesh: Tuple[int, int, int]) -> str:
 
 
 def tri_candidates(ny: int):
-    """Modes per tridiagonal tile: the tile (32 B per mode and padded row) fits the
-    160 KiB of LDS of a block."""
-    nyp = (ny + 15) // 16 * 16
-    out = [m for m in (4, 6, 8, 10, 12, 15, 16, 20, 24, 32, 40, 48, 64) if 32 * m * nyp + 8 * nyp <= 163840]
-    return out or [1]
+    """Modes per tridiagonal tile (256 threads split among them) whose lanes cover
+    ny with at most 16 rows each."""
+    return [m for m in (4, 8, 16, 32) if -(-ny // (256 // m)) <= 16]
 
 
 def _time_phases(mesh, fz: int, tm: int, steps: int) -> Dict[str, float]:

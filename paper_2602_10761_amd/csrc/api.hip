@@ -47,16 +47,30 @@ bool radix_plan(int n, FftPlan* P) {
   while (m % 2 == 0) if (!push(2)) return false;
   while (m % 3 == 0) if (!push(3)) return false;
   while (m % 5 == 0) if (!push(5)) return false;
+  if (m != 1) return false;
+  // in-place plan (fused inverse transforms): largest radices first
+  P->np_ip = 0;
+  P->rc_ip = 0;
+  m = n;
+  for (int r : {16, 8, 4, 2, 3, 5})
+    while (m % r == 0) {
+      if (P->np_ip >= 8) return false;
+      P->rc_ip |= (unsigned)(r - 1) << (4 * P->np_ip++);
+      m /= r;
+    }
   return m == 1;
 }
 
 struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
-  int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_eq_max = 0;
+  int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
-  std::vector<int> fp_blk, fz_blk, tri_blk;
+  std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk;
+  int plane_max = 0;
+  bool plane_any = false, split_any = false;
+  std::vector<int> e_plane;
   std::map<int, int> tw_off;
 };
 
@@ -64,6 +78,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   if (!ens || n_ens < 1 || n_ens > 4096) return fail(TF_EINVAL, "n_ens must be in [1, 4096]");
   S->fp_blk.assign(n_ens + 1, 0);
   S->fz_blk.assign(n_ens + 1, 0);
+  S->pl_blk.assign(n_ens + 1, 0);
   S->tri_blk.assign(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
@@ -86,7 +101,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     for (int j = 0; j < E.ny; ++j)
       if (!(E.y_faces[j + 1] > E.y_faces[j])) return fail(TF_EINVAL, pre + "y_faces must increase strictly");
     long long ncell = (long long)E.nx * E.ny * E.nz;
-    int nh = E.nx / 2 + 1, nhp = (nh + 3) & ~3;
+    int nh = E.nx / 2 + 1, nhp = (nh + 7) & ~7;
     S->n_tot += E.n_particles;
     S->c_tot += ncell;
     S->s_tot += (long long)E.ny * E.nz * nhp;
@@ -106,12 +121,12 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       }
   }
   if (S->n_tot >= (1LL << 31) || S->c_tot >= (1LL << 31) - 2) return fail(TF_ESIZE, "too many particles or cells");
-  // tridiagonal: cyclic reduction holds tm * ny equations (5 doubles each, at
-  // most 8 per thread); Thomas (some ny > 256) holds tm columns (32 B per row)
+  // tridiagonal: tm modes per block, G = kBlock / tm lanes per mode, rows per
+  // lane R = ceil(ny / G) <= 16 (one launch uses the largest R)
   S->e_wz.assign(n_ens, 2);
   S->e_tm.assign(n_ens, 1);
   S->wz = 1;
-  S->tri_eq_max = 0;
+  S->tri_rows = 1;
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     tf_tuning t = g_tune;
@@ -121,20 +136,21 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       if (it->second.tri_modes > 0) t.tri_modes = it->second.tri_modes;
     }
     const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
-    int tm;
-    // tridiagonal tile: tm modes x padded ny rows of spectrum and factors in LDS
-    // (32 B each); default about 64 KiB per block
-    const int nyp = tri_pad(E.ny);
-    tm = t.tri_modes > 0 ? t.tri_modes : std::max(1, std::min(kBlock / 2, (65536 - 8 * nyp) / (32 * nyp)));
-    tm = std::min(tm, kBlock / 2);
+    // default: the fewest lanes (at least 8) that keep R <= 8
+    int lanes = 8;
+    while (lanes < 64 && lanes * 8 < E.ny) lanes *= 2;
+    const int tm = t.tri_modes > 0 ? t.tri_modes : kBlock / lanes;
+    if (tm != 4 && tm != 8 && tm != 16 && tm != 32) return fail(TF_EINVAL, "tri_modes must be 4, 8, 16 or 32");
+    const int rows = (E.ny + kBlock / tm - 1) / (kBlock / tm);
+    if (rows > 16) return fail(TF_ESIZE, "tri_modes too large for ny (more than 16 rows per lane)");
     S->e_wz[e] = wz;
     S->e_tm[e] = tm;
     S->wz = std::max(S->wz, wz);
-    S->tri_eq_max = std::max(S->tri_eq_max, tm * tri_pad(E.ny));
+    S->tri_rows = std::max(S->tri_rows, rows);
   }
   const size_t lds_fx = (size_t)9 * S->nx_max * 16;  // twiddles + 4 waves x 2 line buffers
   const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
-  const size_t lds_tri = (size_t)S->tri_eq_max * 32 + (size_t)tri_pad(S->ny_max) * 8;
+  const size_t lds_tri = ((size_t)kBlock * (S->tri_rows | 1) + kBlock) * 16;
   if (lds_fx > 65536 || lds_fz > (size_t)kLdsMax || lds_tri > (size_t)kLdsMax)
     return fail(TF_ESIZE, "tile shapes exceed the LDS of a block");
   for (int e = 0; e < n_ens; ++e) {
@@ -142,7 +158,22 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     int rows = E.ny * E.nz, nh = E.nx / 2 + 1;
     S->fp_blk[e + 1] = S->fp_blk[e] + (rows / 2 + 3) / 4;  // row pairs, 4 per block
     S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->e_wz[e] - 1) / S->e_wz[e]);
-    S->tri_blk[e + 1] = S->tri_blk[e] + (nh * E.nz + S->e_tm[e] - 1) / S->e_tm[e];
+    S->tri_blk[e + 1] = S->tri_blk[e] + (((nh + 7) & ~7) * E.nz + S->e_tm[e] - 1) / S->e_tm[e];
+    S->pl_blk[e + 1] = S->pl_blk[e] + E.ny;
+  }
+  // fused inverse transforms for the ensembles whose plane (half spectrum and
+  // twiddles) fits one block's LDS
+  S->e_plane.assign(n_ens, 0);
+  for (int e = 0; e < n_ens; ++e) {
+    const tf_ensemble& E = ens[e];
+    const int pts = E.nz * (E.nx / 2 + 1);
+    S->e_plane[e] = pts <= kPlanePts && (size_t)(S->nx_max + S->nz_max + pts) * 16 <= (size_t)kLdsMax;
+    if (S->e_plane[e]) {
+      S->plane_any = true;
+      S->plane_max = std::max(S->plane_max, pts);
+    } else {
+      S->split_any = true;
+    }
   }
   return TF_OK;
 }
@@ -174,6 +205,7 @@ struct tf_handle {
   int* d_fx = nullptr;
   int* d_fz = nullptr;
   int* d_tri = nullptr;
+  int* d_pl = nullptr;
   // recorded trajectory
   int traj_cap = 0, traj_len = 0;
   std::vector<TrajBuf> traj;        // traj_cap + 1 states (perm/phi used for the first traj_cap)
@@ -207,6 +239,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   int* fx = cv.take<int>(n_ens + 1);
   int* fz = cv.take<int>(n_ens + 1);
   int* tri = cv.take<int>(n_ens + 1);
+  int* pl = cv.take<int>(n_ens + 1);
   C.yf = cv.take<double>(S.y_tot);
   C.dy = cv.take<double>(S.y_tot);
   C.idy = cv.take<double>(S.y_tot);
@@ -270,6 +303,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     h->d_fx = fx;
     h->d_fz = fz;
     h->d_tri = tri;
+    h->d_pl = pl;
     h->d_ens = (Ens*)C.ens;
     h->traj = traj;
     h->traj_cap = traj_steps;
@@ -365,7 +399,7 @@ int tf_set_tuning(const tf_tuning* t) {
     return TF_OK;
   }
   if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 128)
+      t->tri_modes > 32)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
   return TF_OK;
@@ -378,7 +412,7 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     g_class_tune.erase(key);
     return TF_OK;
   }
-  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 128)
+  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 32)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -443,7 +477,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.ny = T.ny;
     E.nz = T.nz;
     E.nh = T.nx / 2 + 1;
-    E.nhp = (E.nh + 3) & ~3;
+    E.nhp = (E.nh + 7) & ~7;  // rows of whole 128-byte lines
     E.np = T.n_particles;
     E.p_off = h->p_off[e];
     E.c_off = h->c_off[e];
@@ -456,6 +490,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.st_off = st_off;
     E.wz = S.e_wz[e];
     E.tm = S.e_tm[e];
+    E.plane = S.e_plane[e];
     E.lx = T.lx;
     E.lz = T.lz;
     E.ly = T.y_faces[T.ny];
@@ -549,6 +584,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->d_fx, S.fp_blk);
   UP(h->d_fz, S.fz_blk);
   UP(h->d_tri, S.tri_blk);
+  UP(h->d_pl, S.pl_blk);
   UP(h->C.yf, yf);
   UP(h->C.dy, dy);
   UP(h->C.idy, idy);
@@ -586,7 +622,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.nz_max = S.nz_max;
   h->G.wz = S.wz;
   h->G.ny_max = S.ny_max;
-  h->G.tri_eq_max = S.tri_eq_max;
+  h->G.tri_rows = S.tri_rows;
   h->G.sort_cap = g_tune.sort_cap;
   h->G.fp_blk = h->S.fp_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
@@ -594,6 +630,11 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.d_fp_blk = h->d_fx;
   h->G.d_fz_blk = h->d_fz;
   h->G.d_tri_blk = h->d_tri;
+  h->G.pl_blk = h->S.pl_blk.data();
+  h->G.d_pl_blk = h->d_pl;
+  h->G.plane_any = S.plane_any ? 1 : 0;
+  h->G.split_any = S.split_any ? 1 : 0;
+  h->G.plane_max = S.plane_max;
   h->G.eh = h->eh.data();
   h->cur = h->A;
   h->cur_is_A = true;

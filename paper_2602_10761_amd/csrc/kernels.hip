@@ -319,6 +319,68 @@ __device__ __forceinline__ void butterfly(double2* v) {
   }
 }
 
+// radix 8 and 16 butterflies in place (index n = n1 + 4 n2 in): a layer of
+// radix 2/4 butterflies over n2, the internal twiddles W_R^(n1 k2), a layer
+// of radix-4 butterflies over n1; output k = (R / 4) k1 + k2 is left at
+// position k1 + 4 k2 (out_pos)
+template <bool INV>
+__device__ __forceinline__ double2 mul_w(double2 a, double c, double s) {  // a * exp(-/+ i theta), (c, s) = (cos, sin)
+  return INV ? make_double2(a.x * c - a.y * s, a.x * s + a.y * c) : make_double2(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+template <bool INV>
+__device__ __forceinline__ void bf4(double2& v0, double2& v1, double2& v2, double2& v3) {
+  const double2 a = cadd(v0, v2), b = csub(v0, v2);
+  const double2 c = cadd(v1, v3), d = mul_mi<INV>(csub(v1, v3));
+  v0 = cadd(a, c);
+  v2 = csub(a, c);
+  v1 = cadd(b, d);
+  v3 = csub(b, d);
+}
+template <int R>
+__host__ __device__ constexpr int out_pos(int r) {
+  return R == 16 ? (r >> 2) + 4 * (r & 3) : R == 8 ? (r >> 1) + 4 * (r & 1) : r;
+}
+template <bool INV>
+__device__ __forceinline__ void butterfly8(double2* v) {
+  const double h = 0.70710678118654752440;  // cos(pi/4)
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    const double2 a = v[n1], b = v[n1 + 4];
+    v[n1] = cadd(a, b);
+    v[n1 + 4] = csub(a, b);
+  }
+  v[5] = mul_w<INV>(v[5], h, h);
+  v[6] = mul_mi<INV>(v[6]);
+  v[7] = mul_w<INV>(v[7], -h, h);
+  bf4<INV>(v[0], v[1], v[2], v[3]);
+  bf4<INV>(v[4], v[5], v[6], v[7]);
+}
+template <bool INV>
+__device__ __forceinline__ void butterfly16(double2* v) {
+  // cos and sin of 2 pi m / 16
+  constexpr double c1 = 0.92387953251128675613, c2 = 0.70710678118654752440, c3 = 0.38268343236508977173;
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) bf4<INV>(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+  // position n1 + 4 k2 now holds the k2 output of column n1: twiddle W16^(n1 k2)
+  v[5] = mul_w<INV>(v[5], c1, c3);     // m = 1
+  v[9] = mul_w<INV>(v[9], c2, c2);     // m = 2
+  v[13] = mul_w<INV>(v[13], c3, c1);   // m = 3
+  v[6] = mul_w<INV>(v[6], c2, c2);     // m = 2
+  v[10] = mul_mi<INV>(v[10]);          // m = 4
+  v[14] = mul_w<INV>(v[14], -c2, c2);  // m = 6
+  v[7] = mul_w<INV>(v[7], c3, c1);     // m = 3
+  v[11] = mul_w<INV>(v[11], -c2, c2);  // m = 6
+  v[15] = mul_w<INV>(v[15], -c1, -c3); // m = 9
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) bf4<INV>(v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]);
+}
+template <int R, bool INV>
+__device__ __forceinline__ void butterfly_any(double2* v) {
+  if constexpr (R == 8) butterfly8<INV>(v);
+  else if constexpr (R == 16) butterfly16<INV>(v);
+  else butterfly<R, INV>(v);
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2* __restrict__ b, int rows,
                                          int n, int pitch, int Ns, const double2* __restrict__ tw, int tid,
@@ -642,7 +704,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   const int j = jkA / nz, k = jkA - j * nz;
   const long long rA = E.row_off + jkA;
   const long long c0 = E.c_off + (long long)jkA * nx, c1 = c0 + n2;
-  for (int t = threadIdx.x; t < nx; t += kBlock) tw[t] = C.tw[E.fx.tw_off + t];
   RowSegs S;
   int r0 = 0, rm = 0, r1 = 0, T = 0, TT = 0;
   if (ok) {
@@ -780,6 +841,8 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   __syncthreads();
+  // twiddles of the x transform (nx <= kBlock): loaded now, stored after this phase
+  const double2 twv = C.tw[E.fx.tw_off + min((int)threadIdx.x, nx - 1)];
   // rank each member by id inside its cell; write the sorted arrays; deposit
   bool ovf = false;
   long long rq32[2] = {0, 0};
@@ -859,6 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+  if ((int)threadIdx.x < nx) tw[threadIdx.x] = twv;
   __syncthreads();
   pair_forward_store(C, E, jkA, buf0, buf1, tw, lane, ok);
 }
@@ -884,6 +948,7 @@ __global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const
     E = C.ens[e];
     lb = gb - blk_off[e];
   }
+  if (INV && E.plane) return;  // fused inverse transforms of the plane
   const int nz = E.nz, nh = E.nh, nhp = E.nhp;
   const int wz = E.wz;
   const int pitch = nz + 1;  // odd pitch (in 16-byte units): no bank conflicts in the transposes
@@ -892,7 +957,8 @@ __global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const
   const int m0 = (lb - j * nchunk) * wz;
   const int w = min(wz, nh - m0);
   const double2* __restrict__ twg = C.tw + E.fz.tw_off;
-  staged_copy<4>(nz, threadIdx.x, blockDim.x, [&](int t) { return twg[t]; }, [&](int t, double2 v) { tw[t] = v; });
+  // twiddles (nz <= kBlock = blockDim): the load is in flight with the column loads
+  const double2 twv = twg[min((int)threadIdx.x, nz - 1)];
   double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
   const unsigned mw = magic32(w);
   staged_copy<8>(
@@ -905,6 +971,7 @@ __global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const
         const int k = fdiv32(t, mw, w), c = t - k * w;
         buf0[c * pitch + k] = v;
       });
+  if ((int)threadIdx.x < nz) tw[threadIdx.x] = twv;
   __syncthreads();
   FftPlan P = E.fz;
   double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw, threadIdx.x, blockDim.x);
@@ -918,109 +985,152 @@ __global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal solve in y for a tile of `tm` Fourier modes (mz, mx):
+// tridiagonal solve in y for a tile of Fourier modes (mz, mx):
 //   -am_j phi_{j-1} + (am_j + ap_j + k^2) phi_j - ap_j phi_{j+1} = rho_j
-// (FV Laplacian times -1, phi = 0 on both walls) by the Thomas algorithm with
-// the factors (1 / pivot_j, c'_j) of every mode precomputed from the mesh
-// (stored mode-major: a tile's factors are one contiguous range): the sweeps
-// carry no division.  The tile's columns and factors are staged in LDS, padded
-// with zero rows to a multiple of kTriChunk (the padding solves to zero, so
-// the sweeps run whole chunks without guards); one thread per (mode, re/im)
-// sweeps, kTriChunk rows at a time read ahead of the dependent chain.
+// (FV Laplacian times -1, phi = 0 on both walls).  With the Thomas factors
+// (1 / pivot_j, c'_j) of every mode precomputed from the mesh, both sweeps are
+// first-order linear recurrences,
+//   d_j = A_j d_{j-1} + B_j  (A_j = am_j / pivot_j, B_j = rho_j / pivot_j),
+//   x_j = -c'_j x_{j+1} + d_j,
+// solved as parallel prefix compositions of affine maps: G lanes per mode,
+// R consecutive rows per lane (G R >= ny), a wavefront scan of the per-lane
+// maps (Hillis-Steele with shuffles) between two local passes.  The tile
+// (kBlock / G modes) is staged in LDS, [mode][lane][row] with an odd row
+// stride, from coalesced loads.
 // ---------------------------------------------------------------------------
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_tri(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
-                                                int blk0, int eq_max) {
-  extern __shared__ double2 lds[];
+                                                int blk0) {
+  extern __shared__ double2 col[];  // [tm][G][RS] + one pad entry per mode
   Ens E;
   int lb;
   block_ens(C, Eone, one, blk_off, blk0, E, lb);
-  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp, nyp = tri_pad(E.ny);
-  const int tm = E.tm;
-  double2* col = lds;                         // [nyp][tm] right-hand side -> solution
-  double2* fac = lds + eq_max;                // [nyp][tm] (1 / pivot, c')
-  double* ams = reinterpret_cast<double*>(lds + 2 * (size_t)eq_max);  // [nyp] lower couplings
-  const int nm = nh * nz;
-  const int mode0 = lb * tm;
-  const int w = min(tm, nm - mode0);
-  double2* sp = C.spec + E.s_off;
-  const double2* __restrict__ tf = C.tfac + E.tf_off + (long long)mode0 * ny;  // [mode][ny]
-  const long long pitch = (long long)nz * nhp;
-  const unsigned mw = magic32(w), mnh = magic32(nh), mny = magic32(ny);
+  const int nh = E.nh, nz = E.nz, ny = E.ny, nhp = E.nhp;
+  const int tm = E.tm, G = kBlock / tm;  // slots per block, lanes per slot
+  constexpr int RS = R | 1;               // odd row stride: lanes of a quarter-wave hit distinct banks
+  const int MS = G * RS + 1;              // mode stride: staging threads hit distinct banks
+  // the tile is tm consecutive slots of the padded [nz][nhp] plane (aligned
+  // segments of every y plane); padding slots pass through unchanged
+  const int pitch = nz * nhp;
+  const int slot0 = lb * tm;
+  const int w = min(tm, pitch - slot0);
+  double2* sp = C.spec + E.s_off + slot0;
+  const unsigned mw = magic32(w);
+  // rows per lane of this ensemble (Re <= R): the scan order, and so the
+  // rounding, depends on the ensemble's own mesh only; slots r >= Re are
+  // identity maps (exact: x * 1 + 0)
+  const int Re = (ny + G - 1) / G;
+  const unsigned mre = magic32(Re);
+  auto lidx = [&](int c, int j) {
+    const int g = fdiv32(j, mre, Re);
+    return c * MS + g * RS + (j - g * Re);
+  };
+  // this lane's slot and rows; its factors are loaded with the tile
+  const int c = threadIdx.x / G, g = threadIdx.x - c * G;
+  const int mz = (slot0 + c) / nhp, m = slot0 + c - mz * nhp;
+  const bool act = c < w && m < nh;
+  const int j0 = g * Re;
+  double A[R], Cc[R], ip[R];
+  {
+    const double2* __restrict__ tf = C.tfac + E.tf_off + (long long)(act ? mz * nh + m : 0) * ny;  // (1/pivot, c')
+    const double* __restrict__ am = C.am + E.y_off;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      // rows past the upper wall solve to zero
+      const int j = j0 + r;
+      const bool slot = r < Re, in = act && slot && j < ny;
+      const double2 f = tf[in ? j : 0];
+      const double a = am[in ? j : 0];
+      ip[r] = in ? f.x : 0.0;
+      A[r] = !slot ? 1.0 : (in && j > 0) ? a * f.x : 0.0;
+      Cc[r] = !slot ? 1.0 : (in && j < ny - 1) ? -f.y : 0.0;
+    }
+  }
   staged_copy<8>(
       ny * w, threadIdx.x, kBlock,
       [&](int t) {
         const int j = fdiv32(t, mw, w), c = t - j * w;
-        const int mode = mode0 + c;
-        const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
-        return sp[j * pitch + (long long)mz * nhp + m];
+        return sp[(long long)j * pitch + c];
       },
       [&](int t, double2 v) {
         const int j = fdiv32(t, mw, w), c = t - j * w;
-        col[j * tm + c] = v;
+        col[lidx(c, j)] = v;
       });
-  staged_copy<8>(
-      ny * w, threadIdx.x, kBlock, [&](int t) { return tf[t]; },
-      [&](int t, double2 v) {
-        const int c = fdiv32(t, mny, ny), j = t - c * ny;
-        fac[j * tm + c] = v;
-      });
-  // zero padding rows (and the columns past w of a partial tile)
-  for (int t = threadIdx.x; t < nyp * tm; t += kBlock) {
-    const int j = t / tm, c = t - j * tm;
-    if (j >= ny || c >= w) {
-      col[t] = make_double2(0.0, 0.0);
-      fac[t] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (act) {
+    double2* v = col + c * MS + g * RS;
+    double2 B[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double2 rv = (r < Re && j0 + r < ny) ? v[r] : make_double2(0.0, 0.0);
+      B[r] = make_double2(rv.x * ip[r], rv.y * ip[r]);
+    }
+    // forward: d_j = A_j d_{j-1} + B_j; per-lane map, then an inclusive scan
+    double al = 1.0;
+    double2 bl = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      al = A[r] * al;
+      bl = make_double2(A[r] * bl.x + B[r].x, A[r] * bl.y + B[r].y);
+    }
+    for (int o = 1; o < G; o <<= 1) {
+      const double ao = __shfl_up(al, o, G);
+      const double bx = __shfl_up(bl.x, o, G), by = __shfl_up(bl.y, o, G);
+      if (g >= o) {
+        bl = make_double2(al * bx + bl.x, al * by + bl.y);
+        al = al * ao;
+      }
+    }
+    double dx = __shfl_up(bl.x, 1, G), dy = __shfl_up(bl.y, 1, G);
+    if (g == 0) dx = dy = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      dx = A[r] * dx + B[r].x;
+      dy = A[r] * dy + B[r].y;
+      B[r] = r < Re ? make_double2(dx, dy) : make_double2(0.0, 0.0);
+    }
+    // backward: x_j = -c'_j x_{j+1} + d_j, suffix scan from the upper wall
+    al = 1.0;
+    bl = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+      al = Cc[r] * al;
+      bl = make_double2(Cc[r] * bl.x + B[r].x, Cc[r] * bl.y + B[r].y);
+    }
+    for (int o = 1; o < G; o <<= 1) {
+      const double ao = __shfl_down(al, o, G);
+      const double bx = __shfl_down(bl.x, o, G), by = __shfl_down(bl.y, o, G);
+      if (g + o < G) {
+        bl = make_double2(al * bx + bl.x, al * by + bl.y);
+        al = al * ao;
+      }
+    }
+    double xx = __shfl_down(bl.x, 1, G), xy = __shfl_down(bl.y, 1, G);
+    if (g == G - 1) xx = xy = 0.0;
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+      xx = Cc[r] * xx + B[r].x;
+      xy = Cc[r] * xy + B[r].y;
+      if (r < Re && j0 + r < ny) v[r] = make_double2(xx, xy);
     }
   }
-  for (int j = threadIdx.x; j < nyp; j += kBlock) ams[j] = (j > 0 && j < ny) ? C.am[E.y_off + j] : 0.0;
   __syncthreads();
-  if ((int)threadIdx.x < 2 * w) {
-    const int c = threadIdx.x >> 1, comp = threadIdx.x & 1;
-    double* v = reinterpret_cast<double*>(col + c) + comp;  // row j at v[j * vs]
-    const double2* fc = fac + c;                             // row j at fc[j * tm]
-    const int vs = 2 * tm;
-    double dp = 0.0;
-    for (int j0 = 0; j0 < nyp; j0 += kTriChunk) {
-      double rv[kTriChunk], ra[kTriChunk], rp[kTriChunk];
+  for (int t0 = threadIdx.x; t0 < ny * w; t0 += 4 * kBlock) {
+    double2 r[4];
 #pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) {
-        rv[u] = v[(j0 + u) * vs];
-        ra[u] = ams[j0 + u];
-        rp[u] = fc[(j0 + u) * tm].x;
-      }
-#pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) {
-        dp = (rv[u] + ra[u] * dp) * rp[u];
-        rv[u] = dp;
-      }
-#pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) v[(j0 + u) * vs] = rv[u];
+    for (int u = 0; u < 4; ++u) {
+      const int t = min(t0 + u * kBlock, ny * w - 1);
+      const int j = fdiv32(t, mw, w), cc = t - j * w;
+      r[u] = col[lidx(cc, j)];
     }
-    // back substitution from the top (padding rows give x = 0)
-    double x = 0.0;
-    for (int j0 = nyp - kTriChunk; j0 >= 0; j0 -= kTriChunk) {
-      double rv[kTriChunk], rc[kTriChunk];
 #pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) {
-        const int j = j0 + kTriChunk - 1 - u;
-        rv[u] = v[j * vs];
-        rc[u] = fc[j * tm].y;
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kBlock;
+      if (t < ny * w) {
+        const int j = fdiv32(t, mw, w), cc = t - j * w;
+        sp[(long long)j * pitch + cc] = r[u];
       }
-#pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) {
-        x = rv[u] - rc[u] * x;
-        rv[u] = x;
-      }
-#pragma unroll
-      for (int u = 0; u < kTriChunk; ++u) v[(j0 + kTriChunk - 1 - u) * vs] = rv[u];
     }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < ny * w; t += kBlock) {
-    const int j = fdiv32(t, mw, w), c = t - j * w;
-    const int mode = mode0 + c;
-    const int mz = fdiv32(mode, mnh, nh), m = mode - mz * nh;
-    sp[j * pitch + (long long)mz * nhp + m] = col[j * tm + c];
   }
 }
 
@@ -1043,11 +1153,13 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
   Ens E;
   int lb;
   block_ens(C, Eone, one, blk_off, blk0, E, lb);
+  if (E.plane) return;  // fused inverse transforms of the plane
   const int nx = E.nx, nz = E.nz, half = E.nx >> 1;
   const int lp = lb * kPairsPerBlock + w;
   const bool ok = lp < ((E.ny * nz) >> 1);
   const int jkA = ok ? 2 * lp : 0;
-  for (int t = threadIdx.x; t < nx; t += kBlock) tw[t] = C.tw[E.fx.tw_off + t];
+  // twiddles (nx <= kBlock): the load is in flight with the spectrum loads
+  const double2 twv = C.tw[E.fx.tw_off + min((int)threadIdx.x, nx - 1)];
   if (ok) {
     const double2* sa = C.spec + E.s_off + (long long)jkA * E.nhp;
     const double2* sb = sa + E.nhp;
@@ -1068,6 +1180,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
           buf0[t] = z;
         });
   }
+  if ((int)threadIdx.x < nx) tw[threadIdx.x] = twv;
   __syncthreads();
   double2* res = lds_fft<true>(buf0, buf1, 1, nx, E.fx, tw, lane, 64);
   if (!ok) return;
@@ -1078,6 +1191,159 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
     const double2 v = res[t];
     outA[t] = v.x * sc;
     outB[t] = v.y * sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse z and x transforms of one y plane in a single block, when the
+// plane's half spectrum fits the LDS (nz (nx/2 + 1) <= kPlanePts): one read
+// of the spectrum and one write of phi, no intermediate pass through memory.
+// The transforms run in place: every Stockham pass loads its butterflies'
+// inputs into registers, synchronises the block, then writes the outputs.
+// ---------------------------------------------------------------------------
+template <int R, bool INV>
+__device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, int ls, int es, int n, int Ns,
+                                        const double2* __restrict__ tw, int tid) {
+  constexpr int UM = (kPlanePts / R + kPlaneThreads - 1) / kPlaneThreads;
+  const int nb = n / R, stride = n / (Ns * R), total = lines * nb;
+  const int sin_ = nb * es, sout = Ns * es;  // element steps of a butterfly's inputs and outputs
+  double2 v[UM][R];
+#pragma unroll
+  for (int u = 0; u < UM; ++u) {
+    const int t = tid + u * kPlaneThreads;
+    if (t < total) {
+      const int jj = fdiv32(t, mlines, lines), line = t - jj * lines;
+      const double2* s = a + line * ls + jj * es;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[u][r] = s[r * sin_];
+    }
+  }
+  __syncthreads();
+  const bool ns2 = (Ns & (Ns - 1)) == 0;
+  const unsigned mns = ns2 ? 0u : magic32(Ns);
+#pragma unroll
+  for (int u = 0; u < UM; ++u) {
+    const int t = tid + u * kPlaneThreads;
+    if (t < total) {
+      const int jj = fdiv32(t, mlines, lines), line = t - jj * lines;
+      const int k = ns2 ? (jj & (Ns - 1)) : jj - fdiv32(jj, mns, Ns) * Ns;
+      if constexpr (R <= 5) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[r * k * stride];
+          if (INV) w.y = -w.y;
+          v[u][r] = cmul(v[u][r], w);
+        }
+      } else {
+        // powers of the first twiddle (one table read; error grows by an ulp a power)
+        double2 w1 = tw[k * stride];
+        if (INV) w1.y = -w1.y;
+        double2 w = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[u][r] = cmul(v[u][r], w);
+          w = cmul(w, w1);
+        }
+      }
+      butterfly_any<R, INV>(v[u]);
+      double2* d = a + line * ls + ((jj - k) * R + k) * es;
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r * sout] = v[u][out_pos<R>(r)];
+    }
+  }
+  __syncthreads();
+}
+
+// `lines` transforms of P.n points, element i of line l at a[l * ls + i * es];
+// plan P.rc_ip: radices 2, 3, 4, 5, 8, 16 (radix - 1 in four bits a pass)
+template <bool INV>
+__device__ void ip_fft(double2* a, int lines, int ls, int es, const FftPlan& P, const double2* tw, int tid) {
+  const unsigned ml = magic32(lines);
+  int Ns = 1;
+  for (int ps = 0; ps < P.np_ip; ++ps) {
+    const int R = (int)((P.rc_ip >> (4 * ps)) & 15u) + 1;
+    switch (R) {
+      case 2: ip_pass<2, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 3: ip_pass<3, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 4: ip_pass<4, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 5: ip_pass<5, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 8: ip_pass<8, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      default: ip_pass<16, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+    }
+    Ns *= R;
+  }
+}
+
+__global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, int one,
+                                                             const int* __restrict__ blk_off, int blk0,
+                                                             double* __restrict__ phi_out, long long phi_shift,
+                                                             int* __restrict__ far_reset) {
+  // the sort of this step has read the far list: empty it for this step's push
+  if (far_reset && blockIdx.x == 0 && threadIdx.x == 0) *far_reset = 0;
+  extern __shared__ double2 lds[];
+  Ens E;
+  int j;
+  block_ens(C, Eone, one, blk_off, blk0, E, j);
+  if (!E.plane) return;  // transformed by the z and x kernels
+  const int nx = E.nx, nz = E.nz, nh = E.nh, half = nx >> 1, tid = threadIdx.x;
+  double2* twz = lds;
+  double2* twx = twz + nz;
+  double2* pl = twx + nx;  // [nz][nh]
+  // twiddles (nx, nz <= kBlock < threads) in flight with the plane loads
+  const double2 tzv = C.tw[E.fz.tw_off + min(tid, nz - 1)];
+  const double2 txv = C.tw[E.fx.tw_off + min(tid, nx - 1)];
+  const double2* sp = C.spec + E.s_off + (long long)j * nz * E.nhp;
+  const int np = nz * nh;
+  const unsigned mnh = magic32(nh);
+  staged_copy<8>(
+      np, tid, kPlaneThreads,
+      [&](int t) {
+        const int k = fdiv32(t, mnh, nh);
+        return sp[k * E.nhp + (t - k * nh)];
+      },
+      [&](int t, double2 v) { pl[t] = v; });
+  if (tid < nz) twz[tid] = tzv;
+  if (tid < nx) twx[tid] = txv;
+  __syncthreads();
+  // inverse z transform of the nh columns
+  ip_fft<true>(pl, nh, 1, nh, E.fz, twz, tid);
+  // rows (2p, 2p+1) as one complex line: Z = X_A + i X_B (Hermitian halves
+  // extended; imaginary parts at m = 0 and nx/2 dropped), written over the pair
+  constexpr int UZ = (kPlanePts + kPlaneThreads - 1) / kPlaneThreads;
+  const int npt = (nz >> 1) * nx;
+  const unsigned mnx = magic32(nx);
+  double2 z[UZ];
+#pragma unroll
+  for (int u = 0; u < UZ; ++u) {
+    const int t = tid + u * kPlaneThreads;
+    if (t < npt) {
+      const int p = fdiv32(t, mnx, nx), i = t - p * nx;
+      const int m = i <= half ? i : nx - i;
+      const double2 A = pl[(2 * p) * nh + m], B = pl[(2 * p + 1) * nh + m];
+      if (i == 0 || i == half) z[u] = make_double2(A.x, B.x);
+      else if (i < half) z[u] = make_double2(A.x - B.y, A.y + B.x);
+      else z[u] = make_double2(A.x + B.y, B.x - A.y);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UZ; ++u) {
+    const int t = tid + u * kPlaneThreads;
+    if (t < npt) {
+      const int p = fdiv32(t, mnx, nx), i = t - p * nx;
+      pl[(2 * p) * nh + i] = z[u];
+    }
+  }
+  __syncthreads();
+  // inverse x transform of the nz / 2 packed lines (pitch 2 nh >= nx)
+  ip_fft<true>(pl, nz >> 1, 2 * nh, 1, E.fx, twx, tid);
+  const double sc = (1.0 / (double)nz) * (1.0 / (double)nx);
+  double* out = phi_out + (E.c_off - phi_shift) + (long long)j * nz * nx;
+  for (int t = tid; t < npt; t += kPlaneThreads) {
+    const int p = fdiv32(t, mnx, nx), i = t - p * nx;
+    const double2 v = pl[(2 * p) * nh + i];
+    out[(2 * p) * nx + i] = v.x * sc;
+    out[(2 * p + 1) * nx + i] = v.y * sc;
   }
 }
 
@@ -1384,14 +1650,32 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
-    // columns + factors of the largest tile (tm * ny entries each)
-    const size_t tl = (size_t)2 * G.tri_eq_max * sizeof(double2) + (size_t)tri_pad(G.ny_max) * sizeof(double);
-    k_tri<<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0, G.tri_eq_max);
+    // rows per lane: the largest over the ensembles; tile [tm][G][R | 1] plus a pad per mode
+    const int R = G.tri_rows;
+    const size_t tl = ((size_t)kBlock * (R | 1) + kBlock) * sizeof(double2);
+    switch (R) {
+#define TRI_CASE(r) \
+  case r: k_tri<r><<<nt, kBlock, tl, st>>>(C, Eone, one, G.d_tri_blk, t0); break;
+      TRI_CASE(1) TRI_CASE(2) TRI_CASE(3) TRI_CASE(4) TRI_CASE(5) TRI_CASE(6) TRI_CASE(7) TRI_CASE(8)
+      TRI_CASE(9) TRI_CASE(10) TRI_CASE(11) TRI_CASE(12) TRI_CASE(13) TRI_CASE(14) TRI_CASE(15) TRI_CASE(16)
+#undef TRI_CASE
+      default: break;  // rejected at tf_init
+    }
   }
   mark(2);
-  if (nzb > 0) k_fftz<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
+  // inverse transforms: one block per y plane for the ensembles whose plane
+  // fits the LDS (counted as the z phase), z then x kernels for the others;
+  // the blocks of the other kind exit at once
+  const bool fused = one ? Eone.plane != 0 : G.plane_any != 0;
+  const bool split = one ? Eone.plane == 0 : G.split_any != 0;
+  if (fused) {
+    const int p0 = G.pl_blk[e0], np = G.pl_blk[e1] - p0;
+    const size_t lp = (size_t)(G.nx_max + G.nz_max + G.plane_max) * sizeof(double2);
+    if (np > 0) k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, far_reset);
+  }
+  if (split && nzb > 0) k_fftz<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
   mark(3);
-  if (nb > 0)
+  if (split && nb > 0)
     k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset);
   mark(4);
   return hipGetLastError();

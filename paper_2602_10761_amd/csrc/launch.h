@@ -24,14 +24,18 @@ struct LaunchGeo {
   int nx_max, nz_max;
   int wz;          // spectral columns per block in the z transforms
   int ny_max;
-  int tri_eq_max;  // largest tm * ny over the ensembles (LDS sizing)
+  int tri_rows;    // rows per lane of the tridiagonal scans (largest over the ensembles)
   int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
+  int plane_any, split_any;  // some ensembles with / without fused inverse transforms
+  int plane_max;   // largest nz (nx/2 + 1) over the fused ensembles
   const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block
   const int* fz_blk;
   const int* tri_blk;
   const int* d_fp_blk;
   const int* d_fz_blk;
   const int* d_tri_blk;
+  const int* pl_blk;  // fused inverse transforms: one block per y plane
+  const int* d_pl_blk;
   const Ens* eh;   // host copies of the ensemble descriptors
 };
 

@@ -18,7 +18,9 @@ constexpr double kInv4Pi = 1.0 / (4.0 * 3.14159265358979323846);
 // (rcode >> 3p) & 7, passes in order.
 struct FftPlan {
   int n, npass, tw_off;
-  unsigned rcode;
+  unsigned rcode;   // radices 2..5, three bits a pass
+  int np_ip;
+  unsigned rc_ip;   // in-place passes: radix - 1 (radices 2, 3, 4, 5, 8, 16), four bits a pass
 };
 
 // One ensemble as seen by the kernels.
@@ -33,6 +35,7 @@ struct Ens {
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
   int wz, tm;        // tile shapes: z-transform columns, tridiagonal modes per block
+  int plane;         // inverse transforms fused per y plane (the plane fits the LDS)
   double lx, ly, lz, dx, dz;
   double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
   // derived on the host
@@ -53,11 +56,11 @@ inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
 
-// rows per register chunk of the tridiagonal sweeps; tiles are padded to it
-constexpr int kTriChunk = 16;
-__host__ __device__ inline int tri_pad(int ny) { return (ny + kTriChunk - 1) / kTriChunk * kTriChunk; }
 // LDS per block available on gfx950
 constexpr int kLdsMax = 163840;
+// fused inverse transforms of a y plane: threads per block, largest nz (nx/2 + 1)
+constexpr int kPlaneThreads = 768;
+constexpr int kPlanePts = 10240;
 
 // Particle buffer (structure of arrays).  key = global cell of the position.
 struct PState {

@@ -237,7 +237,9 @@ def test_batched_equals_plain():
     specs = [W.CONFIGS[1].replace(nx=16, ny=24, nz=32, n_particles=2500, v_jitter=3.0, precharge=0.2),
              W.CONFIGS[1].replace(re_tau=300.0, nx=48, ny=40, nz=20, n_particles=7000, v_jitter=2.0, d_choices=(1.0,)),
              W.CONFIGS[1].replace(nx=8, ny=8, nz=8, n_particles=0),
-             W.CONFIGS[1].replace(re_tau=550.0, nx=40, ny=16, nz=12, n_particles=1, v_jitter=1.0)]
+             W.CONFIGS[1].replace(re_tau=550.0, nx=40, ny=16, nz=12, n_particles=1, v_jitter=1.0),
+             # plane too large for the fused inverse transforms (nz (nx/2 + 1) > 10240)
+             W.CONFIGS[1].replace(nx=256, ny=6, nz=96, n_particles=3000, v_jitter=2.0)]
     ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
     sim = sim_of(ens, graphs=True)
     sim.step(9)
