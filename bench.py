@@ -32,6 +32,13 @@ KERNEL_SOURCES = ["paper_2602_10761_amd/csrc/kernels.hip", "paper_2602_10761_amd
                   "paper_2602_10761_amd/csrc/tribo_dev.h"]
 
 
+def plane_fused(nx, nz):
+    """Whether the library runs both inverse transforms of a y plane in one block
+    (half spectrum of the plane and twiddles within 160 KiB, at most 10240 points)."""
+    pts = nz * (nx // 2 + 1)
+    return pts <= 10240 and 16 * (nx + nz + pts) <= 163840
+
+
 def algorithmic_bytes(phase, n_p, nx, ny, nz):
     """Bytes each kernel group must move per launch (FP64 state, int32 keys)."""
     n_c = nx * ny * nz
@@ -51,9 +58,10 @@ def algorithmic_bytes(phase, n_p, nx, ny, nz):
         "fftz_fwd": 2 * spec,
         # spectrum in and out, Thomas factors (16 B per mode and row)
         "tridiag": 3 * spec,
-        "fftz_inv": 2 * spec,
-        # spectrum in, phi out
-        "ifftx": spec + 8 * n_c,
+        # inverse transforms: fused per y plane (spectrum in, phi out) when the
+        # plane fits one block's LDS, else z (spectrum in and out) then x
+        "fftz_inv": spec + 8 * n_c if plane_fused(nx, nz) else 2 * spec,
+        "ifftx": 0 if plane_fused(nx, nz) else spec + 8 * n_c,
         # row-pair counts in, row-pair starts out
         "sort": 4 * ny * nz,
     }[phase]

@@ -218,7 +218,8 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  *              more take a second pass through global memory); 0 = about 2.5
  *              times the mean pair, -1 = none (always two passes), else
  *              1..4096 (clamped to what fits 64 KiB of LDS per block)
- *   fz_cols    spectral columns per block of the z transforms (1..64)
+ *   fz_cols    spectral columns per block of the z transforms (1..64, and
+ *              fz_cols nz <= 2048)
  *   tri_modes  Fourier modes per block of the tridiagonal solves: 4, 8, 16
  *              or 32 (the block's 256 threads split evenly among them; a
  *              mode's lanes must cover ny with at most 16 rows each)

@@ -18,9 +18,9 @@ from . import workload as W
 
 CACHE = os.environ.get("TRIBO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                         "tune_cache.json"))
-FZ_COLS = (2, 4, 5, 8, 13, 16, 22, 33)
+FZ_COLS = (4, 8, 12, 16)
 # bumped whenever the tiled kernels change shape semantics (older entries are ignored)
-KERNEL_REV = 5
+KERNEL_REV = 6
 
 
 def _arch() -> str:

@@ -143,13 +143,14 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     if (tm != 4 && tm != 8 && tm != 16 && tm != 32) return fail(TF_EINVAL, "tri_modes must be 4, 8, 16 or 32");
     const int rows = (E.ny + kBlock / tm - 1) / (kBlock / tm);
     if (rows > 16) return fail(TF_ESIZE, "tri_modes too large for ny (more than 16 rows per lane)");
+    if (wz * E.nz > kZPts) return fail(TF_ESIZE, "fz_cols times nz exceeds the z-transform tile (2048 points)");
     S->e_wz[e] = wz;
     S->e_tm[e] = tm;
     S->wz = std::max(S->wz, wz);
     S->tri_rows = std::max(S->tri_rows, rows);
   }
   const size_t lds_fx = (size_t)9 * S->nx_max * 16;  // twiddles + 4 waves x 2 line buffers
-  const size_t lds_fz = (size_t)(2 * S->wz * (S->nz_max + 1) + S->nz_max) * 16;
+  const size_t lds_fz = (size_t)(S->wz * S->nz_max + S->nz_max) * 16;
   const size_t lds_tri = ((size_t)kBlock * (S->tri_rows | 1) + kBlock) * 16;
   if (lds_fx > 65536 || lds_fz > (size_t)kLdsMax || lds_tri > (size_t)kLdsMax)
     return fail(TF_ESIZE, "tile shapes exceed the LDS of a block");

@@ -928,63 +928,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
 }
 
 // ---------------------------------------------------------------------------
-// FFT along z on the half spectrum: block = (ensemble, y plane, wz columns)
-// ---------------------------------------------------------------------------
-template <bool INV>
-__global__ __launch_bounds__(kBlock) void k_fftz(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
-                                             int wmax, int nmax) {
-  extern __shared__ double2 lds[];
-  double2* buf0 = lds;
-  double2* buf1 = lds + wmax * (nmax + 1);
-  double2* tw = lds + 2 * wmax * (nmax + 1);
-  Ens E;
-  int lb;
-  if (one) {
-    E = Eone;
-    lb = blockIdx.x;
-  } else {
-    const int gb = blk0 + blockIdx.x;
-    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
-    E = C.ens[e];
-    lb = gb - blk_off[e];
-  }
-  if (INV && E.plane) return;  // fused inverse transforms of the plane
-  const int nz = E.nz, nh = E.nh, nhp = E.nhp;
-  const int wz = E.wz;
-  const int pitch = nz + 1;  // odd pitch (in 16-byte units): no bank conflicts in the transposes
-  const int nchunk = (nh + wz - 1) / wz;
-    const int j = fdiv32(lb, magic32(nchunk), nchunk);
-  const int m0 = (lb - j * nchunk) * wz;
-  const int w = min(wz, nh - m0);
-  const double2* __restrict__ twg = C.tw + E.fz.tw_off;
-  // twiddles (nz <= kBlock = blockDim): the load is in flight with the column loads
-  const double2 twv = twg[min((int)threadIdx.x, nz - 1)];
-  double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
-  const unsigned mw = magic32(w);
-  staged_copy<8>(
-      w * nz, threadIdx.x, blockDim.x,
-      [&](int t) {
-        const int k = fdiv32(t, mw, w), c = t - k * w;
-        return sp[k * nhp + c];
-      },
-      [&](int t, double2 v) {
-        const int k = fdiv32(t, mw, w), c = t - k * w;
-        buf0[c * pitch + k] = v;
-      });
-  if ((int)threadIdx.x < nz) tw[threadIdx.x] = twv;
-  __syncthreads();
-  FftPlan P = E.fz;
-  double2* res = lds_fft<INV>(buf0, buf1, w, pitch, P, tw, threadIdx.x, blockDim.x);
-  const double sc = INV ? 1.0 / (double)nz : 1.0;
-  for (int t = threadIdx.x; t < w * nz; t += blockDim.x) {
-    const int k = fdiv32(t, mw, w), c = t - k * w;
-    double2 v = res[c * pitch + k];
-    if (INV) v = make_double2(v.x * sc, v.y * sc);
-    sp[k * nhp + c] = v;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // tridiagonal solve in y for a tile of Fourier modes (mz, mx):
 //   -am_j phi_{j-1} + (am_j + ap_j + k^2) phi_j - ap_j phi_{j+1} = rho_j
 // (FV Laplacian times -1, phi = 0 on both walls).  With the Thomas factors
@@ -1201,16 +1144,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
 // The transforms run in place: every Stockham pass loads its butterflies'
 // inputs into registers, synchronises the block, then writes the outputs.
 // ---------------------------------------------------------------------------
-template <int R, bool INV>
+template <int R, bool INV, int NT, int MAXPTS>
 __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, int ls, int es, int n, int Ns,
                                         const double2* __restrict__ tw, int tid) {
-  constexpr int UM = (kPlanePts / R + kPlaneThreads - 1) / kPlaneThreads;
+  constexpr int UM = (MAXPTS / R + NT - 1) / NT;
   const int nb = n / R, stride = n / (Ns * R), total = lines * nb;
   const int sin_ = nb * es, sout = Ns * es;  // element steps of a butterfly's inputs and outputs
   double2 v[UM][R];
 #pragma unroll
   for (int u = 0; u < UM; ++u) {
-    const int t = tid + u * kPlaneThreads;
+    const int t = tid + u * NT;
     if (t < total) {
       const int jj = fdiv32(t, mlines, lines), line = t - jj * lines;
       const double2* s = a + line * ls + jj * es;
@@ -1223,7 +1166,7 @@ __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, 
   const unsigned mns = ns2 ? 0u : magic32(Ns);
 #pragma unroll
   for (int u = 0; u < UM; ++u) {
-    const int t = tid + u * kPlaneThreads;
+    const int t = tid + u * NT;
     if (t < total) {
       const int jj = fdiv32(t, mlines, lines), line = t - jj * lines;
       const int k = ns2 ? (jj & (Ns - 1)) : jj - fdiv32(jj, mns, Ns) * Ns;
@@ -1256,21 +1199,73 @@ __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, 
 
 // `lines` transforms of P.n points, element i of line l at a[l * ls + i * es];
 // plan P.rc_ip: radices 2, 3, 4, 5, 8, 16 (radix - 1 in four bits a pass)
-template <bool INV>
+template <bool INV, int NT, int MAXPTS>
 __device__ void ip_fft(double2* a, int lines, int ls, int es, const FftPlan& P, const double2* tw, int tid) {
   const unsigned ml = magic32(lines);
   int Ns = 1;
   for (int ps = 0; ps < P.np_ip; ++ps) {
     const int R = (int)((P.rc_ip >> (4 * ps)) & 15u) + 1;
     switch (R) {
-      case 2: ip_pass<2, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 3: ip_pass<3, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 4: ip_pass<4, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 5: ip_pass<5, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 8: ip_pass<8, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      default: ip_pass<16, INV>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 2: ip_pass<2, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 3: ip_pass<3, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 4: ip_pass<4, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 5: ip_pass<5, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      case 8: ip_pass<8, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
+      default: ip_pass<16, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
     }
     Ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FFT along z of the half spectrum: block = (ensemble, y plane, wz columns);
+// the tile [c][k] (wz nz <= kZPts points) is transformed in place in LDS
+// ---------------------------------------------------------------------------
+template <bool INV>
+__global__ __launch_bounds__(kBlock) void k_z(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off, int blk0,
+                                              int nmax) {
+  extern __shared__ double2 lds[];
+  Ens E;
+  int lb;
+  block_ens(C, Eone, one, blk_off, blk0, E, lb);
+  if (INV && E.plane) return;  // fused inverse transforms of the plane
+  const int nz = E.nz, nh = E.nh, nhp = E.nhp, wz = E.wz;
+  const int nchunk = (nh + wz - 1) / wz;
+  const int j = fdiv32(lb, magic32(nchunk), nchunk);
+  const int m0 = (lb - j * nchunk) * wz;
+  const int w = min(wz, nh - m0);
+  double2* tw = lds;
+  double2* tile = lds + nmax;  // [k][c], pitch w: consecutive threads take consecutive columns
+  // twiddles (nz <= kBlock): the load is in flight with the column loads
+  const double2 twv = C.tw[E.fz.tw_off + min((int)threadIdx.x, nz - 1)];
+  double2* sp = C.spec + E.s_off + (long long)j * nz * nhp + m0;
+  const unsigned mw = magic32(w);
+  staged_copy<8>(
+      w * nz, threadIdx.x, kBlock,
+      [&](int t) {
+        const int k = fdiv32(t, mw, w);
+        return sp[k * nhp + (t - k * w)];
+      },
+      [&](int t, double2 v) { tile[t] = v; });
+  if ((int)threadIdx.x < nz) tw[threadIdx.x] = twv;
+  __syncthreads();
+  ip_fft<INV, kBlock, kZPts>(tile, w, 1, w, E.fz, tw, threadIdx.x);
+  __syncthreads();
+  const double sc = INV ? 1.0 / (double)nz : 1.0;
+  for (int t0 = threadIdx.x; t0 < w * nz; t0 += 4 * kBlock) {
+    double2 r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = tile[min(t0 + u * kBlock, w * nz - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kBlock;
+      if (t < w * nz) {
+        const int k = fdiv32(t, mw, w);
+        double2 v = r[u];
+        if (INV) v = make_double2(v.x * sc, v.y * sc);
+        sp[k * nhp + (t - k * w)] = v;
+      }
+    }
   }
 }
 
@@ -1306,7 +1301,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
   if (tid < nx) twx[tid] = txv;
   __syncthreads();
   // inverse z transform of the nh columns
-  ip_fft<true>(pl, nh, 1, nh, E.fz, twz, tid);
+  ip_fft<true, kPlaneThreads, kPlanePts>(pl, nh, 1, nh, E.fz, twz, tid);
   // rows (2p, 2p+1) as one complex line: Z = X_A + i X_B (Hermitian halves
   // extended; imaginary parts at m = 0 and nx/2 dropped), written over the pair
   constexpr int UZ = (kPlanePts + kPlaneThreads - 1) / kPlaneThreads;
@@ -1336,7 +1331,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
   }
   __syncthreads();
   // inverse x transform of the nz / 2 packed lines (pitch 2 nh >= nx)
-  ip_fft<true>(pl, nz >> 1, 2 * nh, 1, E.fx, twx, tid);
+  ip_fft<true, kPlaneThreads, kPlanePts>(pl, nz >> 1, 2 * nh, 1, E.fx, twx, tid);
   const double sc = (1.0 / (double)nz) * (1.0 / (double)nx);
   double* out = phi_out + (E.c_off - phi_shift) + (long long)j * nz * nx;
   for (int t = tid; t < npt; t += kPlaneThreads) {
@@ -1645,8 +1640,8 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
     k_pair_fftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, q_in, q_shift, r_in, do_stats);
   mark(0);
   const int z0 = G.fz_blk[e0], nzb = G.fz_blk[e1] - z0;
-  const size_t lz = (size_t)(2 * G.wz * (G.nz_max + 1) + G.nz_max) * sizeof(double2);  // wz: largest over ensembles
-  if (nzb > 0) k_fftz<false><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
+  const size_t lz = (size_t)(G.wz * G.nz_max + G.nz_max) * sizeof(double2);  // wz: largest over ensembles
+  if (nzb > 0) k_z<false><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.nz_max);
   mark(1);
   const int t0 = G.tri_blk[e0], nt = G.tri_blk[e1] - t0;
   if (nt > 0) {
@@ -1673,7 +1668,7 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
     const size_t lp = (size_t)(G.nx_max + G.nz_max + G.plane_max) * sizeof(double2);
     if (np > 0) k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, far_reset);
   }
-  if (split && nzb > 0) k_fftz<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.wz, G.nz_max);
+  if (split && nzb > 0) k_z<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.nz_max);
   mark(3);
   if (split && nb > 0)
     k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset);

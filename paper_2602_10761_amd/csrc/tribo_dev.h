@@ -61,6 +61,8 @@ constexpr int kLdsMax = 163840;
 // fused inverse transforms of a y plane: threads per block, largest nz (nx/2 + 1)
 constexpr int kPlaneThreads = 768;
 constexpr int kPlanePts = 10240;
+// z transforms: largest tile of wz columns times nz points
+constexpr int kZPts = 2048;
 
 // Particle buffer (structure of arrays).  key = global cell of the position.
 struct PState {
