@@ -67,6 +67,7 @@ typedef struct tf_handle tf_handle;
 /* tf_init flags */
 #define TF_INIT_KEEP_DEPOSIT 1u   /* also store each step's per-cell fixed-point charge */
 #define TF_INIT_GRAPHS 2u         /* replay steps from captured HIP graphs */
+#define TF_INIT_SOURCE 4u         /* also compute each step's 2-way coupling source (TF_FIELD_SOURCE) */
 
 /* tf_step flags */
 #define TF_STEP_RECORD 1u         /* record the steps for tf_adjoint_step (needs trajectory capacity) */
@@ -187,10 +188,16 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
 int tf_poisson(tf_handle* h, int32_t ens, const int64_t* q_fixed, double* phi);
 
 /* Copy a field of the latest step of ensemble `ens` to device memory `out`:
- * TF_FIELD_PHI (double [ncell]) or, with TF_INIT_KEEP_DEPOSIT,
- * TF_FIELD_DEPOSIT (int64 [ncell]). */
+ * TF_FIELD_PHI (double [ncell]); with TF_INIT_KEEP_DEPOSIT, TF_FIELD_DEPOSIT
+ * (int64 [ncell]); with TF_INIT_SOURCE, TF_FIELD_SOURCE (double [3][ncell],
+ * component-major): the momentum source F_s of the carrier equation
+ * (Sec. 2.1, 2-way coupling), minus the aerodynamic forces on the particles
+ * of each cell (cell of x^n) per unit cell volume, the force on a particle
+ * being the step's implicit drag m_p (phi_D / tau_p)(u - v^{n+1}),
+ * m_p = rho_r pi d^3 / 6, fluid density 1.  Asynchronous on the stream. */
 #define TF_FIELD_PHI 0
 #define TF_FIELD_DEPOSIT 1
+#define TF_FIELD_SOURCE 2
 int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
 
 /*

@@ -307,6 +307,32 @@ def _sum_by(index, values, n):
 
 
 # ----------------------------------------------------------------------------
+# 2-way coupling: momentum source of the carrier
+# ----------------------------------------------------------------------------
+def two_way_source(g: Geo, cid: np.ndarray, d: np.ndarray, sdr: np.ndarray, u, v1, rr: float) -> np.ndarray:
+    """Source term F_s of the carrier momentum equation (Sec. 2.1): the
+    aerodynamic forces on the particles of a grid cell, summed and fed back to
+    the fluid with the opposite sign, per unit fluid mass (fluid density 1 in
+    these units), i.e. divided by the cell volume.
+
+    Reading: the force on a particle over the step is the drag of the
+    semi-implicit update, f_ad = m_p (phi_D / tau_p) (u - v^{n+1}), with
+    m_p = rho_r pi d^3 / 6, so that the particles' drag impulse and the
+    fluid's source balance exactly; the cell is the one of x^n (where the
+    particle's charge is deposited).  Returns [3][ncell] (cell index
+    (j nz + k) nx + i), summed over particles in ascending id.
+    """
+    mp = (rr * (math.pi / 6.0)) * ((d * d) * d)
+    jrow = np.repeat(np.arange(g.ny), g.nz * g.nx)  # y row of every cell
+    out = np.zeros((3, g.ncell))
+    for c in range(3):
+        f = (mp * sdr) * (u[c] - v1[c])
+        np.add.at(out[c], cid, f)
+        out[c] = -out[c] / g.vol[jrow]
+    return out
+
+
+# ----------------------------------------------------------------------------
 # One step
 # ----------------------------------------------------------------------------
 KEYS = ("x", "y", "z", "vx", "vy", "vz", "q", "d")
@@ -419,7 +445,8 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
         record.append(dict(i=i, j=j, k=k, wall=wall, wx=wx, wz=wz))
     if want is not None:
         want.update(Q=Q, phi=phi, E=(Ex, Ey, Ez), u=(ux, uy, uz), coul=(sx, sy, sz), cid=cid,
-                    wall=wall, un=un, dq=dq)
+                    wall=wall, un=un, dq=dq,
+                    fs=two_way_source(g, cid, d, sdr, (ux, uy, uz), (v1x, v1y, v1z), rr))
     return dict(x=x1, y=yr, z=z1, vx=v1x, vy=vyr, vz=v1z, q=q1, d=d)
 
 

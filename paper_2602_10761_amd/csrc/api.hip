@@ -279,6 +279,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.spec = cv.take<double2>(S.s_tot);
   C.phi = cv.take<double>(S.c_tot);
   C.qdep = (flags & TF_INIT_KEEP_DEPOSIT) ? cv.take<long long>(S.c_tot) : nullptr;
+  C.fslot = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.n_tot) : nullptr;
+  C.fsrc = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.c_tot) : nullptr;
   std::vector<TrajBuf> traj;
   if (traj_steps > 0) {
     for (int t = 0; t <= traj_steps; ++t) {
@@ -358,6 +360,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)
     return e;
+  if (h->C.fsrc && (e = launch_source(h->C, h->stream)) != hipSuccess) return e;
   if (ev[TF_NPHASE] && (e = hipEventRecord(ev[TF_NPHASE], h->stream)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -422,7 +425,7 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
 size_t tf_workspace_size(const tf_ensemble* ens, int32_t n_ens, int32_t traj_steps) {
   Sizes S;
   if (check_config(ens, n_ens, &S) != TF_OK || traj_steps < 0) return 0;
-  return layout(S, n_ens, traj_steps, TF_INIT_KEEP_DEPOSIT, nullptr, nullptr);
+  return layout(S, n_ens, traj_steps, TF_INIT_KEEP_DEPOSIT | TF_INIT_SOURCE, nullptr, nullptr);
 }
 
 int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, void* workspace,
@@ -607,6 +610,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_new, 0, sizeof(int) * (S.rows + 1), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.far_n, 0, sizeof(int) * 2, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.phi, 0, sizeof(double) * S.c_tot, h->stream);
+  if (he == hipSuccess && h->C.fsrc && S.c_tot)
+    he = hipMemsetAsync(h->C.fsrc, 0, sizeof(double) * 3 * S.c_tot, h->stream);
   for (int e = 0; e < n_ens && he == hipSuccess; ++e) {
     if (ens[e].n_particles == 0) continue;
     const tf_particles& P = init[e];
@@ -842,6 +847,11 @@ int tf_field(tf_handle* h, int32_t e, int32_t which, void* out) {
     if (!h->C.qdep) return fail(TF_ESTATE, "deposit not kept (TF_INIT_KEEP_DEPOSIT)");
     HIPCHK(hipMemcpyAsync(out, h->C.qdep + h->c_off[e], ncell * sizeof(long long), hipMemcpyDeviceToDevice,
                           h->stream));
+  } else if (which == TF_FIELD_SOURCE) {
+    if (!h->C.fsrc) return fail(TF_ESTATE, "source not computed (TF_INIT_SOURCE)");
+    for (int c = 0; c < 3; ++c)
+      HIPCHK(hipMemcpyAsync((double*)out + c * ncell, h->C.fsrc + c * h->C.c_tot + h->c_off[e],
+                            ncell * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   } else {
     return fail(TF_EINVAL, "unknown field");
   }

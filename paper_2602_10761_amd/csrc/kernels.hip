@@ -1453,6 +1453,15 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   out.q[s] = q1;
   out.d[s] = d;
   out.id[s] = in.id[p];
+  if (C.fslot) {
+    // drag force of the step on this particle (2-way coupling source)
+    const double mp = (E.rr * (kPi / 6.0)) * ((d * d) * d);
+    const double ms = mp * F.sdr;
+    const long long n = C.n_tot;
+    C.fslot[s] = ms * (F.u[0] - v1x);
+    C.fslot[n + s] = ms * (F.u[1] - v1y);
+    C.fslot[2 * n + s] = ms * (F.u[2] - v1z);
+  }
   // next cell: exact divisions in x, z; local face search in y from the old cell
   const int ni = clamp_floor(x1 / E.dx, nx);
   const int nk = clamp_floor(z1 / E.dz, nz);
@@ -1682,6 +1691,35 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
   const int nb = std::max(1, (int)((C.n_tot + kBlock - 1) / kBlock));
   const int one = (C.n_ens == 1) ? 1 : 0;
   k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  return hipGetLastError();
+}
+
+// 2-way coupling source: minus the summed drag forces of a cell's particles
+// (its slot range, ascending id) per unit cell volume
+__global__ __launch_bounds__(kBlock) void k_source(Ctx C) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= C.c_tot) return;
+  const int e = find_off(C.c_off, C.n_ens + 1, c);
+  const Ens& E = C.ens[e];
+  const int j = (int)((c - E.c_off) / ((long long)E.nx * E.nz));
+  const double vol = C.vol[E.y_off + j];
+  const int a = C.start[c], b = C.start[c + 1];
+  const long long n = C.n_tot;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int t = a; t < b; ++t) {
+    fx += C.fslot[t];
+    fy += C.fslot[n + t];
+    fz += C.fslot[2 * n + t];
+  }
+  C.fsrc[c] = -fx / vol;
+  C.fsrc[C.c_tot + c] = -fy / vol;
+  C.fsrc[2 * C.c_tot + c] = -fz / vol;
+}
+
+hipError_t launch_source(const Ctx& C, hipStream_t st) {
+  if (C.c_tot == 0) return hipSuccess;
+  const int nb = (int)((C.c_tot + kBlock - 1) / kBlock);
+  k_source<<<nb, kBlock, 0, st>>>(C);
   return hipGetLastError();
 }
 

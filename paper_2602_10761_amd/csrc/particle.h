@@ -19,6 +19,9 @@ __device__ __forceinline__ int y_cell_from(const double* __restrict__ yf, int ny
   return j;
 }
 
+// two doubles with 8-byte alignment (one dwordx4 load)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
 struct Fwd {
   int i, j, k, i1, k1, n00, n01, n10, n11, plane;
   double x, y, z, vx, vy, vz, q, d;
@@ -63,10 +66,24 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
     const double* __restrict__ b = E.U + cc * plane;
-    const double c00 = b[n00 + i] * (1.0 - tx) + b[n00 + i1] * tx;
-    const double c01 = b[n01 + i] * (1.0 - tx) + b[n01 + i1] * tx;
-    const double c10 = b[n10 + i] * (1.0 - tx) + b[n10 + i1] * tx;
-    const double c11 = b[n11 + i] * (1.0 - tx) + b[n11 + i1] * tx;
+    // nodes i and i + 1 of a row as one 16-byte load (8-byte aligned) away
+    // from the periodic end of the row: half the gather instructions
+    d2u u00, u01, u10, u11;
+    if (i1 == i + 1) {
+      u00 = *reinterpret_cast<const d2u*>(b + n00 + i);
+      u01 = *reinterpret_cast<const d2u*>(b + n01 + i);
+      u10 = *reinterpret_cast<const d2u*>(b + n10 + i);
+      u11 = *reinterpret_cast<const d2u*>(b + n11 + i);
+    } else {
+      u00 = d2u{b[n00 + i], b[n00 + i1]};
+      u01 = d2u{b[n01 + i], b[n01 + i1]};
+      u10 = d2u{b[n10 + i], b[n10 + i1]};
+      u11 = d2u{b[n11 + i], b[n11 + i1]};
+    }
+    const double c00 = u00.x * (1.0 - tx) + u00.y * tx;
+    const double c01 = u01.x * (1.0 - tx) + u01.y * tx;
+    const double c10 = u10.x * (1.0 - tx) + u10.y * tx;
+    const double c11 = u11.x * (1.0 - tx) + u11.y * tx;
     const double c0 = c00 * (1.0 - tz) + c01 * tz;
     const double c1 = c10 * (1.0 - tz) + c11 * tz;
     uc[cc] = c0 * (1.0 - ty) + c1 * ty;
@@ -92,35 +109,29 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
 
   // near field: Coulomb's law with the other particles of the cell, ascending id
   double sx = 0.0, sy = 0.0, sz = 0.0;
+  auto coulomb = [&](double ox, double oy, double oz, double oq) {
+    const double rx = x - ox, ry = y - oy, rz = z - oz;
+    const double r2 = (rx * rx + ry * ry) + rz * rz;
+    if (r2 > 0.0) {
+      const double ri = rsqrt(r2);
+      const double w = oq * (ri * ri * ri);
+      sx += w * rx;
+      sy += w * ry;
+      sz += w * rz;
+    }
+  };
   {
     const int a = C.start[c], b = C.start[c + 1];
     for (int t = a; t < b; ++t) {
       if (t == s) continue;
-      double ox, oy, oz, oq;
-      if (SORTED) {
-        ox = C.sx[t];
-        oy = C.sy[t];
-        oz = C.sz[t];
-        oq = C.sq[t];
+      if constexpr (SORTED) {
+        coulomb(C.sx[t], C.sy[t], C.sz[t], C.sq[t]);
       } else {
         const int pj = C.perm[t];
-        ox = in.x[pj];
-        oy = in.y[pj];
-        oz = in.z[pj];
-        oq = in.q[pj];
-      }
-      const double rx = x - ox, ry = y - oy, rz = z - oz;
-      const double r2 = (rx * rx + ry * ry) + rz * rz;
-      if (r2 > 0.0) {
-        const double ri = rsqrt(r2);
-        const double w = oq * (ri * ri * ri);
-        sx += w * rx;
-        sy += w * ry;
-        sz += w * rz;
+        coulomb(in.x[pj], in.y[pj], in.z[pj], in.q[pj]);
       }
     }
   }
-
   // forces and semi-implicit Euler
   const double d2 = d * d;
   const double ke = (E.cel * q) / (d2 * d);

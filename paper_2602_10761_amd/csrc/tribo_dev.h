@@ -13,6 +13,7 @@ constexpr int kFixDep = 48;
 constexpr int kFixWall = 40;
 constexpr int kFixQcum = 32;
 constexpr double kInv4Pi = 1.0 / (4.0 * 3.14159265358979323846);
+constexpr double kPi = 3.14159265358979323846;
 
 // Complex FFT of length n, Stockham autosort; the radix of pass p is
 // (rcode >> 3p) & 7, passes in order.
@@ -103,6 +104,8 @@ struct Ctx {
   long long* rowq;           // [sum ny*nz] sum rne(q 2^48) per (j,k) row, latest deposit
   longlong2* rowacc;         // [sum ny*nz] (particle count, sum rne(q 2^32)) per row, summed over steps
   long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
+  double* fslot;             // optional [3][n_tot] drag force on the particle of each slot (2-way source)
+  double* fsrc;              // optional [3][c_tot] 2-way coupling source of the latest step
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
   const double2* tfac;       // Thomas factors per ensemble: [modes][ny] (1 / pivot, c')

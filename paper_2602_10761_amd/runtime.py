@@ -19,9 +19,11 @@ LIB_PATH = os.path.join(HERE, "libtribo.so")
 
 TF_INIT_KEEP_DEPOSIT = 1
 TF_INIT_GRAPHS = 2
+TF_INIT_SOURCE = 4
 TF_STEP_RECORD = 1
 TF_FIELD_PHI = 0
 TF_FIELD_DEPOSIT = 1
+TF_FIELD_SOURCE = 2
 TF_NBIN = 64
 TF_NPHASE = 7
 PHASES = ("sort", "deposit_fftx", "fftz_fwd", "tridiag", "fftz_inv", "ifftx", "push")
@@ -123,7 +125,7 @@ class TriboSim:
     """
 
     def __init__(self, ensembles: Sequence, device: str = "cuda", traj_steps: int = 0, graphs: bool = False,
-                 keep_deposit: bool = False):
+                 keep_deposit: bool = False, source: bool = False):
         import torch
 
         self.torch = torch
@@ -162,7 +164,8 @@ class TriboSim:
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.dev)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255
-        flags = (TF_INIT_KEEP_DEPOSIT if keep_deposit else 0) | (TF_INIT_GRAPHS if graphs else 0)
+        flags = ((TF_INIT_KEEP_DEPOSIT if keep_deposit else 0) | (TF_INIT_GRAPHS if graphs else 0) |
+                 (TF_INIT_SOURCE if source else 0))
         h = c_void_p()
         self.stream.wait_stream(torch.cuda.current_stream(self.dev))
         _check(self.L.tf_init(cfg, self.n_ens, init, c_void_p(self.ws_ptr), nbytes, traj_steps,
@@ -239,9 +242,12 @@ class TriboSim:
         return phi
 
     def field(self, e: int, which: int) -> "object":
+        """Latest step's field of ensemble e: phi [ncell], the fixed-point deposit
+        [ncell] or the 2-way coupling source [3][ncell] (cell (j nz + k) nx + i)."""
         E = self.ens[e].mesh
-        dt = self.torch.float64 if which == TF_FIELD_PHI else self.torch.int64
-        out = self.torch.empty(E.nx * E.ny * E.nz, dtype=dt, device=self.dev)
+        dt = self.torch.int64 if which == TF_FIELD_DEPOSIT else self.torch.float64
+        ncomp = 3 if which == TF_FIELD_SOURCE else 1
+        out = self.torch.empty(ncomp * E.nx * E.ny * E.nz, dtype=dt, device=self.dev)
         self._sync_in()
         _check(self.L.tf_field(self.h, e, which, out.data_ptr()))
         self._sync_out()

@@ -80,12 +80,13 @@ def test_one_step_parity(case):
               dense=dict(nx=8, ny=8, nz=8, n=20000, precharge=0.3, c_el=5.0, v_jitter=2.0),
               gravity=dict(g=(0.0, -0.02, 0.01), precharge=0.1, v_jitter=1.0))[case]
     ens = ens_small(**kw)
-    sim = sim_of(ens, keep_deposit=True)
+    sim = sim_of(ens, keep_deposit=True, source=True)
     sim.step(1)
     gpu = sim.state_np(0)
     gst = sim.stats(0)
     Qg = sim.field(0, 1).cpu().numpy()
     phig = sim.field(0, 0).cpu().numpy()
+    fsg = sim.field(0, 2).cpu().numpy().reshape(3, -1)
     g = O.Geo.from_mesh(ens.mesh)
     st = O.Stats(g.ny)
     want = {}
@@ -97,6 +98,11 @@ def test_one_step_parity(case):
     assert perr < TOL
     assert max(err.values()) < TOL
     assert_stats_equal(gst, st)
+    # 2-way coupling source: same cells, same summation order (ascending id)
+    fserr = np.abs(fsg - want["fs"]).max() / np.abs(want["fs"]).max()
+    say("  source err", fserr)
+    assert np.all((fsg == 0.0) == (want["fs"] == 0.0))
+    assert fserr < TOL
     sim.close()
 
 
@@ -241,15 +247,16 @@ def test_batched_equals_plain():
              # plane too large for the fused inverse transforms (nz (nx/2 + 1) > 10240)
              W.CONFIGS[1].replace(nx=256, ny=6, nz=96, n_particles=3000, v_jitter=2.0)]
     ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
-    sim = sim_of(ens, graphs=True)
+    sim = sim_of(ens, graphs=True, source=True)
     sim.step(9)
-    batched = [(sim.state_np(e), sim.stats(e)) for e in range(len(ens))]
+    batched = [(sim.state_np(e), sim.stats(e), sim.field(e, 2).cpu().numpy()) for e in range(len(ens))]
     sim.close()
     for e, E in enumerate(ens):
-        s1 = sim_of(E)
+        s1 = sim_of(E, source=True)
         s1.step(9)
-        st, ss = s1.state_np(0), s1.stats(0)
+        st, ss, fs = s1.state_np(0), s1.stats(0), s1.field(0, 2).cpu().numpy()
         s1.close()
+        np.testing.assert_array_equal(batched[e][2], fs)
         for k in KEYS:
             np.testing.assert_array_equal(batched[e][0][k], st[k])
         for k in ("impacts", "wallq", "crel_y", "qcum_y", "qnow_y", "unhist"):

@@ -388,3 +388,62 @@ def test_channel_invariants():
     r = 0.5 * s["d"]
     assert np.all((s["y"] >= r) & (s["y"] <= g.ly - r))
     assert np.all((s["x"] >= 0) & (s["x"] <= g.lx) & (s["z"] >= 0) & (s["z"] <= g.lz))
+
+
+# --------------------------------------------------------------------------
+# 2-way coupling source (Sec. 2.1): momentum balance with the particles
+# --------------------------------------------------------------------------
+def test_two_way_source_balances_particle_momentum():
+    # without gravity and electric forces the particles' momentum change over
+    # a step is their drag impulse, which the fluid receives with the opposite
+    # sign in the particles' cells of x^n: per cell, F_s V = -sum m_p dv / dt
+    ens = W.make_ensemble(W.CONFIGS[1].replace(n_particles=2000, v_jitter=3.0, density_ratio=100.0,
+                                               nx=8, ny=10, nz=6))
+    g = O.Geo.from_mesh(ens.mesh)
+    s = O.state_of(ens)
+    prm = dict(ens.params, c_el=0.0, g=(0.0, 0.0, 0.0))
+    want = {}
+    s1 = O.step(g, ens.U, s, prm, want=want)
+    dt, rr = prm["dt"], prm["density_ratio"]
+    mp = rr * math.pi / 6.0 * s["d"] ** 3
+    i, j, k = O.locate(g, s["x"], s["y"], s["z"])
+    cell = (j * g.nz + k) * g.nx + i
+    # wall impacts flip v_y after the drag: use the velocity before the rebound
+    hit = want["wall"] >= 0
+    vy1 = np.where(hit, -s1["vy"] / prm["e"], s1["vy"])
+    for c, (a, b) in enumerate((("vx", s1["vx"]), ("vy", vy1), ("vz", s1["vz"]))):
+        ref = np.zeros(g.ncell)
+        np.add.at(ref, cell, -mp * (b - s[a]) / dt)
+        vol = np.repeat(g.vol, g.nz * g.nx)
+        got = want["fs"][c] * vol
+        scale = np.abs(ref).max()
+        assert scale > 0
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * scale)
+    # cells without particles receive nothing
+    empty = np.setdiff1d(np.arange(g.ncell), cell)
+    assert np.all(want["fs"][:, empty] == 0.0)
+
+
+def test_two_way_source_single_particle_stokes():
+    # one particle at rest in a uniform stream, Re_p -> 0 (phi_D -> 1): the
+    # fluid loses 3 pi d u / (1 + dt / tau_p) per unit time (Stokes drag with
+    # the implicit update) in the particle's cell only
+    g = small_geo()
+    U = np.zeros((3, g.ny + 1, g.nz, g.nx))
+    u0 = 1e-7
+    U[0] = u0
+    s = zero_state(1)
+    d = 0.5
+    s["d"][:] = d
+    s["x"][:], s["y"][:], s["z"][:] = 1.3, g.ly / 2, 2.1
+    prm = dict(BASE, density_ratio=50.0)
+    want = {}
+    O.step(g, U, s, prm, want=want)
+    taup = 50.0 * d * d / 18.0
+    i, j, k = O.locate(g, s["x"], s["y"], s["z"])
+    c = int(((j * g.nz + k) * g.nx + i)[0])
+    expect = -(3.0 * math.pi * d * u0) / (1.0 + prm["dt"] / taup) / g.vol[j[0]]
+    assert want["fs"][0, c] == pytest.approx(expect, rel=1e-4)  # phi_D - 1 ~ Re_p^(2/3) / 6 ~ 1e-6
+    fs = want["fs"].copy()
+    fs[0, c] = 0.0
+    assert np.all(fs == 0.0)
