@@ -138,6 +138,28 @@ def batched_vs_plain(torch, W, R, autotune, steps, log):
             "particle_steps_per_s_batched": n_tot / (ms_b * 1e-3)}
 
 
+def source_cost(torch, W, R, steps, log):
+    """Extra time of the 2-way coupling source (per-particle drag force written
+    by the push, per-cell sums) on the headline workload, graph replays on and
+    off the source."""
+    ens = W.make_workload(2)[0]
+    m = ens.mesh
+    ms = {}
+    for on in (False, True):
+        sim = R.TriboSim([ens], graphs=True, source=on)
+        sim.step(3)
+        ms[on] = timed_steps(torch, sim, steps) / steps
+        sim.close()
+        del sim
+    n_c = m.nx * m.ny * m.nz
+    extra_bytes = 24 * ens.n + (4 * n_c + 24 * ens.n + 24 * n_c)  # push write; cell sums (starts, forces, source)
+    d_us = (ms[True] - ms[False]) * 1e3
+    log(f"2-way source: {ms[False] * 1e3:.1f} -> {ms[True] * 1e3:.1f} us/step")
+    return {"workload": WORKLOAD_NAME[2], "us_per_step_without": ms[False] * 1e3, "us_per_step_with": ms[True] * 1e3,
+            "extra_us_per_step": d_us, "extra_algorithmic_bytes": extra_bytes,
+            "extra_GBs": extra_bytes / (d_us * 1e-6) / 1e9 if d_us > 0 else None}
+
+
 def adjoint_ratio(torch, W, R, autotune, seg, log):
     ens = W.make_workload(5, v_jitter=3.0, precharge=0.02)[0]
     autotune.ensure_tuned(autotune.meshes_of([ens]))
@@ -179,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-source", action="store_true", help="skip the 2-way coupling source timing")
     ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (reference kernel for HBM byte counters)")
@@ -276,6 +299,8 @@ def main():
         out["batched"] = batched_vs_plain(torch, W, R, autotune, args.batched_steps, log)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, W, R, autotune, 50, log)
+    if not args.no_source:
+        out["two_way_source"] = source_cost(torch, W, R, 50, log)
     if not args.no_cpu:
         v, secs = cpu_baseline(ens, args.cpu_steps)
         out["cpu_baseline"] = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
