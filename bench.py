@@ -84,7 +84,7 @@ def measured_traffic(kernel):
     for line in open(TRAFFIC_FILE):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+            kv[k.strip()] = v.split("#", 1)[0].strip()
     if kv.get("source_hash") != source_hash():
         return None
     v = kv.get(f"{kernel}_bytes")

@@ -84,3 +84,17 @@ def test_init_rejects_without_touching_device():
     assert rc == -1 and not h.value
     assert b"nx" in L.tf_last_error()
     assert L.tf_error_string(-2) == b"size limit or workspace too small"
+
+
+def test_bench_traffic_file_parsing(tmp_path, monkeypatch):
+    # the committed HBM traffic summary carries comments after the values
+    import bench
+    f = tmp_path / "traffic.txt"
+    f.write_text("# header\nsource_hash: abc\npush_bytes: 123   # fetch 1 KiB raw\nsort_bytes: 7\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "source_hash", lambda: "abc")
+    assert bench.measured_traffic("push") == 123.0
+    assert bench.measured_traffic("sort") == 7.0
+    assert bench.measured_traffic("tridiag") is None
+    monkeypatch.setattr(bench, "source_hash", lambda: "other")
+    assert bench.measured_traffic("push") is None
