@@ -288,6 +288,7 @@ class Stats:
     wallq_f: np.ndarray = None    # [2] float sum of -dq (conservation checks)
     unhist: np.ndarray = None     # [N_UNBIN]
     flags: int = 0
+    pp_pairs: int = 0             # colliding particle pairs (4-way coupling)
 
     def __post_init__(self):
         z = lambda n: np.zeros(n, dtype=np.int64)
@@ -304,6 +305,64 @@ def _sum_by(index, values, n):
     out = np.zeros(n, dtype=np.int64)
     np.add.at(out, index, values)
     return out
+
+
+# ----------------------------------------------------------------------------
+# 4-way coupling: particle-particle collisions and charge exchange
+# ----------------------------------------------------------------------------
+def pp_transfer_exponent(di, dj, speed, k_pp):
+    """Delta t_12 / T_12 of the particle-particle condenser model (Sec. 2.3.1)
+    with the Hertzian contact area and duration substituted: the material
+    constants (rho_p, k_e, mu_p, E_p, phi_p, eps) collapse into one
+    coefficient k_pp, leaving
+    k_pp (d_i d_j)^2 (d_i + d_j)^(-3/5) (d_i^3 + d_j^3)^(-4/5) |u_12|^(3/5)."""
+    return k_pp * ((di * dj) ** 2 * (di + dj) ** -0.6 * (di ** 3 + dj ** 3) ** -0.8) * speed ** 0.6
+
+
+def collide_pp(cid, x, y, z, vx, vy, vz, q, d, k_pp):
+    """Binary hard-sphere collisions between particles sharing a grid cell,
+    resolved simultaneously on the state at the start of the step (Sec. 2.2):
+    a pair collides when it overlaps, |s_i - s_j| < (d_i + d_j)/2, and
+    approaches, (u_i - u_j).(s_i - s_j) < 0.  Fully elastic, masses ~ d^3:
+    u_i += -2 m_j / (m_i + m_j) ((u_i - u_j).n) n, n = (s_i - s_j)/|s_i - s_j|.
+    Charge exchange (condenser model, Sec. 2.3.1), capacities ~ d:
+    dq_i = -dq_j = (d_i q_j - d_j q_i)/(d_i + d_j) (1 - exp(-Delta t_12/T_12)).
+    Every particle's increments are summed over its partners in ascending id.
+    Returns (dvx, dvy, dvz, dq, number of colliding pairs)."""
+    n = x.shape[0]
+    dv = np.zeros((3, n))
+    dq = np.zeros(n)
+    pairs = 0
+    order = np.lexsort((np.arange(n), cid))
+    cs = cid[order]
+    bounds = np.flatnonzero(np.diff(cs)) + 1
+    for grp in np.split(order, bounds):
+        m = len(grp)
+        for a in range(m):
+            for b in range(a + 1, m):
+                i, j = grp[a], grp[b]
+                rx, ry, rz = x[i] - x[j], y[i] - y[j], z[i] - z[j]
+                r2 = (rx * rx + ry * ry) + rz * rz
+                rc = 0.5 * (d[i] + d[j])
+                if not (0.0 < r2 < rc * rc):
+                    continue
+                wx, wy, wz = vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j]
+                if (wx * rx + wy * ry) + wz * rz >= 0.0:
+                    continue
+                pairs += 1
+                ri = 1.0 / math.sqrt(r2)
+                nx_, ny_, nz_ = rx * ri, ry * ri, rz * ri
+                un = (wx * nx_ + wy * ny_) + wz * nz_
+                mi, mj = (d[i] * d[i]) * d[i], (d[j] * d[j]) * d[j]
+                ci, cj = 2.0 * mj / (mi + mj) * un, 2.0 * mi / (mi + mj) * un
+                dv[:, i] -= (ci * nx_, ci * ny_, ci * nz_)
+                dv[:, j] += (cj * nx_, cj * ny_, cj * nz_)
+                speed = math.sqrt((wx * wx + wy * wy) + wz * wz)
+                fr = 1.0 - math.exp(-pp_transfer_exponent(d[i], d[j], speed, k_pp))
+                t = (d[i] * q[j] - d[j] * q[i]) / (d[i] + d[j]) * fr
+                dq[i] += t
+                dq[j] -= t
+    return dv[0], dv[1], dv[2], dq, pairs
 
 
 # ----------------------------------------------------------------------------
@@ -345,6 +404,10 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
     Order within the step (the paper gives none): cells of x^n -> deposit
     q^n -> Poisson -> E -> per particle (carrier u, E, same-cell Coulomb at
     x^n, q^n) -> v^{n+1}, x^{n+1} -> wall impact (reflect, charge) -> wrap.
+    With prm["pp"] (4-way coupling), same-cell particle-particle collisions
+    (collide_pp, coefficient prm["k_pp"]) first change v^n and q^n; the drag
+    update and the wall charging start from the changed values, the electric
+    forces use the deposited q^n.
     """
     x, y, z, vx, vy, vz, q, d = (s[k] for k in KEYS)
     n = x.shape[0]
@@ -371,6 +434,15 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
         stats.qnow_y = _sum_by(j, fq, g.ny)
         if np.any(np.abs(q) * 2.0 ** FIX_DEP >= 2.0 ** 62):
             stats.flags |= F_OVERFLOW
+
+    # 4-way coupling: collisions act on the velocities and charges at the start
+    # of the step; the step's electric forces use the deposited charges q^n
+    npp = 0
+    qc = q
+    if prm.get("pp", 0):
+        dvxc, dvyc, dvzc, dqc, npp = collide_pp(cid, x, y, z, vx, vy, vz, q, d, prm["k_pp"])
+        vx, vy, vz = vx + dvxc, vy + dvyc, vz + dvzc
+        qc = q + dqc
 
     phi = poisson(g, Q)
     Ex, Ey, Ez = efield(g, phi)
@@ -414,8 +486,8 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
     yr = np.where(lo, r + e * (r - y1), np.where(hi, top - e * (y1 - top), y1))
     vyr = np.where(hit, -e * v1y, v1y)
     fchg = (kc * math.pow(1.0 + e, 0.4)) * np.power(np.where(hit, un, 0.0), 0.8)
-    dq = np.where(hit, -fchg * (dU + q), 0.0)
-    q1 = np.where(hit, q + dq, q)
+    dq = np.where(hit, -fchg * (dU + qc), 0.0)
+    q1 = np.where(hit, qc + dq, qc)
 
     # periodic wrap
     if replay is not None:
@@ -428,6 +500,7 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
 
     if stats is not None:
         stats.steps += 1
+        stats.pp_pairs += npp
         for w in (0, 1):
             m = wall == w
             stats.impacts[w] += int(m.sum())

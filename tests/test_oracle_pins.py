@@ -447,3 +447,136 @@ def test_two_way_source_single_particle_stokes():
     fs = want["fs"].copy()
     fs[0, c] = 0.0
     assert np.all(fs == 0.0)
+
+
+# --------------------------------------------------------------------------
+# 4-way coupling (Sec. 2.2, 2.3.1): particle-particle collisions
+# --------------------------------------------------------------------------
+def _pair(p1, p2, v1, v2, q=(0.0, 0.0), d=(1.0, 1.0)):
+    arr = lambda a, b: np.array([a, b], dtype=np.float64)
+    cid = np.array([0, 0])
+    return (cid, arr(p1[0], p2[0]), arr(p1[1], p2[1]), arr(p1[2], p2[2]), arr(v1[0], v2[0]), arr(v1[1], v2[1]),
+            arr(v1[2], v2[2]), arr(*q), arr(*d))
+
+
+def test_pp_head_on_equal_spheres_swap_velocities():
+    args = _pair((0.0, 0.0, 0.0), (0.9, 0.0, 0.0), (1.0, 0.2, 0.0), (-0.5, 0.2, 0.1), q=(0.3, -0.1))
+    dvx, dvy, dvz, dq, npairs = O.collide_pp(*args, k_pp=0.5)
+    assert npairs == 1
+    np.testing.assert_allclose(args[4] + dvx, [-0.5, 1.0], rtol=0, atol=1e-15)  # normal components swap
+    assert np.all(dvy == 0.0) and np.all(dvz == 0.0)                            # tangential unchanged
+    # equal capacities: the charges relax toward their mean by 1 - exp(-x)
+    x = 0.5 * 1.0 ** 4 * 2.0 ** -0.6 * 2.0 ** -0.8 * math.sqrt(1.5 ** 2 + 0.0 + 0.1 ** 2) ** 0.6
+    expect = 0.5 * (-0.1 - 0.3) * (1.0 - math.exp(-x))
+    np.testing.assert_allclose(dq, [expect, -expect], rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_pp_conserves_momentum_energy_charge(seed):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.3, 2.0, 2)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    r = 0.5 * (d[0] + d[1]) * rng.uniform(0.3, 0.99)
+    v1, v2 = rng.normal(size=3), rng.normal(size=3)
+    if np.dot(v1 - v2, u) >= 0:  # make the pair approach along u (s1 - s2 = r u)
+        v1, v2 = v2, v1
+    args = _pair(tuple(r * u), (0.0, 0.0, 0.0), tuple(v1), tuple(v2), q=tuple(rng.normal(size=2)), d=tuple(d))
+    dvx, dvy, dvz, dq, npairs = O.collide_pp(*args, k_pp=rng.uniform(0.1, 3.0))
+    assert npairs == 1
+    m = d ** 3
+    vb = np.stack([args[4], args[5], args[6]])
+    va = vb + np.stack([dvx, dvy, dvz])
+    np.testing.assert_allclose(va @ m, vb @ m, atol=1e-14 * np.abs(vb).max() * m.sum())
+    ke = lambda v: float(np.sum(m * np.sum(v * v, axis=0)))
+    assert ke(va) == pytest.approx(ke(vb), rel=1e-13)
+    # the pair separates afterwards, and charge is conserved
+    assert np.dot(va[:, 0] - va[:, 1], u) > 0
+    assert abs(dq.sum()) <= 1e-16 * max(1.0, np.abs(args[7]).max())
+    # larger capacity (diameter) ends with the larger share: q/d moves toward equality
+    qa = args[7] + dq
+    gap0, gap1 = args[7][0] / d[0] - args[7][1] / d[1], qa[0] / d[0] - qa[1] / d[1]
+    assert abs(gap1) < abs(gap0) and gap1 * gap0 >= 0
+
+
+def test_pp_no_collision_when_apart_or_receding():
+    apart = _pair((0.0, 0.0, 0.0), (1.01, 0.0, 0.0), (1.0, 0, 0), (-1.0, 0, 0))
+    recede = _pair((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (-1.0, 0, 0), (1.0, 0, 0))
+    for a in (apart, recede):
+        dvx, dvy, dvz, dq, npairs = O.collide_pp(*a, k_pp=1.0)
+        assert npairs == 0 and not np.any(dvx) and not np.any(dq)
+    other_cell = list(_pair((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (1.0, 0, 0), (-1.0, 0, 0)))
+    other_cell[0] = np.array([0, 1])
+    assert O.collide_pp(*other_cell, k_pp=1.0)[4] == 0
+
+
+def test_pp_repeated_exchange_closed_form():
+    # equal diameters: each collision multiplies the charge difference by exp(-x_m)
+    q = np.array([0.7, -0.2])
+    prod = 1.0
+    for m, speed in enumerate((0.5, 1.3, 2.0, 0.1)):
+        args = list(_pair((0.0, 0.0, 0.0), (0.8, 0.0, 0.0), (speed, 0, 0), (0.0, 0, 0), q=tuple(q)))
+        *_, dq, npairs = O.collide_pp(*args, k_pp=0.8)
+        assert npairs == 1
+        q = q + dq
+        prod *= math.exp(-0.8 * 2.0 ** -0.6 * 2.0 ** -0.8 * speed ** 0.6)
+    assert q[0] - q[1] == pytest.approx(0.9 * prod, rel=1e-13)
+    assert q.sum() == pytest.approx(0.5, abs=1e-15)
+
+
+def test_pp_pairs_brute_force_count():
+    # the grouped pair search finds exactly the overlapping, approaching
+    # same-cell pairs of an all-pairs scan
+    rng = np.random.default_rng(5)
+    n = 300
+    cid = rng.integers(0, 20, n)
+    x, y, z = rng.uniform(0, 3, (3, n))
+    v = rng.normal(size=(3, n))
+    q = rng.normal(size=n)
+    d = rng.uniform(0.2, 1.2, n)
+    *_, npairs = O.collide_pp(cid, x, y, z, v[0], v[1], v[2], q, d, k_pp=1.0)
+    brute = 0
+    for i in range(n):
+        for j in range(n):
+            if i < j and cid[i] == cid[j]:
+                r = np.array([x[i] - x[j], y[i] - y[j], z[i] - z[j]])
+                if 0 < r @ r < (0.5 * (d[i] + d[j])) ** 2 and (v[:, i] - v[:, j]) @ r < 0:
+                    brute += 1
+    assert npairs == brute > 10
+
+
+def test_pp_in_step_conserves_charge():
+    # a tiny dense channel where particles collide every step: particle-particle
+    # exchange moves charge between particles only
+    ens = W.make_ensemble(W.CONFIGS[1].replace(re_tau=2.0, nx=4, ny=4, nz=4, n_particles=800, precharge=0.3,
+                                               v_jitter=1.0, d_choices=(0.5, 1.0), density_ratio=50.0))
+    g = O.Geo.from_mesh(ens.mesh)
+    s = O.state_of(ens)
+    prm = dict(ens.params, pp=1, k_pp=2.0, k_c=0.0)
+    st = O.Stats(g.ny)
+    q0 = s["q"].sum()
+    for _ in range(5):
+        s = O.step(g, ens.U, s, prm, st)
+    assert st.pp_pairs > 20
+    assert s["q"].sum() == pytest.approx(q0, abs=1e-12)
+
+
+def test_pp_exponent_is_the_hertz_condenser_chain():
+    # Delta t_12 / T_12 from the paper's chain (Hertz contact radius alpha_12,
+    # contact area A_12, contact time, relaxation time T_12 with capacities
+    # 4 pi eps d / 2) for arbitrary material constants: one coefficient k_pp
+    # fitted at one (d_i, d_j, |u_12|) reproduces every other case
+    rho_p, k_e, mu_p, e_p, phi_p, eps = 1.3e3, 0.9, 0.3, 2.1e4, 7.0, 0.8
+
+    def chain(di, dj, u):
+        a = (di * dj / 2.0) * ((5.0 / 8.0) * math.pi * rho_p * (1 + k_e) * u * u * math.sqrt(di + dj)
+                               / (di ** 3 + dj ** 3) * (1 - mu_p) / e_p) ** 0.4
+        area = math.pi * di * dj * a / (2.0 * (di + dj))
+        dt12 = 2.94 * a / u
+        ci, cj = 4 * math.pi * eps * di / 2, 4 * math.pi * eps * dj / 2
+        t12 = ci * cj / (ci + cj) * (di + dj) / (2 * area) * phi_p
+        return dt12 / t12
+
+    k_pp = chain(0.5, 1.0, 1.0) / O.pp_transfer_exponent(0.5, 1.0, 1.0, 1.0)
+    for di, dj, u in ((0.25, 0.25, 0.3), (2.0, 0.5, 4.0), (1.0, 1.0, 0.01), (0.7, 1.9, 12.0)):
+        assert O.pp_transfer_exponent(di, dj, u, k_pp) == pytest.approx(chain(di, dj, u), rel=1e-12)
