@@ -160,6 +160,25 @@ def source_cost(torch, W, R, steps, log):
             "extra_GBs": extra_bytes / (d_us * 1e-6) / 1e9 if d_us > 0 else None}
 
 
+def four_way_cost(torch, W, R, steps, log):
+    """Time of the headline step with 4-way coupling (same-cell particle-particle
+    collisions, k_pp = 1) against the plain step, graph replays, and the pairs
+    that collided."""
+    ms, pairs = {}, 0
+    for on in (False, True):
+        ens = W.make_workload(2, pp=int(on), k_pp=1.0)[0]
+        sim = R.TriboSim([ens], graphs=True)
+        sim.step(3)
+        ms[on] = timed_steps(torch, sim, steps) / steps
+        if on:
+            pairs = int(sim.stats(0)["pp_pairs"])
+        sim.close()
+        del sim
+    log(f"4-way coupling: {ms[False] * 1e3:.1f} -> {ms[True] * 1e3:.1f} us/step, {pairs} pairs")
+    return {"workload": WORKLOAD_NAME[2] + ", k_pp=1", "us_per_step_without": ms[False] * 1e3,
+            "us_per_step_with": ms[True] * 1e3, "colliding_pairs": pairs, "steps": steps + 3}
+
+
 def adjoint_ratio(torch, W, R, autotune, seg, log):
     ens = W.make_workload(5, v_jitter=3.0, precharge=0.02)[0]
     autotune.ensure_tuned(autotune.meshes_of([ens]))
@@ -202,6 +221,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-source", action="store_true", help="skip the 2-way coupling source timing")
+    ap.add_argument("--no-fourway", action="store_true", help="skip the 4-way coupling timing")
     ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (reference kernel for HBM byte counters)")
@@ -301,6 +321,8 @@ def main():
         out["adjoint"] = adjoint_ratio(torch, W, R, autotune, 50, log)
     if not args.no_source:
         out["two_way_source"] = source_cost(torch, W, R, 50, log)
+    if not args.no_fourway:
+        out["four_way"] = four_way_cost(torch, W, R, 50, log)
     if not args.no_cpu:
         v, secs = cpu_baseline(ens, args.cpu_steps)
         out["cpu_baseline"] = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

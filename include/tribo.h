@@ -102,6 +102,18 @@ typedef struct tf_handle tf_handle;
  *               (i, j, k) at (i dx, y_faces[j], k dz); borrowed (read by
  *               every step) until tf_set_carrier replaces it
  *   n_particles 1..2^30
+ *   pp, k_pp    4-way coupling (pp = 1; 0 = off): binary hard-sphere
+ *               collisions between particles sharing a grid cell (Sec. 2.2),
+ *               resolved together on the state at the start of each step
+ *               when a pair overlaps and approaches; fully elastic, masses
+ *               ~ d^3; condenser charge exchange (Sec. 2.3.1)
+ *               dq_i = -dq_j = (d_i q_j - d_j q_i)/(d_i + d_j) (1 - exp(-x)),
+ *               x = k_pp (d_i d_j)^2 (d_i + d_j)^(-3/5) (d_i^3 + d_j^3)^(-4/5)
+ *               |u_i - u_j|^(3/5) (the Hertz contact area and time with the
+ *               material constants folded into k_pp >= 0).  The drag update
+ *               and wall charging start from the changed velocity and charge;
+ *               the step's electric forces use the deposited charges.  Not
+ *               differentiated: TF_STEP_RECORD is refused while pp is on.
  */
 typedef struct {
   int32_t nx, ny, nz, n_particles;
@@ -111,6 +123,8 @@ typedef struct {
   double g[3];
   double un_bin;
   const double* u_nodes;
+  double k_pp;
+  int32_t pp, reserved;
 } tf_ensemble;
 
 /* Particle arrays (device pointers, n_particles doubles each, indexed by
@@ -130,6 +144,7 @@ typedef struct {
   int64_t* qcum_y;            /* optional host [ny]: time-summed sum rne(q 2^32) per y cell */
   int64_t* qnow_y;            /* optional host [ny]: sum rne(q 2^48) per y cell at the latest deposit */
   double q_sum;               /* total particle charge at the latest deposit */
+  int64_t pp_pairs;           /* colliding particle pairs (4-way coupling) since tf_init */
 } tf_stats_out;
 
 /* Bytes of device workspace for these ensembles.  traj_steps > 0 reserves

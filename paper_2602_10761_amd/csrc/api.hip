@@ -95,6 +95,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     if (!(E.e > 0 && E.e <= 1)) return fail(TF_EINVAL, pre + "restitution e must be in (0, 1]");
     if (!std::isfinite(E.k_c) || !std::isfinite(E.delta_u) || !std::isfinite(E.c_el))
       return fail(TF_EINVAL, pre + "k_c, delta_u, c_el must be finite");
+    if ((E.pp != 0 && E.pp != 1) || !(E.k_pp >= 0) || !std::isfinite(E.k_pp))
+      return fail(TF_EINVAL, pre + "pp must be 0 or 1 and k_pp finite and >= 0");
     if (!E.y_faces) return fail(TF_EINVAL, pre + "y_faces is NULL");
     if (!E.u_nodes) return fail(TF_EINVAL, pre + "u_nodes is NULL");
     if (E.y_faces[0] != 0.0) return fail(TF_EINVAL, pre + "y_faces[0] must be 0");
@@ -516,6 +518,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.inv_2dz = 1.0 / (2.0 * E.dz);
     E.inv_nx = 1.0 / T.nx;
     E.inv_nz = 1.0 / T.nz;
+    E.pp = T.pp;
+    E.kpp = T.k_pp;
     E.c18 = 18.0 / T.density_ratio;
     E.fe = T.k_c * std::pow(1.0 + T.e, 0.4);
     E.pe = std::pow(1.0 + T.e, 0.4);
@@ -639,6 +643,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.pl_blk = h->S.pl_blk.data();
   h->G.d_pl_blk = h->d_pl;
   h->G.plane_any = S.plane_any ? 1 : 0;
+  h->G.pp_any = 0;
+  for (int e = 0; e < n_ens; ++e) h->G.pp_any |= ens[e].pp;
   h->G.split_any = S.split_any ? 1 : 0;
   h->G.plane_max = S.plane_max;
   h->G.eh = h->eh.data();
@@ -657,6 +663,9 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
     return TF_OK;
   }
   const bool rec = (flags & TF_STEP_RECORD) != 0;
+  if (rec)
+    for (int e = 0; e < h->n_ens; ++e)
+      if (h->eh[e].pp) return fail(TF_ESTATE, "recording (adjoint) is not available with particle-particle collisions");
   if (rec) {
     if (h->traj_cap == 0) return fail(TF_ESTATE, "no trajectory capacity (traj_steps = 0 at tf_init)");
     if (h->traj_len + n_steps > h->traj_cap) return fail(TF_ESIZE, "recorded trajectory would exceed traj_steps");
@@ -735,6 +744,7 @@ int tf_stats(tf_handle* h, int32_t e, tf_stats_out* out) {
     out->wall_q[w] = st[ST_WQ + w];
   }
   for (int b = 0; b < kNbin; ++b) out->un_hist[b] = st[ST_HIST + b];
+  out->pp_pairs = st[ST_PP];
   __int128 tot = 0;
   for (int j = 0; j < E.ny; ++j) {
     long long qj = 0, cj = 0, q32 = 0;

@@ -1389,13 +1389,14 @@ __device__ __forceinline__ void pair_count(int* __restrict__ pair_cnt, int key) 
   atomicAdd(&pair_cnt[key], __popcll(act & upto & ~((1ull << lane) - 1ull)));
 }
 
+template <bool PP>
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
                                          int p, int c, signed char* __restrict__ wall_rec) {
   Fwd F;
-  eval_particle<true>(C, E, in, s, p, c, F);
+  eval_particle<true, PP>(C, E, in, s, p, c, F);
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int j = F.j;
-  const double q = F.q, d = F.d;
+  const double q = F.qc, d = F.d;  // charge after any particle-particle exchange
   const double v1x = F.v1[0], v1y = F.v1[1], v1z = F.v1[2];
   double x1 = F.x1, z1 = F.z1;
   const double y1 = F.y1;
@@ -1416,6 +1417,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
     yr = top - E.e * (y1 - top);
   }
   long long* st = C.stats + E.st_off;
+  if (F.npp) atomicAdd((unsigned long long*)&st[ST_PP], (unsigned long long)F.npp);
   if (wall_rec) wall_rec[s] = (signed char)wall;
   if (wall >= 0) {
     vyr = -E.e * v1y;
@@ -1484,6 +1486,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
 
 // four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat
 // the few spilled registers
+template <bool PP>
 __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   // the new row ranges become the stored order's (read by the next sort)
@@ -1497,7 +1500,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
     if (perm_rec) perm_rec[s] = p;
     const int c = C.skey[s];
     if (one) {
-      push_one(C, Eone, in, out, s, p, c, wall_rec);
+      push_one<PP>(C, Eone, in, out, s, p, c, wall_rec);
     } else {
       const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
       // waterfall over the ensembles present in this wave (usually one)
@@ -1505,7 +1508,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
       while (!done) {
         const int e = __builtin_amdgcn_readfirstlane(e_lane);
         if (e_lane == e) {
-          push_one(C, C.ens[e], in, out, s, p, c, wall_rec);
+          push_one<PP>(C, C.ens[e], in, out, s, p, c, wall_rec);
           done = true;
         }
       }
@@ -1690,7 +1693,11 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
   // at least one block: the step counters are kept by block 0
   const int nb = std::max(1, (int)((C.n_tot + kBlock - 1) / kBlock));
   const int one = (C.n_ens == 1) ? 1 : 0;
-  k_push<<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  // the collision code only when an ensemble has 4-way coupling on
+  if (G.pp_any)
+    k_push<true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  else
+    k_push<false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
   return hipGetLastError();
 }
 

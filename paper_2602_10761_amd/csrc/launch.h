@@ -26,6 +26,7 @@ struct LaunchGeo {
   int ny_max;
   int tri_rows;    // rows per lane of the tridiagonal scans (largest over the ensembles)
   int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
+  int pp_any;      // some ensemble has 4-way coupling on
   int plane_any, split_any;  // some ensembles with / without fused inverse transforms
   int plane_max;   // largest nz (nx/2 + 1) over the fused ensembles
   const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block

@@ -29,12 +29,15 @@ struct Fwd {
   double u[3], Ep[3], S[3];
   double ke, a[3], du[3], re, phid, sdr, iden, v1[3];
   double x1, y1, z1;  // after the update, before rebound and wrap
+  double qc;          // charge after particle-particle exchange (= q without 4-way coupling)
+  int npp;            // colliding pairs counted by this particle (partner of larger id)
 };
 
 // SORTED: positions and charges of slot s and of its cell mates come from the
 // slot-ordered copies C.sx, C.sy, C.sz, C.sq written by the sort (coalesced,
 // no dependent gather); otherwise they are gathered through C.perm from `in`.
-template <bool SORTED>
+// PP: compiled with the 4-way coupling (particle-particle collisions)
+template <bool SORTED, bool PP = false>
 __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
                                               Fwd& F) {
   const int nx = E.nx, ny = E.ny, nz = E.nz;
@@ -120,32 +123,65 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
       sz += w * rz;
     }
   };
+  // 4-way coupling: binary hard-sphere collisions with the cell's particles on
+  // the state at the start of the step (increments summed in ascending id)
+  double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
+  int npp = 0;
+  auto collide = [&](int t, double ox, double oy, double oz, double oq) {
+    const double rx = x - ox, ry = y - oy, rz = z - oz;
+    const double r2 = (rx * rx + ry * ry) + rz * rz;
+    const int pj = C.perm[t];
+    const double od = in.d[pj];
+    const double rc = 0.5 * (d + od);
+    if (!(r2 > 0.0 && r2 < rc * rc)) return;
+    const double wx = vx - in.vx[pj], wy = vy - in.vy[pj], wz = vz - in.vz[pj];
+    if ((wx * rx + wy * ry) + wz * rz >= 0.0) return;
+    if (t > s) ++npp;  // each pair counted once
+    const double ri = 1.0 / sqrt(r2);
+    const double nx_ = rx * ri, ny_ = ry * ri, nz_ = rz * ri;
+    const double un = (wx * nx_ + wy * ny_) + wz * nz_;
+    const double mi = (d * d) * d, mj = (od * od) * od;
+    const double ci = 2.0 * mj / (mi + mj) * un;
+    cvx -= ci * nx_;
+    cvy -= ci * ny_;
+    cvz -= ci * nz_;
+    const double speed = sqrt((wx * wx + wy * wy) + wz * wz);
+    const double xe =
+        E.kpp * (pow(d * od, 2.0) * pow(d + od, -0.6) * pow(pow(d, 3.0) + pow(od, 3.0), -0.8)) * pow(speed, 0.6);
+    cq += (d * oq - od * q) / (d + od) * (1.0 - exp(-xe));
+  };
   {
     const int a = C.start[c], b = C.start[c + 1];
     for (int t = a; t < b; ++t) {
       if (t == s) continue;
       if constexpr (SORTED) {
-        coulomb(C.sx[t], C.sy[t], C.sz[t], C.sq[t]);
+        const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t], oq = C.sq[t];
+        coulomb(ox, oy, oz, oq);
+        if constexpr (PP) {
+          if (E.pp) collide(t, ox, oy, oz, oq);
+        }
       } else {
         const int pj = C.perm[t];
         coulomb(in.x[pj], in.y[pj], in.z[pj], in.q[pj]);
       }
     }
   }
+  const bool pp = PP && E.pp;
+  const double vxs = pp ? vx + cvx : vx, vys = pp ? vy + cvy : vy, vzs = pp ? vz + cvz : vz;
   // forces and semi-implicit Euler
   const double d2 = d * d;
   const double ke = (E.cel * q) / (d2 * d);
   const double ax = E.gp0 + ke * (Ex + sx * kInv4Pi);
   const double ay = E.gp1 + ke * (Ey + sy * kInv4Pi);
   const double az = E.gp2 + ke * (Ez + sz * kInv4Pi);
-  const double dux = vx - uc[0], duy = vy - uc[1], duz = vz - uc[2];
+  const double dux = vxs - uc[0], duy = vys - uc[1], duz = vzs - uc[2];
   const double re = sqrt((dux * dux + duy * duy) + duz * duz) * d;
   const double phid = (re <= 1000.0) ? 1.0 + cbrt(re * re) * (1.0 / 6.0) : 0.424 * re * (1.0 / 24.0);
   const double sdr = phid * (E.c18 / d2);  // phi_D / tau_p
   const double iden = 1.0 / (1.0 + E.dt * sdr);
-  const double v1x = (vx + E.dt * (uc[0] * sdr + ax)) * iden;
-  const double v1y = (vy + E.dt * (uc[1] * sdr + ay)) * iden;
-  const double v1z = (vz + E.dt * (uc[2] * sdr + az)) * iden;
+  const double v1x = (vxs + E.dt * (uc[0] * sdr + ax)) * iden;
+  const double v1y = (vys + E.dt * (uc[1] * sdr + ay)) * iden;
+  const double v1z = (vzs + E.dt * (uc[2] * sdr + az)) * iden;
   const double x1 = x + E.dt * v1x;
   const double y1 = y + E.dt * v1y;
   const double z1 = z + E.dt * v1z;
@@ -161,6 +197,8 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   F.re = re; F.phid = phid; F.sdr = sdr; F.iden = iden;
   F.v1[0] = v1x; F.v1[1] = v1y; F.v1[2] = v1z;
   F.x1 = x1; F.y1 = y1; F.z1 = z1;
+  F.qc = pp ? q + cq : q;
+  F.npp = npp;
 }
 
 }  // namespace tf

@@ -44,6 +44,8 @@ struct Ens {
   double inv_nx, inv_nz;                    // 1/nx, 1/nz (index decomposition)
   double c18;                               // 18 / rr  (1/tau_p = c18 / d^2)
   double fe;                                // k_c (1 + e)^(2/5)
+  double kpp;                               // particle-particle charge-exchange coefficient
+  int pp;                                   // 4-way coupling on
   double pe;                                // (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
   FftPlan fx, fz;
@@ -52,7 +54,7 @@ struct Ens {
 // statistics block (int64) of one ensemble; the per-height sums live per (j,k)
 // row in Ctx::rowacc (each row owned by one deposit block: no atomics) and are
 // summed over k when read
-enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_END = 6 + kNbin };
+enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_PP = 6 + kNbin, ST_END = 7 + kNbin };
 inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };

@@ -36,7 +36,7 @@ class TfEnsemble(Structure):
                 ("lx", c_double), ("lz", c_double), ("y_faces", POINTER(c_double)),
                 ("dt", c_double), ("density_ratio", c_double), ("k_c", c_double), ("delta_u", c_double),
                 ("e", c_double), ("c_el", c_double), ("g", c_double * 3), ("un_bin", c_double),
-                ("u_nodes", c_void_p)]
+                ("u_nodes", c_void_p), ("k_pp", c_double), ("pp", c_int32), ("reserved", c_int32)]
 
 
 class TfParticles(Structure):
@@ -50,7 +50,8 @@ class TfTuning(Structure):
 class TfStatsOut(Structure):
     _fields_ = [("steps", c_int64), ("flags", c_int32), ("ny", c_int32), ("impacts", c_int64 * 2),
                 ("wall_q", c_int64 * 2), ("un_hist", c_int64 * TF_NBIN), ("crel_y", POINTER(c_int64)),
-                ("qcum_y", POINTER(c_int64)), ("qnow_y", POINTER(c_int64)), ("q_sum", c_double)]
+                ("qcum_y", POINTER(c_int64)), ("qnow_y", POINTER(c_int64)), ("q_sum", c_double),
+                ("pp_pairs", c_int64)]
 
 
 _LIB = None
@@ -152,6 +153,7 @@ class TriboSim:
             for i in range(3):
                 c.g[i] = p["g"][i]
             c.un_bin = p["un_bin"]
+            c.pp, c.k_pp = int(p.get("pp", 0)), float(p.get("k_pp", 0.0))
             c.u_nodes = self.U[e].data_ptr()
             arrs = {k: t(getattr(E, k)) for k in KEYS}
             init_t.append(arrs)
@@ -194,7 +196,8 @@ class TriboSim:
         o.qnow_y = qnow.ctypes.data_as(POINTER(c_int64))
         _check(self.L.tf_stats(self.h, e, ctypes.byref(o)))
         return dict(steps=o.steps, flags=o.flags, impacts=np.array(o.impacts[:]), wallq=np.array(o.wall_q[:]),
-                    unhist=np.array(o.un_hist[:]), crel_y=crel, qcum_y=qcum, qnow_y=qnow, q_sum=o.q_sum)
+                    unhist=np.array(o.un_hist[:]), crel_y=crel, qcum_y=qcum, qnow_y=qnow, q_sum=o.q_sum,
+                    pp_pairs=o.pp_pairs)
 
     def state(self, e: int = 0) -> Dict[str, "object"]:
         """Current particle state of ensemble e (device tensors, id order)."""

@@ -264,6 +264,8 @@ class EnsembleSpec:
     c_el: Optional[float] = None      # None: derive from re_tau
     g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     un_bin: float = 0.05
+    pp: int = 0                      # 4-way coupling (particle-particle collisions) on
+    k_pp: float = 0.0                # particle-particle charge-exchange coefficient
     steps: int = 1000
     precharge: float = 0.0           # q0 ~ U[-precharge, precharge]
     v_jitter: float = 0.0            # v0 += v_jitter * U[-1, 1]^3 (tests that need early impacts)
@@ -324,7 +326,8 @@ def make_ensemble(spec: EnsembleSpec, config_index: int = 0, seed: int = 0, sub:
         q = np.zeros(n)
     c_el = spec.c_el if spec.c_el is not None else electric_coupling(spec.re_tau)
     params = dict(dt=spec.dt, density_ratio=spec.density_ratio, k_c=spec.k_c,
-                  delta_u=spec.delta_u, e=spec.e, c_el=c_el, g=tuple(spec.g), un_bin=spec.un_bin)
+                  delta_u=spec.delta_u, e=spec.e, c_el=c_el, g=tuple(spec.g), un_bin=spec.un_bin,
+                  pp=spec.pp, k_pp=spec.k_pp)
     return Ensemble(spec, mesh, U, x, y, z, vx, vy, vz, q, d, params)
 
 

@@ -245,7 +245,10 @@ def test_batched_equals_plain():
              W.CONFIGS[1].replace(nx=8, ny=8, nz=8, n_particles=0),
              W.CONFIGS[1].replace(re_tau=550.0, nx=40, ny=16, nz=12, n_particles=1, v_jitter=1.0),
              # plane too large for the fused inverse transforms (nz (nx/2 + 1) > 10240)
-             W.CONFIGS[1].replace(nx=256, ny=6, nz=96, n_particles=3000, v_jitter=2.0)]
+             W.CONFIGS[1].replace(nx=256, ny=6, nz=96, n_particles=3000, v_jitter=2.0),
+             # 4-way coupling on for this one only (the others run the collision-enabled push)
+             W.CONFIGS[1].replace(re_tau=2.0, nx=4, ny=4, nz=4, n_particles=600, precharge=0.3, v_jitter=1.0,
+                                  d_choices=(0.5, 1.0), density_ratio=50.0, pp=1, k_pp=2.0)]
     ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
     sim = sim_of(ens, graphs=True, source=True)
     sim.step(9)
@@ -297,3 +300,42 @@ def test_conservation_and_flags():
     assert abs(s["q"].sum() - q0 + wall) < 1e-9
     r = 0.5 * s["d"]
     assert np.all((s["y"] >= r) & (s["y"] <= ens.mesh.ly - r))
+
+
+# ---------------------------------------------------------------------------
+# 4-way coupling: particle-particle collisions and charge exchange
+# ---------------------------------------------------------------------------
+def pp_ensemble(n=800, seed=0, **kw):
+    spec = W.CONFIGS[1].replace(re_tau=2.0, nx=4, ny=4, nz=4, n_particles=n, precharge=0.3, v_jitter=1.0,
+                                d_choices=(0.5, 1.0), density_ratio=50.0, pp=1, k_pp=2.0, **kw)
+    return W.make_ensemble(spec, 1, seed)
+
+
+@pytest.mark.parametrize("steps", [1, 6])
+def test_pp_collisions_parity(steps):
+    say("pp collisions", steps)
+    ens = pp_ensemble(k_c=0.01)
+    sim = sim_of(ens)
+    sim.step(steps)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    sim.close()
+    ref, st = oracle_run(ens, steps)
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  pairs", gst["pp_pairs"], st.pp_pairs, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert st.pp_pairs > 10 * steps
+    assert gst["pp_pairs"] == st.pp_pairs
+    assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+    np.testing.assert_array_equal(gst["impacts"], st.impacts)
+    np.testing.assert_array_equal(gst["crel_y"], st.crel_y)
+    assert abs(gpu["q"].sum() - ref["q"].sum()) < 1e-12
+
+
+def test_pp_record_refused():
+    from paper_2602_10761_amd.runtime import TriboError
+    sim = sim_of(pp_ensemble(n=100), traj_steps=2)
+    with pytest.raises(TriboError):
+        sim.step(1, record=True)
+    sim.step(1)
+    assert sim.stats(0)["steps"] == 1
+    sim.close()
