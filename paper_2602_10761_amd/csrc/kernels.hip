@@ -1368,6 +1368,10 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
   const int j = y_cell(C.yf + E.y_off, E.ny, y);
   const int c = (int)(E.c_off + (long long)(j * E.nz + k) * E.nx + i);
   S.key[p] = c;
+  // diameter bound of the ensemble (the collision search's prefilter)
+  const double d = S.d[p];
+  if (d > 0.0)
+    atomicMax((unsigned long long*)&C.stats[E.st_off + ST_DMAX], (unsigned long long)__double_as_longlong(d));
 }
 
 // ---------------------------------------------------------------------------

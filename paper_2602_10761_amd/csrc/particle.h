@@ -36,6 +36,39 @@ struct Fwd {
 // SORTED: positions and charges of slot s and of its cell mates come from the
 // slot-ordered copies C.sx, C.sy, C.sz, C.sq written by the sort (coalesced,
 // no dependent gather); otherwise they are gathered through C.perm from `in`.
+// One binary collision of the particle (position difference r = s_self -
+// s_mate, |r|^2 = r2, diameter d, velocity v, charge q) with the mate at old
+// slot pj: hit when they overlap and approach; then the velocity and charge
+// increments of the particle (fully elastic, masses ~ d^3; condenser exchange
+// with the Hertz exponent).
+struct PPHit {
+  double dvx, dvy, dvz, dq;
+  int hit;
+};
+__device__ __forceinline__ PPHit pp_pair(int pj, const PState& in, double kpp, double rx, double ry, double rz,
+                                      double r2, double d, double vx, double vy, double vz, double q, double oq) {
+  PPHit h{0.0, 0.0, 0.0, 0.0, 0};
+  const double od = in.d[pj];
+  const double rc = 0.5 * (d + od);
+  if (!(r2 > 0.0 && r2 < rc * rc)) return h;
+  const double wx = vx - in.vx[pj], wy = vy - in.vy[pj], wz = vz - in.vz[pj];
+  if ((wx * rx + wy * ry) + wz * rz >= 0.0) return h;
+  h.hit = 1;
+  const double ri = 1.0 / sqrt(r2);
+  const double nx_ = rx * ri, ny_ = ry * ri, nz_ = rz * ri;
+  const double un = (wx * nx_ + wy * ny_) + wz * nz_;
+  const double mi = (d * d) * d, mj = (od * od) * od;
+  const double ci = 2.0 * mj / (mi + mj) * un;
+  h.dvx = -(ci * nx_);
+  h.dvy = -(ci * ny_);
+  h.dvz = -(ci * nz_);
+  const double speed = sqrt((wx * wx + wy * wy) + wz * wz);
+  const double xe =
+      kpp * (pow(d * od, 2.0) * pow(d + od, -0.6) * pow(pow(d, 3.0) + pow(od, 3.0), -0.8)) * pow(speed, 0.6);
+  h.dq = (d * oq - od * q) / (d + od) * (1.0 - exp(-xe));
+  return h;
+}
+
 // PP: compiled with the 4-way coupling (particle-particle collisions)
 template <bool SORTED, bool PP = false>
 __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
@@ -124,32 +157,17 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
     }
   };
   // 4-way coupling: binary hard-sphere collisions with the cell's particles on
-  // the state at the start of the step (increments summed in ascending id)
+  // the state at the start of the step (increments summed in ascending id);
+  // pairs farther apart than (d + d_max)/2 are skipped before any gather
   double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
   int npp = 0;
-  auto collide = [&](int t, double ox, double oy, double oz, double oq) {
-    const double rx = x - ox, ry = y - oy, rz = z - oz;
-    const double r2 = (rx * rx + ry * ry) + rz * rz;
-    const int pj = C.perm[t];
-    const double od = in.d[pj];
-    const double rc = 0.5 * (d + od);
-    if (!(r2 > 0.0 && r2 < rc * rc)) return;
-    const double wx = vx - in.vx[pj], wy = vy - in.vy[pj], wz = vz - in.vz[pj];
-    if ((wx * rx + wy * ry) + wz * rz >= 0.0) return;
-    if (t > s) ++npp;  // each pair counted once
-    const double ri = 1.0 / sqrt(r2);
-    const double nx_ = rx * ri, ny_ = ry * ri, nz_ = rz * ri;
-    const double un = (wx * nx_ + wy * ny_) + wz * nz_;
-    const double mi = (d * d) * d, mj = (od * od) * od;
-    const double ci = 2.0 * mj / (mi + mj) * un;
-    cvx -= ci * nx_;
-    cvy -= ci * ny_;
-    cvz -= ci * nz_;
-    const double speed = sqrt((wx * wx + wy * wy) + wz * wz);
-    const double xe =
-        E.kpp * (pow(d * od, 2.0) * pow(d + od, -0.6) * pow(pow(d, 3.0) + pow(od, 3.0), -0.8)) * pow(speed, 0.6);
-    cq += (d * oq - od * q) / (d + od) * (1.0 - exp(-xe));
-  };
+  double rcut2 = 0.0;
+  if constexpr (PP) {
+    if (E.pp) {
+      const double rc = 0.5 * (d + __longlong_as_double(C.stats[E.st_off + ST_DMAX]));
+      rcut2 = rc * rc;
+    }
+  }
   {
     const int a = C.start[c], b = C.start[c + 1];
     for (int t = a; t < b; ++t) {
@@ -158,7 +176,18 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
         const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t], oq = C.sq[t];
         coulomb(ox, oy, oz, oq);
         if constexpr (PP) {
-          if (E.pp) collide(t, ox, oy, oz, oq);
+          const double rx = x - ox, ry = y - oy, rz = z - oz;
+          const double r2 = (rx * rx + ry * ry) + rz * rz;
+          if (r2 < rcut2) {
+            const PPHit h = pp_pair(C.perm[t], in, E.kpp, rx, ry, rz, r2, d, vx, vy, vz, q, oq);
+            if (h.hit) {
+              if (t > s) ++npp;  // each pair counted once
+              cvx += h.dvx;
+              cvy += h.dvy;
+              cvz += h.dvz;
+              cq += h.dq;
+            }
+          }
         }
       } else {
         const int pj = C.perm[t];

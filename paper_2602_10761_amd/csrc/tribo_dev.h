@@ -54,7 +54,12 @@ struct Ens {
 // statistics block (int64) of one ensemble; the per-height sums live per (j,k)
 // row in Ctx::rowacc (each row owned by one deposit block: no atomics) and are
 // summed over k when read
-enum { ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_PP = 6 + kNbin, ST_END = 7 + kNbin };
+// ST_DMAX: bit pattern of an upper bound of the ensemble's diameters (set by
+// the binning of uploaded particles; positive doubles order like their bits)
+enum {
+  ST_STEPS = 0, ST_FLAGS = 1, ST_IMP = 2, ST_WQ = 4, ST_HIST = 6, ST_PP = 6 + kNbin, ST_DMAX = 7 + kNbin,
+  ST_END = 8 + kNbin
+};
 inline int stats_len(int) { return ST_END; }
 
 enum { FLAG_NONFINITE = 1, FLAG_OVERFLOW = 2, FLAG_OUTSIDE = 4 };
