@@ -70,6 +70,7 @@ struct Sizes {
   std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk;
   int plane_max = 0;
   bool plane_any = false, split_any = false;
+  bool pp_any = false;  // some ensemble has 4-way coupling on
   std::vector<int> e_plane;
   std::map<int, int> tw_off;
 };
@@ -97,6 +98,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       return fail(TF_EINVAL, pre + "k_c, delta_u, c_el must be finite");
     if ((E.pp != 0 && E.pp != 1) || !(E.k_pp >= 0) || !std::isfinite(E.k_pp))
       return fail(TF_EINVAL, pre + "pp must be 0 or 1 and k_pp finite and >= 0");
+    if (E.pp) S->pp_any = true;
     if (!E.y_faces) return fail(TF_EINVAL, pre + "y_faces is NULL");
     if (!E.u_nodes) return fail(TF_EINVAL, pre + "u_nodes is NULL");
     if (E.y_faces[0] != 0.0) return fail(TF_EINVAL, pre + "y_faces[0] must be 0");
@@ -283,6 +285,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.qdep = (flags & TF_INIT_KEEP_DEPOSIT) ? cv.take<long long>(S.c_tot) : nullptr;
   C.fslot = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.n_tot) : nullptr;
   C.fsrc = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.c_tot) : nullptr;
+  C.cinc = S.pp_any ? cv.take<double>(4 * S.n_tot) : nullptr;
   std::vector<TrajBuf> traj;
   if (traj_steps > 0) {
     for (int t = 0; t <= traj_steps; ++t) {
@@ -359,6 +362,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
         hipSuccess)
       return e;
   }
+  if (h->C.cinc && (e = launch_collide(h->C, in, h->stream)) != hipSuccess) return e;
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)
     return e;
@@ -643,8 +647,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.pl_blk = h->S.pl_blk.data();
   h->G.d_pl_blk = h->d_pl;
   h->G.plane_any = S.plane_any ? 1 : 0;
-  h->G.pp_any = 0;
-  for (int e = 0; e < n_ens; ++e) h->G.pp_any |= ens[e].pp;
+  h->G.pp_any = S.pp_any ? 1 : 0;
   h->G.split_any = S.split_any ? 1 : 0;
   h->G.plane_max = S.plane_max;
   h->G.eh = h->eh.data();

@@ -1421,7 +1421,6 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
     yr = top - E.e * (y1 - top);
   }
   long long* st = C.stats + E.st_off;
-  if (F.npp) atomicAdd((unsigned long long*)&st[ST_PP], (unsigned long long)F.npp);
   if (wall_rec) wall_rec[s] = (signed char)wall;
   if (wall >= 0) {
     vyr = -E.e * v1y;
@@ -1731,6 +1730,33 @@ hipError_t launch_source(const Ctx& C, hipStream_t st) {
   if (C.c_tot == 0) return hipSuccess;
   const int nb = (int)((C.c_tot + kBlock - 1) / kBlock);
   k_source<<<nb, kBlock, 0, st>>>(C);
+  return hipGetLastError();
+}
+
+// 4-way coupling: per slot, the velocity and charge increments of its
+// collisions (zero for ensembles without it), read by the push
+__global__ __launch_bounds__(kBlock) void k_collide(Ctx C, PState in) {
+  const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+  if (s >= C.n_tot) return;
+  const int c = C.skey[s];
+  const int e = find_off(C.c_off, C.n_ens + 1, c);
+  const Ens& E = C.ens[e];
+  double inc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (E.pp) {
+    const int npp = pp_collide(C, E, in, s, C.perm[s], c, inc);
+    if (npp) atomicAdd((unsigned long long*)&C.stats[E.st_off + ST_PP], (unsigned long long)npp);
+  }
+  const long long n = C.n_tot;
+  C.cinc[s] = inc[0];
+  C.cinc[n + s] = inc[1];
+  C.cinc[2 * n + s] = inc[2];
+  C.cinc[3 * n + s] = inc[3];
+}
+
+hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st) {
+  if (C.n_tot == 0) return hipSuccess;
+  const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
+  k_collide<<<nb, kBlock, 0, st>>>(C, in);
   return hipGetLastError();
 }
 

@@ -52,6 +52,8 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
                           bool x_done = false, int* far_reset = nullptr);
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st);
+// 4-way coupling: per-slot collision increments (before the push)
+hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st);
 // 2-way coupling source per cell from the push's per-slot drag forces
 hipError_t launch_source(const Ctx& C, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);

@@ -30,7 +30,6 @@ struct Fwd {
   double ke, a[3], du[3], re, phid, sdr, iden, v1[3];
   double x1, y1, z1;  // after the update, before rebound and wrap
   double qc;          // charge after particle-particle exchange (= q without 4-way coupling)
-  int npp;            // colliding pairs counted by this particle (partner of larger id)
 };
 
 // SORTED: positions and charges of slot s and of its cell mates come from the
@@ -156,43 +155,27 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
       sz += w * rz;
     }
   };
-  // 4-way coupling: binary hard-sphere collisions with the cell's particles on
-  // the state at the start of the step (increments summed in ascending id);
-  // pairs farther apart than (d + d_max)/2 are skipped before any gather
-  double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
-  int npp = 0;
-  double rcut2 = 0.0;
-  if constexpr (PP) {
-    if (E.pp) {
-      const double rc = 0.5 * (d + __longlong_as_double(C.stats[E.st_off + ST_DMAX]));
-      rcut2 = rc * rc;
-    }
-  }
   {
     const int a = C.start[c], b = C.start[c + 1];
     for (int t = a; t < b; ++t) {
       if (t == s) continue;
       if constexpr (SORTED) {
-        const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t], oq = C.sq[t];
-        coulomb(ox, oy, oz, oq);
-        if constexpr (PP) {
-          const double rx = x - ox, ry = y - oy, rz = z - oz;
-          const double r2 = (rx * rx + ry * ry) + rz * rz;
-          if (r2 < rcut2) {
-            const PPHit h = pp_pair(C.perm[t], in, E.kpp, rx, ry, rz, r2, d, vx, vy, vz, q, oq);
-            if (h.hit) {
-              if (t > s) ++npp;  // each pair counted once
-              cvx += h.dvx;
-              cvy += h.dvy;
-              cvz += h.dvz;
-              cq += h.dq;
-            }
-          }
-        }
+        coulomb(C.sx[t], C.sy[t], C.sz[t], C.sq[t]);
       } else {
         const int pj = C.perm[t];
         coulomb(in.x[pj], in.y[pj], in.z[pj], in.q[pj]);
       }
+    }
+  }
+  // 4-way coupling: the collision increments of this slot (pp_collide)
+  double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
+  if constexpr (PP) {
+    if (E.pp) {
+      const long long n = C.n_tot;
+      cvx = C.cinc[s];
+      cvy = C.cinc[n + s];
+      cvz = C.cinc[2 * n + s];
+      cq = C.cinc[3 * n + s];
     }
   }
   const bool pp = PP && E.pp;
@@ -227,7 +210,38 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   F.v1[0] = v1x; F.v1[1] = v1y; F.v1[2] = v1z;
   F.x1 = x1; F.y1 = y1; F.z1 = z1;
   F.qc = pp ? q + cq : q;
-  F.npp = npp;
+}
+
+// 4-way coupling: binary hard-sphere collisions of slot s (cell c, state at
+// the start of the step) with the other particles of its cell, increments
+// summed in ascending id; pairs farther apart than (d + d_max)/2 are skipped
+// before any gather.  Returns the pairs with a partner of larger id (each
+// pair is counted once over the two particles).
+__device__ __forceinline__ int pp_collide(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
+                                          double inc[4]) {
+  inc[0] = inc[1] = inc[2] = inc[3] = 0.0;
+  const double x = C.sx[s], y = C.sy[s], z = C.sz[s], q = C.sq[s];
+  const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p], d = in.d[p];
+  const double rc = 0.5 * (d + __longlong_as_double(C.stats[E.st_off + ST_DMAX]));
+  const double rcut2 = rc * rc;
+  int npp = 0;
+  const int a = C.start[c], b = C.start[c + 1];
+  for (int t = a; t < b; ++t) {
+    if (t == s) continue;
+    const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t];
+    const double rx = x - ox, ry = y - oy, rz = z - oz;
+    const double r2 = (rx * rx + ry * ry) + rz * rz;
+    if (!(r2 < rcut2)) continue;
+    const PPHit h = pp_pair(C.perm[t], in, E.kpp, rx, ry, rz, r2, d, vx, vy, vz, q, C.sq[t]);
+    if (h.hit) {
+      if (t > s) ++npp;
+      inc[0] += h.dvx;
+      inc[1] += h.dvy;
+      inc[2] += h.dvz;
+      inc[3] += h.dq;
+    }
+  }
+  return npp;
 }
 
 }  // namespace tf

@@ -113,6 +113,7 @@ struct Ctx {
   long long* qdep;           // optional [c_tot] per-cell deposit of the latest step
   double* fslot;             // optional [3][n_tot] drag force on the particle of each slot (2-way source)
   double* fsrc;              // optional [3][c_tot] 2-way coupling source of the latest step
+  double* cinc;              // optional [4][n_tot] collision increments (vx, vy, vz, q) of each slot
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
   const double2* tfac;       // Thomas factors per ensemble: [modes][ny] (1 / pivot, c')
