@@ -308,6 +308,84 @@ def _sum_by(index, values, n):
 
 
 # ----------------------------------------------------------------------------
+# Stochastic scaling model (SSM) of particle-wall charging (Sec. 2.3.2)
+# ----------------------------------------------------------------------------
+SSM_KEY1 = 0x53534D31  # second key word of the impact random numbers
+
+
+def philox4x32(c0, c1, c2, c3, k0, k1, rounds: int = 10):
+    """Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw,
+    SC'11): ten rounds of two 32x32->64 multiplications (multipliers
+    0xD2511F53, 0xCD9E8D57) with the key bumped by (0x9E3779B9, 0xBB67AE85)
+    between rounds.  Arguments: integer arrays (or ints) < 2^32; returns the
+    four output words."""
+    m = np.uint64(0xFFFFFFFF)
+    x = [np.asarray(v, dtype=np.uint64) & m for v in (c0, c1, c2, c3)]
+    k0, k1 = np.asarray(k0, dtype=np.uint64) & m, np.asarray(k1, dtype=np.uint64) & m
+    for r in range(rounds):
+        if r:
+            k0 = (k0 + np.uint64(0x9E3779B9)) & m
+            k1 = (k1 + np.uint64(0xBB67AE85)) & m
+        p0 = np.uint64(0xD2511F53) * x[0]
+        p1 = np.uint64(0xCD9E8D57) * x[2]
+        x = [(p1 >> np.uint64(32)) ^ x[1] ^ k0, p1 & m, (p0 >> np.uint64(32)) ^ x[3] ^ k1, p0 & m]
+    return x
+
+
+def impact_normals(ids, step: int, seed: int):
+    """Two standard normal numbers per impact: Philox4x32-10 at counter
+    (particle id, step number, 0, 0) and key (seed, SSM_KEY1); uniforms
+    u = (w + 1/2) 2^-32 of the first two words; Box-Muller."""
+    w = philox4x32(ids, step, 0, 0, seed, SSM_KEY1)
+    u0 = (w[0].astype(np.float64) + 0.5) * 2.0 ** -32
+    u1 = (w[1].astype(np.float64) + 0.5) * 2.0 ** -32
+    r = np.sqrt(-2.0 * np.log(u0))
+    t = 2.0 * math.pi * u1
+    return r * np.cos(t), r * np.sin(t)
+
+
+def skew_normal(mu, sigma, gamma, n0, n1):
+    """A skew-normal sample with mean mu, standard deviation sigma and
+    skewness gamma (|gamma| limited to 0.99), by the moment relations of the
+    skew-normal family: delta from gamma, omega = sigma / sqrt(1 - 2 delta^2/pi),
+    xi = mu - omega delta sqrt(2/pi), Z = delta |n0| + sqrt(1 - delta^2) n1."""
+    g = np.clip(gamma, -0.99, 0.99)
+    r = np.cbrt(2.0 * np.abs(g) / (4.0 - math.pi))
+    delta = np.sign(g) * (r / np.sqrt(1.0 + r * r)) * math.sqrt(math.pi / 2.0)
+    b = math.sqrt(2.0 / math.pi)
+    omega = sigma / np.sqrt(1.0 - (b * delta) ** 2)
+    xi = mu - omega * b * delta
+    return xi + omega * (delta * np.abs(n0) + np.sqrt(1.0 - delta * delta) * n1)
+
+
+def ssm_wall_charge(q, d, un, ids, step: int, prm: dict):
+    """Charge received by each impacting particle under the SSM.
+
+    Readings: the wall's active sites give the particle their mean,
+    mu_w = dq0min N_w/N_w0 (a grounded conducting wall regenerates at once);
+    the particle's sites give Delta q_1 ~ G(mu_i, sigma_i, gamma_i) to the
+    wall, so dq = mu_w - Delta q_1 (mean mu_0 in the reference impact);
+    A/A_0 = (d/d_0)^2 (u_n/u_n0)^(4/5) from the Hertz contact area with the
+    material constants cancelling; chi_w/chi_0 = 1 - sgn(dq0min) 4q/(c_sat d^2),
+    chi_i/chi_0 = 1 + sgn(dq0min - mu_0) 4q/(c_sat d^2), both clipped to [0, 1];
+    the site density c/c_0 = 1 (no depletion: its history term is not fully
+    specified); N/N_0 = 0 leaves no particle contribution."""
+    dq0, mu0 = prm["ssm_dq0min"], prm["ssm_mu0"]
+    s0, g0, csat = prm["ssm_sigma0"], prm["ssm_gamma0"], prm["ssm_csat"]
+    area = (d / prm["ssm_d0"]) ** 2 * (un / prm["ssm_un0"]) ** 0.8
+    load = 4.0 * q / (csat * (d * d))
+    chi_w = np.clip(1.0 - np.sign(dq0) * load, 0.0, 1.0)
+    chi_i = np.clip(1.0 + np.sign(dq0 - mu0) * load, 0.0, 1.0)
+    nw = area * chi_w
+    ni = area * chi_i
+    mu_w = dq0 * nw
+    n0, n1 = impact_normals(ids, step, prm["seed"])
+    safe = np.where(ni > 0.0, ni, 1.0)
+    dq1 = skew_normal((dq0 - mu0) * ni, s0 * np.sqrt(ni), -g0 / safe, n0, n1)
+    return mu_w - np.where(ni > 0.0, dq1, 0.0)
+
+
+# ----------------------------------------------------------------------------
 # 4-way coupling: particle-particle collisions and charge exchange
 # ----------------------------------------------------------------------------
 def pp_transfer_exponent(di, dj, speed, k_pp):
@@ -485,8 +563,17 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
     un = np.where(lo, -v1y, np.where(hi, v1y, 0.0))
     yr = np.where(lo, r + e * (r - y1), np.where(hi, top - e * (y1 - top), y1))
     vyr = np.where(hit, -e * v1y, v1y)
-    fchg = (kc * math.pow(1.0 + e, 0.4)) * np.power(np.where(hit, un, 0.0), 0.8)
-    dq = np.where(hit, -fchg * (dU + qc), 0.0)
+    if prm.get("charging", 0) == 1:
+        # stochastic scaling model: random numbers per (particle id, step number)
+        if stats is None:
+            raise ValueError("the SSM draws its random numbers by step number: pass stats")
+        dq = np.zeros(n)
+        h = np.flatnonzero(hit)
+        if h.size:
+            dq[h] = ssm_wall_charge(qc[h], d[h], un[h], h, stats.steps + 1, prm)
+    else:
+        fchg = (kc * math.pow(1.0 + e, 0.4)) * np.power(np.where(hit, un, 0.0), 0.8)
+        dq = np.where(hit, -fchg * (dU + qc), 0.0)
     q1 = np.where(hit, qc + dq, qc)
 
     # periodic wrap

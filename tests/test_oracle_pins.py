@@ -580,3 +580,92 @@ def test_pp_exponent_is_the_hertz_condenser_chain():
     k_pp = chain(0.5, 1.0, 1.0) / O.pp_transfer_exponent(0.5, 1.0, 1.0, 1.0)
     for di, dj, u in ((0.25, 0.25, 0.3), (2.0, 0.5, 4.0), (1.0, 1.0, 0.01), (0.7, 1.9, 12.0)):
         assert O.pp_transfer_exponent(di, dj, u, k_pp) == pytest.approx(chain(di, dj, u), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Stochastic scaling model (Sec. 2.3.2) and its random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        ctr, key, out = (list(map(lambda h: int(h, 16), part.split())) for part in line.split("|"))
+        got = O.philox4x32(*ctr, *key)
+        assert [int(v) for v in got] == out
+
+
+def _moments(x):
+    m = x.mean()
+    s = x.std()
+    return m, s, np.mean(((x - m) / s) ** 3)
+
+
+def test_impact_normals_are_standard():
+    ids = np.arange(200_000)
+    n0, n1 = O.impact_normals(ids, 7, 12345)
+    for v in (n0, n1):
+        m, s, g = _moments(v)
+        assert abs(m) < 0.01 and abs(s - 1) < 0.01 and abs(g) < 0.03
+    assert abs(np.corrcoef(n0, n1)[0, 1]) < 0.01
+    # counter-based: the same (id, step, seed) gives the same numbers, another step others
+    a, _ = O.impact_normals(ids[:10], 7, 12345)
+    b, _ = O.impact_normals(ids[:10], 8, 12345)
+    np.testing.assert_array_equal(a, n0[:10])
+    assert not np.any(a == b)
+
+
+@pytest.mark.parametrize("mu,sigma,gamma", [(0.0, 1.0, 0.0), (2.0, 0.5, 0.8), (-1.0, 3.0, -0.5)])
+def test_skew_normal_moments(mu, sigma, gamma):
+    n0, n1 = O.impact_normals(np.arange(400_000), 3, 99)
+    x = O.skew_normal(mu, sigma, gamma, n0, n1)
+    m, s, g = _moments(x)
+    assert m == pytest.approx(mu, abs=0.01 * sigma)
+    assert s == pytest.approx(sigma, rel=0.01)
+    assert g == pytest.approx(gamma, abs=0.03)
+
+
+SSM = dict(charging=1, ssm_dq0min=-2e-3, ssm_mu0=-1.5e-3, ssm_sigma0=4e-4, ssm_gamma0=0.6, ssm_csat=20.0,
+           ssm_d0=0.5, ssm_un0=1.0, seed=2024)
+
+
+def test_ssm_reproduces_reference_impact():
+    # d = d_0, u_n = u_n0, q = 0: the impact charge has the reference
+    # experiment's mean, standard deviation and skewness
+    n = 400_000
+    prm = dict(SSM)
+    dq = O.ssm_wall_charge(np.zeros(n), np.full(n, 0.5), np.full(n, 1.0), np.arange(n), 5, prm)
+    m, s, g = _moments(dq)
+    assert m == pytest.approx(prm["ssm_mu0"], rel=0.01)
+    assert s == pytest.approx(prm["ssm_sigma0"], rel=0.01)
+    assert g == pytest.approx(prm["ssm_gamma0"], abs=0.03)
+
+
+def test_ssm_deterministic_limit_is_the_condenser_model():
+    # sigma_0 = gamma_0 = 0, mu_0 = dq0min: the SSM impact charge
+    # dq0min (u_n/u_n0)^(4/5) (1 + q/dU) equals the condenser model's
+    # -k_c (1 + e)^(2/5) u_n^(4/5) (dU + q) for monodisperse particles with
+    # d_0 = d, dq0min = -k_c (1 + e)^(2/5) dU u_n0^(4/5), c_sat = 4 dU / d^2
+    # (while 0 <= 1 + q/dU <= 1)
+    ens = W.make_ensemble(W.CONFIGS[1].replace(re_tau=20.0, n_particles=3000, v_jitter=4.0, precharge=0.0,
+                                               density_ratio=30.0, nx=16, ny=16, nz=16))
+    g = O.Geo.from_mesh(ens.mesh)
+    base = dict(ens.params, k_c=0.02)
+    kc, e, dU, d = base["k_c"], base["e"], base["delta_u"], 0.5
+    un0 = 0.7
+    ssm = dict(base, charging=1, ssm_sigma0=0.0, ssm_gamma0=0.0, ssm_d0=d, ssm_un0=un0,
+               ssm_dq0min=-kc * (1 + e) ** 0.4 * dU * un0 ** 0.8, ssm_csat=4.0 * dU / d ** 2, seed=1)
+    ssm["ssm_mu0"] = ssm["ssm_dq0min"]
+    sa, sb = O.state_of(ens), O.state_of(ens)
+    sta, stb = O.Stats(g.ny), O.Stats(g.ny)
+    for _ in range(40):
+        sa = O.step(g, ens.U, sa, base, sta)
+        sb = O.step(g, ens.U, sb, ssm, stb)
+    assert sta.impacts.sum() > 40
+    np.testing.assert_array_equal(sta.impacts, stb.impacts)
+    np.testing.assert_allclose(sb["q"], sa["q"], rtol=1e-12, atol=1e-15)
+    assert np.all(sa["q"] <= 0) and np.all(sa["q"] >= -dU)
+    # the SSM path was taken: another saturation parameter changes the charges
+    sc, stc = O.state_of(ens), O.Stats(g.ny)
+    for _ in range(40):
+        sc = O.step(g, ens.U, sc, dict(ssm, ssm_csat=2.0 * ssm["ssm_csat"]), stc)
+    assert np.abs(sc["q"] - sa["q"]).max() > 1e-6
