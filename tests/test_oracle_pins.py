@@ -664,8 +664,8 @@ def test_ssm_deterministic_limit_is_the_condenser_model():
     np.testing.assert_array_equal(sta.impacts, stb.impacts)
     np.testing.assert_allclose(sb["q"], sa["q"], rtol=1e-12, atol=1e-15)
     assert np.all(sa["q"] <= 0) and np.all(sa["q"] >= -dU)
-    # the SSM path was taken: another saturation parameter changes the charges
+    # the SSM path was taken: another reference impact speed changes the charges
     sc, stc = O.state_of(ens), O.Stats(g.ny)
     for _ in range(40):
-        sc = O.step(g, ens.U, sc, dict(ssm, ssm_csat=2.0 * ssm["ssm_csat"]), stc)
+        sc = O.step(g, ens.U, sc, dict(ssm, ssm_un0=2.0 * un0), stc)
     assert np.abs(sc["q"] - sa["q"]).max() > 1e-6
