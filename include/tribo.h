@@ -114,6 +114,21 @@ typedef struct tf_handle tf_handle;
  *               and wall charging start from the changed velocity and charge;
  *               the step's electric forces use the deposited charges.  Not
  *               differentiated: TF_STEP_RECORD is refused while pp is on.
+ *   charging    wall charging: 0 = condenser model (k_c, delta_u), 1 = the
+ *               stochastic scaling model (Sec. 2.3.2): an impact gives the
+ *               particle dq = mu_w - Dq_1, mu_w = ssm_dq0min N_w/N_w0 (the
+ *               wall's sites, mean), Dq_1 a skew-normal number with mean
+ *               (ssm_dq0min - ssm_mu0) N_i/N_0, standard deviation
+ *               ssm_sigma0 sqrt(N_i/N_0), skewness -ssm_gamma0 N_0/N_i
+ *               (limited to +-0.99); N_w/N_w0 = A/A_0 chi_w, N_i/N_0 = A/A_0
+ *               chi_i, A/A_0 = (d/ssm_d0)^2 (u_n/ssm_un0)^(4/5),
+ *               chi_w = 1 - sgn(ssm_dq0min) 4q/(ssm_csat d^2),
+ *               chi_i = 1 + sgn(ssm_dq0min - ssm_mu0) 4q/(ssm_csat d^2), both
+ *               clipped to [0, 1].  Random numbers: Philox4x32-10 at counter
+ *               (particle id, step number since tf_init, 0, 0), key (seed,
+ *               0x53534D31), Box-Muller on the first two words.  With
+ *               ssm_sigma0 = ssm_gamma0 = 0 and ssm_mu0 = ssm_dq0min the model
+ *               is deterministic.  Not differentiated (TF_STEP_RECORD refused).
  */
 typedef struct {
   int32_t nx, ny, nz, n_particles;
@@ -124,7 +139,10 @@ typedef struct {
   double un_bin;
   const double* u_nodes;
   double k_pp;
-  int32_t pp, reserved;
+  int32_t pp;
+  int32_t charging;           /* wall charging model: 0 condenser, 1 SSM */
+  uint32_t seed, reserved;    /* SSM random numbers */
+  double ssm_dq0min, ssm_mu0, ssm_sigma0, ssm_gamma0, ssm_csat, ssm_d0, ssm_un0;
 } tf_ensemble;
 
 /* Particle arrays (device pointers, n_particles doubles each, indexed by

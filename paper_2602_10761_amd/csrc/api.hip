@@ -99,6 +99,12 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     if ((E.pp != 0 && E.pp != 1) || !(E.k_pp >= 0) || !std::isfinite(E.k_pp))
       return fail(TF_EINVAL, pre + "pp must be 0 or 1 and k_pp finite and >= 0");
     if (E.pp) S->pp_any = true;
+    if (E.charging != 0 && E.charging != 1) return fail(TF_EINVAL, pre + "charging must be 0 or 1");
+    if (E.charging == 1 &&
+        !(std::isfinite(E.ssm_dq0min) && std::isfinite(E.ssm_mu0) && std::isfinite(E.ssm_gamma0) &&
+          E.ssm_sigma0 >= 0 && std::isfinite(E.ssm_sigma0) && E.ssm_csat != 0 && std::isfinite(E.ssm_csat) &&
+          E.ssm_d0 > 0 && std::isfinite(E.ssm_d0) && E.ssm_un0 > 0 && std::isfinite(E.ssm_un0)))
+      return fail(TF_EINVAL, pre + "SSM parameters: finite, sigma0 >= 0, csat != 0, d0 > 0, un0 > 0");
     if (!E.y_faces) return fail(TF_EINVAL, pre + "y_faces is NULL");
     if (!E.u_nodes) return fail(TF_EINVAL, pre + "u_nodes is NULL");
     if (E.y_faces[0] != 0.0) return fail(TF_EINVAL, pre + "y_faces[0] must be 0");
@@ -524,6 +530,15 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.inv_nz = 1.0 / T.nz;
     E.pp = T.pp;
     E.kpp = T.k_pp;
+    E.charging = T.charging;
+    E.seed = T.seed;
+    E.sdq0 = T.ssm_dq0min;
+    E.smu0 = T.ssm_mu0;
+    E.ssig0 = T.ssm_sigma0;
+    E.sgam0 = T.ssm_gamma0;
+    E.scsat = T.ssm_csat;
+    E.sd0 = T.ssm_d0;
+    E.sun0 = T.ssm_un0;
     E.c18 = 18.0 / T.density_ratio;
     E.fe = T.k_c * std::pow(1.0 + T.e, 0.4);
     E.pe = std::pow(1.0 + T.e, 0.4);
@@ -668,7 +683,8 @@ int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags) {
   const bool rec = (flags & TF_STEP_RECORD) != 0;
   if (rec)
     for (int e = 0; e < h->n_ens; ++e)
-      if (h->eh[e].pp) return fail(TF_ESTATE, "recording (adjoint) is not available with particle-particle collisions");
+      if (h->eh[e].pp || h->eh[e].charging)
+        return fail(TF_ESTATE, "recording (adjoint) is not available with collisions or the SSM");
   if (rec) {
     if (h->traj_cap == 0) return fail(TF_ESTATE, "no trajectory capacity (traj_steps = 0 at tf_init)");
     if (h->traj_len + n_steps > h->traj_cap) return fail(TF_ESIZE, "recorded trajectory would exceed traj_steps");

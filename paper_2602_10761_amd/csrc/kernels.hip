@@ -1085,9 +1085,15 @@ __global__ __launch_bounds__(kBlock) void k_tri(Ctx C, Ens Eone, int one, const 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one, const int* __restrict__ blk_off,
                                                        int blk0, int nmax, double* __restrict__ phi_out,
-                                                       long long phi_shift, int* __restrict__ far_reset) {
-  // the sort of this step has read the far list: empty it for this step's push
-  if (far_reset && blockIdx.x == 0 && threadIdx.x == 0) *far_reset = 0;
+                                                       long long phi_shift, int* __restrict__ far_reset,
+                                                       int bump) {
+  // the sort of this step has read the far list: empty it for this step's push;
+  // bump: count the step (the push then reads the step number)
+  if (far_reset && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *far_reset = 0;
+    if (bump)
+      for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+  }
   extern __shared__ double2 lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double2* tw = lds;
@@ -1272,9 +1278,14 @@ __global__ __launch_bounds__(kBlock) void k_z(Ctx C, Ens Eone, int one, const in
 __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, int one,
                                                              const int* __restrict__ blk_off, int blk0,
                                                              double* __restrict__ phi_out, long long phi_shift,
-                                                             int* __restrict__ far_reset) {
-  // the sort of this step has read the far list: empty it for this step's push
-  if (far_reset && blockIdx.x == 0 && threadIdx.x == 0) *far_reset = 0;
+                                                             int* __restrict__ far_reset, int bump) {
+  // the sort of this step has read the far list: empty it for this step's push;
+  // bump: count the step (the push then reads the step number)
+  if (far_reset && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *far_reset = 0;
+    if (bump)
+      for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+  }
   extern __shared__ double2 lds[];
   Ens E;
   int j;
@@ -1393,6 +1404,54 @@ __device__ __forceinline__ void pair_count(int* __restrict__ pair_cnt, int key) 
   atomicAdd(&pair_cnt[key], __popcll(act & upto & ~((1ull << lane) - 1ull)));
 }
 
+// ---------------------------------------------------------------------------
+// stochastic scaling model of particle-wall charging
+// ---------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC'11)
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    const unsigned hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+  }
+  return c;
+}
+
+// charge received by a particle (charge q, diameter d, id) hitting a wall with
+// normal speed un in step number step: the wall's sites give their mean
+// mu_w, the particle's sites a skew-normal number Dq_1 (mean, standard
+// deviation and skewness scaled from the reference impact by the active sites)
+__device__ double ssm_dq(const Ens& E, double q, double d, double un, int id, unsigned step) {
+  const double a0 = d / E.sd0;
+  const double area = (a0 * a0) * pow(un / E.sun0, 0.8);
+  const double load = 4.0 * q / (E.scsat * (d * d));
+  const double sw = (E.sdq0 > 0.0) - (E.sdq0 < 0.0), si = (E.sdq0 - E.smu0 > 0.0) - (E.sdq0 - E.smu0 < 0.0);
+  const double chi_w = fmin(fmax(1.0 - sw * load, 0.0), 1.0);
+  const double chi_i = fmin(fmax(1.0 + si * load, 0.0), 1.0);
+  const double nw = area * chi_w, ni = area * chi_i;
+  const double mu_w = E.sdq0 * nw;
+  if (!(ni > 0.0)) return mu_w;
+  const uint4 w = philox4x32_10(make_uint4((unsigned)id, step, 0u, 0u), make_uint2(E.seed, 0x53534D31u));
+  const double u0 = ((double)w.x + 0.5) * 0x1p-32, u1 = ((double)w.y + 0.5) * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u0)), t = 2.0 * kPi * u1;
+  const double n0 = r * cos(t), n1 = r * sin(t);
+  // skew-normal with mean mu, deviation sigma, skewness g (moment relations)
+  const double mu = (E.sdq0 - E.smu0) * ni, sigma = E.ssig0 * sqrt(ni);
+  const double g = fmin(fmax(-E.sgam0 / ni, -0.99), 0.99);
+  const double rc = cbrt(2.0 * fabs(g) / (4.0 - kPi));
+  const double delta = ((g > 0.0) - (g < 0.0)) * (rc / sqrt(1.0 + rc * rc)) * sqrt(kPi / 2.0);
+  const double b = sqrt(2.0 / kPi);
+  const double bd = b * delta;
+  const double omega = sigma / sqrt(1.0 - bd * bd);
+  const double xi = mu - omega * b * delta;
+  const double dq1 = xi + omega * (delta * fabs(n0) + sqrt(1.0 - delta * delta) * n1);
+  return mu_w - dq1;
+}
+
 template <bool PP>
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
                                          int p, int c, signed char* __restrict__ wall_rec) {
@@ -1424,8 +1483,13 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   if (wall_rec) wall_rec[s] = (signed char)wall;
   if (wall >= 0) {
     vyr = -E.e * v1y;
-    const double f = E.fe * pow(un, 0.8);
-    const double dq = -f * (E.dU + q);
+    double dq;
+    if (E.charging) {
+      dq = ssm_dq(E, q, d, un, in.id[p], (unsigned)st[ST_STEPS]);
+    } else {
+      const double f = E.fe * pow(un, 0.8);
+      dq = -f * (E.dU + q);
+    }
     q1 = q + dq;
     bool ovf = false;
     const long long wq = fixed_round(-dq, kFixWall, &ovf);
@@ -1495,8 +1559,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
   // the new row ranges become the stored order's (read by the next sort)
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
     C.rs_old[r] = C.rs_new[r];
-  if (blockIdx.x == 0)  // the step counter of every ensemble (one push per step)
-    for (int e = threadIdx.x; e < C.n_ens; e += kBlock) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
   if (s < C.n_tot) {
     const int p = C.perm[s];
@@ -1681,19 +1743,20 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
   if (fused) {
     const int p0 = G.pl_blk[e0], np = G.pl_blk[e1] - p0;
     const size_t lp = (size_t)(G.nx_max + G.nz_max + G.plane_max) * sizeof(double2);
-    if (np > 0) k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, far_reset);
+    if (np > 0)
+      k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, far_reset, 1);
   }
   if (split && nzb > 0) k_z<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.nz_max);
   mark(3);
   if (split && nb > 0)
-    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset);
+    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset,
+                                         fused ? 0 : 1);
   mark(4);
   return hipGetLastError();
 }
 
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st) {
-  // at least one block: the step counters are kept by block 0
   const int nb = std::max(1, (int)((C.n_tot + kBlock - 1) / kBlock));
   const int one = (C.n_ens == 1) ? 1 : 0;
   // the collision code only when an ensemble has 4-way coupling on

@@ -46,6 +46,9 @@ struct Ens {
   double fe;                                // k_c (1 + e)^(2/5)
   double kpp;                               // particle-particle charge-exchange coefficient
   int pp;                                   // 4-way coupling on
+  int charging;                             // 0 condenser, 1 stochastic scaling model
+  unsigned seed;                            // SSM random numbers
+  double sdq0, smu0, ssig0, sgam0, scsat, sd0, sun0;  // SSM reference impact
   double pe;                                // (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
   FftPlan fx, fz;

@@ -31,12 +31,17 @@ FIX_DEPOSIT, FIX_WALL, FIX_QCUM = 48, 40, 32
 KEYS = ("x", "y", "z", "vx", "vy", "vz", "q", "d")
 
 
+SSM_KEYS = ("ssm_dq0min", "ssm_mu0", "ssm_sigma0", "ssm_gamma0", "ssm_csat", "ssm_d0", "ssm_un0")
+
+
 class TfEnsemble(Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("n_particles", c_int32),
                 ("lx", c_double), ("lz", c_double), ("y_faces", POINTER(c_double)),
                 ("dt", c_double), ("density_ratio", c_double), ("k_c", c_double), ("delta_u", c_double),
                 ("e", c_double), ("c_el", c_double), ("g", c_double * 3), ("un_bin", c_double),
-                ("u_nodes", c_void_p), ("k_pp", c_double), ("pp", c_int32), ("reserved", c_int32)]
+                ("u_nodes", c_void_p), ("k_pp", c_double), ("pp", c_int32), ("charging", c_int32),
+                ("seed", ctypes.c_uint32), ("reserved", ctypes.c_uint32)] + \
+        [(k, c_double) for k in SSM_KEYS]
 
 
 class TfParticles(Structure):
@@ -154,6 +159,9 @@ class TriboSim:
                 c.g[i] = p["g"][i]
             c.un_bin = p["un_bin"]
             c.pp, c.k_pp = int(p.get("pp", 0)), float(p.get("k_pp", 0.0))
+            c.charging, c.seed = int(p.get("charging", 0)), int(p.get("seed", 0)) & 0xFFFFFFFF
+            for k in SSM_KEYS:
+                setattr(c, k, float(p.get(k, 1.0 if k in ("ssm_csat", "ssm_d0", "ssm_un0") else 0.0)))
             c.u_nodes = self.U[e].data_ptr()
             arrs = {k: t(getattr(E, k)) for k in KEYS}
             init_t.append(arrs)

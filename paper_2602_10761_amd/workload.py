@@ -266,6 +266,9 @@ class EnsembleSpec:
     un_bin: float = 0.05
     pp: int = 0                      # 4-way coupling (particle-particle collisions) on
     k_pp: float = 0.0                # particle-particle charge-exchange coefficient
+    charging: int = 0                # wall charging: 0 condenser, 1 stochastic scaling model
+    ssm: Tuple[float, ...] = ()      # SSM (dq0min, mu0, sigma0, gamma0, csat, d0, un0)
+    seed: int = 0                    # SSM random numbers
     steps: int = 1000
     precharge: float = 0.0           # q0 ~ U[-precharge, precharge]
     v_jitter: float = 0.0            # v0 += v_jitter * U[-1, 1]^3 (tests that need early impacts)
@@ -327,7 +330,10 @@ def make_ensemble(spec: EnsembleSpec, config_index: int = 0, seed: int = 0, sub:
     c_el = spec.c_el if spec.c_el is not None else electric_coupling(spec.re_tau)
     params = dict(dt=spec.dt, density_ratio=spec.density_ratio, k_c=spec.k_c,
                   delta_u=spec.delta_u, e=spec.e, c_el=c_el, g=tuple(spec.g), un_bin=spec.un_bin,
-                  pp=spec.pp, k_pp=spec.k_pp)
+                  pp=spec.pp, k_pp=spec.k_pp, charging=spec.charging, seed=spec.seed)
+    if spec.ssm:
+        params.update(zip(("ssm_dq0min", "ssm_mu0", "ssm_sigma0", "ssm_gamma0", "ssm_csat", "ssm_d0", "ssm_un0"),
+                          spec.ssm))
     return Ensemble(spec, mesh, U, x, y, z, vx, vy, vz, q, d, params)
 
 

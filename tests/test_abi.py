@@ -98,3 +98,31 @@ def test_bench_traffic_file_parsing(tmp_path, monkeypatch):
     assert bench.measured_traffic("tridiag") is None
     monkeypatch.setattr(bench, "source_hash", lambda: "other")
     assert bench.measured_traffic("push") is None
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of the ABI structs have the C layout (sizes and offsets)
+    import shutil
+    import subprocess
+    from paper_2602_10761_amd import runtime as R
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"tf_ensemble": R.TfEnsemble, "tf_particles": R.TfParticles, "tf_stats_out": R.TfStatsOut,
+               "tf_tuning": R.TfTuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tribo.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{name}.{f[0]}"

@@ -339,3 +339,55 @@ def test_pp_record_refused():
     sim.step(1)
     assert sim.stats(0)["steps"] == 1
     sim.close()
+
+
+# ---------------------------------------------------------------------------
+# stochastic scaling model of wall charging
+# ---------------------------------------------------------------------------
+SSM_PARAMS = (-2e-3, -1.5e-3, 4e-4, 0.6, 20.0, 0.5, 1.0)  # dq0min, mu0, sigma0, gamma0, csat, d0, un0
+
+
+def ssm_ensemble(**kw):
+    spec = W.CONFIGS[1].replace(re_tau=20.0, nx=16, ny=16, nz=16, n_particles=4000, v_jitter=4.0, precharge=0.0,
+                                density_ratio=30.0, charging=1, ssm=SSM_PARAMS, seed=77, **kw)
+    return W.make_ensemble(spec, 1, 0)
+
+
+def test_ssm_parity():
+    say("ssm")
+    ens = ssm_ensemble()
+    n = 30
+    sim = sim_of(ens)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    sim.close()
+    ref, st = oracle_run(ens, n)
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  impacts", st.impacts, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert st.impacts.sum() > 40
+    np.testing.assert_array_equal(gst["impacts"], st.impacts)
+    np.testing.assert_array_equal(gst["unhist"], st.unhist)
+    assert max(err.values()) < 1e-10
+    # wall charge: sums of rne(-dq 2^40) (an impact may round the other way)
+    assert np.all(np.abs(gst["wallq"] - st.wallq) <= st.impacts)
+    assert np.std(gpu["q"][gpu["q"] != 0]) > 0  # random, not one value
+
+
+def test_ssm_deterministic_limit_equals_condenser():
+    # sigma0 = gamma0 = 0, mu0 = dq0min, csat and dq0min matched to k_c, delta_u
+    kc, e, dU, d, un0 = 0.02, 0.9, 1.0, 0.5, 0.7
+    dq0 = -kc * (1 + e) ** 0.4 * dU * un0 ** 0.8
+    base = dict(re_tau=20.0, nx=16, ny=16, nz=16, n_particles=3000, v_jitter=4.0, density_ratio=30.0, k_c=kc, e=e)
+    a = W.make_ensemble(W.CONFIGS[1].replace(**base), 1, 0)
+    b = W.make_ensemble(W.CONFIGS[1].replace(charging=1, ssm=(dq0, dq0, 0.0, 0.0, 4.0 * dU / d ** 2, d, un0),
+                                             **base), 1, 0)
+    res = []
+    for E in (a, b):
+        sim = sim_of(E)
+        sim.step(40)
+        res.append((sim.state_np(0), sim.stats(0)))
+        sim.close()
+    assert res[0][1]["impacts"].sum() > 40
+    np.testing.assert_array_equal(res[0][1]["impacts"], res[1][1]["impacts"])
+    np.testing.assert_allclose(res[1][0]["q"], res[0][0]["q"], rtol=1e-12, atol=1e-15)
