@@ -163,20 +163,24 @@ def source_cost(torch, W, R, steps, log):
 def four_way_cost(torch, W, R, steps, log):
     """Time of the headline step with 4-way coupling (same-cell particle-particle
     collisions, k_pp = 1) against the plain step, graph replays, and the pairs
-    that collided."""
+    that collided; and with the stochastic scaling model of wall charging."""
     ms, pairs = {}, 0
-    for on in (False, True):
-        ens = W.make_workload(2, pp=int(on), k_pp=1.0)[0]
+    ssm = (-2e-3, -1.5e-3, 4e-4, 0.6, 20.0, 0.5, 1.0)
+    for on in (False, True, "ssm"):
+        kw = dict(charging=1, ssm=ssm, seed=1) if on == "ssm" else dict(pp=int(on), k_pp=1.0)
+        ens = W.make_workload(2, **kw)[0]
         sim = R.TriboSim([ens], graphs=True)
         sim.step(3)
         ms[on] = timed_steps(torch, sim, steps) / steps
-        if on:
+        if on is True:
             pairs = int(sim.stats(0)["pp_pairs"])
         sim.close()
         del sim
-    log(f"4-way coupling: {ms[False] * 1e3:.1f} -> {ms[True] * 1e3:.1f} us/step, {pairs} pairs")
+    log(f"4-way coupling: {ms[False] * 1e3:.1f} -> {ms[True] * 1e3:.1f} us/step, {pairs} pairs; "
+        f"SSM wall charging {ms['ssm'] * 1e3:.1f} us/step")
     return {"workload": WORKLOAD_NAME[2] + ", k_pp=1", "us_per_step_without": ms[False] * 1e3,
-            "us_per_step_with": ms[True] * 1e3, "colliding_pairs": pairs, "steps": steps + 3}
+            "us_per_step_with": ms[True] * 1e3, "colliding_pairs": pairs, "steps": steps + 3,
+            "us_per_step_ssm_wall_charging": ms["ssm"] * 1e3}
 
 
 def adjoint_ratio(torch, W, R, autotune, seg, log):
