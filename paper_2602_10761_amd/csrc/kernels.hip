@@ -1370,8 +1370,32 @@ __device__ __forceinline__ int y_cell(const double* __restrict__ yf, int ny, dou
 // initial binning: cell key of every particle (the next sort is a full one)
 __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, long long n1) {
   const long long p = n0 + (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n1) return;
-  const int e = find_off(C.p_off, C.n_ens + 1, p);
+  const bool valid = p < n1;
+  const long long pc = valid ? p : n1 - 1;  // n1 > n0: every lane reads a particle
+  const int e = find_off(C.p_off, C.n_ens + 1, pc);
+  // diameter bound of the ensemble (the collision search's prefilter): the
+  // maximum over a wave's lanes of one ensemble, one atomic per wave and
+  // ensemble (positive doubles order like their bit patterns); all lanes take
+  // part in the shuffles
+  {
+    const unsigned long long dm = valid ? (unsigned long long)__double_as_longlong(fmax(S.d[pc], 0.0)) : 0ull;
+    bool pending = valid;
+    for (unsigned long long m = __ballot(pending); m; m = __ballot(pending)) {
+      // the ensemble of the first pending lane: at least that lane finishes
+      const int e0 = __shfl(e, __ffsll((long long)m) - 1, 64);
+      unsigned long long v = (pending && e == e0) ? dm : 0ull;
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+      }
+      if (pending && e == e0) {
+        if (__lane_id() == __builtin_amdgcn_readfirstlane(__lane_id()) && v)
+          atomicMax((unsigned long long*)&C.stats[C.ens[e0].st_off + ST_DMAX], v);
+        pending = false;
+      }
+    }
+  }
+  if (!valid) return;
   const Ens& E = C.ens[e];
   const double x = S.x[p], y = S.y[p], z = S.z[p];
   const int i = clamp_floor(x / E.dx, E.nx);
@@ -1379,10 +1403,6 @@ __global__ __launch_bounds__(kBlock) void k_bin(Ctx C, PState S, long long n0, l
   const int j = y_cell(C.yf + E.y_off, E.ny, y);
   const int c = (int)(E.c_off + (long long)(j * E.nz + k) * E.nx + i);
   S.key[p] = c;
-  // diameter bound of the ensemble (the collision search's prefilter)
-  const double d = S.d[p];
-  if (d > 0.0)
-    atomicMax((unsigned long long*)&C.stats[E.st_off + ST_DMAX], (unsigned long long)__double_as_longlong(d));
 }
 
 // ---------------------------------------------------------------------------
