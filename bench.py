@@ -183,6 +183,30 @@ def four_way_cost(torch, W, R, steps, log):
             "us_per_step_ssm_wall_charging": ms["ssm"] * 1e3}
 
 
+def carrier_stream_cost(torch, W, R, steps, log):
+    """Step time of the headline workload when the carrier field changes every
+    step (two fields alternating through tf_set_carrier, graph replays)."""
+    import numpy as np
+    ens = W.make_workload(2)[0]
+    sim = R.TriboSim([ens], graphs=True)
+    U2 = torch.as_tensor(np.ascontiguousarray(ens.U * 0.9), dtype=torch.float64).to(sim.dev)
+    fields = [sim.U[0], U2]
+    sim.step(3)
+    sim.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(sim.stream)
+    for n in range(steps):
+        sim.set_carrier(0, fields[n % 2])
+        sim.step(1)
+    ev1.record(sim.stream)
+    sim.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    sim.close()
+    log(f"carrier changed every step: {ms * 1e3:.1f} us/step")
+    return {"workload": WORKLOAD_NAME[2] + ", two carrier fields alternating", "us_per_step": ms * 1e3}
+
+
 def adjoint_ratio(torch, W, R, autotune, seg, log):
     ens = W.make_workload(5, v_jitter=3.0, precharge=0.02)[0]
     autotune.ensure_tuned(autotune.meshes_of([ens]))
@@ -327,6 +351,7 @@ def main():
         out["two_way_source"] = source_cost(torch, W, R, 50, log)
     if not args.no_fourway:
         out["four_way"] = four_way_cost(torch, W, R, 50, log)
+        out["carrier_every_step"] = carrier_stream_cost(torch, W, R, 50, log)
     if not args.no_cpu:
         v, secs = cpu_baseline(ens, args.cpu_steps)
         out["cpu_baseline"] = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

@@ -193,8 +193,10 @@ int tf_set_state(tf_handle* h, int32_t ens, const tf_particles* in);
 
 /* Make ensemble `ens` read its carrier velocity from u_nodes (same layout
  * as tf_ensemble.u_nodes, device memory, borrowed) from the next step on: a
- * time-dependent carrier field.  Synchronises the handle's stream.  Errors:
- * TF_EINVAL (NULL, ensemble out of range), TF_EHIP. */
+ * time-dependent carrier field.  Asynchronous, in stream order (steps queued
+ * before the call read the previous field, which must stay valid until they
+ * have run); captured step graphs stay valid.  Errors: TF_EINVAL (NULL,
+ * ensemble out of range), TF_ESTATE (a recorded trajectory is pending), TF_EHIP. */
 int tf_set_carrier(tf_handle* h, int32_t ens, const double* u_nodes);
 
 /* Replace (k_c, delta_u, e) of every ensemble: host array [n_ens][3]. */

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(Ctx C, Ens Eone, int one, PSta
     const double idyj = C.idy[E.y_off + F.j];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      const double* __restrict__ b = E.U + cc * F.plane;
+      const double* __restrict__ b = C.uptr[E.ei] + cc * F.plane;
       const double a000 = b[F.n00 + F.i], a100 = b[F.n00 + F.i1];
       const double a001 = b[F.n01 + F.i], a101 = b[F.n01 + F.i1];
       const double a010 = b[F.n10 + F.i], a110 = b[F.n10 + F.i1];

@@ -273,6 +273,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.rs_new = cv.take<int>(S.rows + 1);
   C.far = cv.take<int>(S.n_tot);
   C.far_n = cv.take<int>(2);
+  C.uptr = cv.take<const double*>(n_ens);
   PState A = carve_state(cv, S.n_tot);
   PState B = carve_state(cv, S.n_tot);
   C.count = cv.take<int>(S.c_tot);
@@ -501,6 +502,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.tf_off = tf_off;
     E.row_off = row_off;
     E.y_off = y_off;
+    E.ei = e;
     E.kx_off = kx_off;
     E.kz_off = kz_off;
     E.st_off = st_off;
@@ -622,6 +624,9 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->C.kx2, kx2);
   UP(h->C.kz2, kz2);
   UP(h->C.tw, tw);
+  std::vector<const double*> uptr(n_ens);
+  for (int e = 0; e < n_ens; ++e) uptr[e] = ens[e].u_nodes;
+  UP(h->C.uptr, uptr);
   UP(h->C.tfac, tfac);
 #undef UP
   if (he == hipSuccess) he = hipMemsetAsync(h->C.stats, 0, sizeof(long long) * S.st_tot, h->stream);
@@ -830,11 +835,11 @@ int tf_set_state(tf_handle* h, int32_t e, const tf_particles* in) {
 int tf_set_carrier(tf_handle* h, int32_t e, const double* u_nodes) {
   if (!h || !u_nodes) return fail(TF_EINVAL, "NULL argument");
   if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
+  if (h->traj_len > 0) return fail(TF_ESTATE, "a recorded trajectory is pending (tf_adjoint_step first)");
   h->eh[e].U = u_nodes;
-  // the descriptors live on the device and, by value, in the captured graphs
-  HIPCHK(hipMemcpyAsync(h->d_ens + e, &h->eh[e], sizeof(Ens), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  destroy_graphs(h);
+  // kernels read the pointer from the device table: one tiny kernel in stream
+  // order, no synchronisation, captured graphs stay valid
+  HIPCHK(launch_set_ptr(h->C.uptr + e, u_nodes, h->stream));
   return TF_OK;
 }
 

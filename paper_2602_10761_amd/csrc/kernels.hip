@@ -1843,6 +1843,13 @@ hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_set_ptr(const double** slot, const double* value) { *slot = value; }
+
+hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st) {
+  k_set_ptr<<<1, 1, 0, st>>>(slot, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st) {
   if (n1 <= n0) return hipSuccess;
   const int nb = (int)((n1 - n0 + kBlock - 1) / kBlock);

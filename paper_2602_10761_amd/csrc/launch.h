@@ -54,6 +54,8 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
                        signed char* wall_rec, hipStream_t st);
 // 4-way coupling: per-slot collision increments (before the push)
 hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st);
+// *slot = value, in stream order (a kernel: usable between captured graphs)
+hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st);
 // 2-way coupling source per cell from the push's per-slot drag forces
 hipError_t launch_source(const Ctx& C, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);

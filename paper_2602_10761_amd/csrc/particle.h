@@ -100,7 +100,7 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   double uc[3];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
-    const double* __restrict__ b = E.U + cc * plane;
+    const double* __restrict__ b = C.uptr[E.ei] + cc * plane;
     // nodes i and i + 1 of a row as one 16-byte load (8-byte aligned) away
     // from the periodic end of the row: half the gather instructions
     d2u u00, u01, u10, u11;

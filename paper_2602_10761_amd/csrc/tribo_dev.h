@@ -33,6 +33,7 @@ struct Ens {
   long long row_off; // first (j, k) row
   long long tf_off;  // first tridiagonal factor ([nz * nh][ny], mode-major)
   int y_off;         // first entry in the per-y tables (ny+1 reserved)
+  int ei;            // index of the ensemble (its carrier pointer: Ctx::uptr[ei])
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
   int wz, tm;        // tile shapes: z-transform columns, tridiagonal modes per block
@@ -50,7 +51,7 @@ struct Ens {
   unsigned seed;                            // SSM random numbers
   double sdq0, smu0, ssig0, sgam0, scsat, sd0, sun0;  // SSM reference impact
   double pe;                                // (1 + e)^(2/5)
-  const double* U;   // carrier velocity nodes [3][ny+1][nz][nx]
+  const double* U;   // carrier velocity nodes [3][ny+1][nz][nx] at tf_init (kernels read Ctx::uptr)
   FftPlan fx, fz;
 };
 
@@ -107,6 +108,7 @@ struct Ctx {
   int* rs_new;               // [n_rows+1]   slot range of each row after this step's sort
   int* far;                  // [n_tot]    slots of particles whose row moved by 2+ in j or k
   int* far_n;                // [2]        [0]: entries (the push appends; reset before the next push)
+  const double** uptr;       // [n_ens]    carrier field of each ensemble (replaced by tf_set_carrier in stream order)
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
   double* phi;               // [c_tot]   potential of the latest step

@@ -240,7 +240,11 @@ class TriboSim:
             raise ValueError("carrier field has the wrong size")
         self._sync_in()
         _check(self.L.tf_set_carrier(self.h, e, u.data_ptr()))
-        self.U[e] = u  # borrowed by the library: keep it alive
+        # borrowed by the library: keep the new field alive, and the old one
+        # until the steps already queued on the library's stream have read it
+        if self.U[e] is not u and self.U[e].device.type == "cuda":
+            self.U[e].record_stream(self.stream)
+        self.U[e] = u
 
     def poisson(self, e: int, q_fixed) -> "object":
         E = self.ens[e].mesh

@@ -125,12 +125,13 @@ def test_multi_step_parity():
     sim.close()
 
 
-def test_carrier_replacement():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_carrier_replacement(graphs):
     """tf_set_carrier: steps after a new carrier field follow the oracle with
-    that field; the field is copied, so the caller's buffer may change."""
-    say("carrier replacement")
+    that field (also when the steps replay captured graphs)."""
+    say("carrier replacement", graphs)
     ens = ens_small(n=3000, v_jitter=2.0, precharge=0.2, c_el=5.0)
-    sim = sim_of(ens)
+    sim = sim_of(ens, graphs=graphs)
     sim.step(2)
     mid = sim.state_np(0)
     rng = np.random.default_rng(7)
@@ -391,3 +392,23 @@ def test_ssm_deterministic_limit_equals_condenser():
     assert res[0][1]["impacts"].sum() > 40
     np.testing.assert_array_equal(res[0][1]["impacts"], res[1][1]["impacts"])
     np.testing.assert_allclose(res[1][0]["q"], res[0][0]["q"], rtol=1e-12, atol=1e-15)
+
+
+def test_carrier_every_step_with_graphs():
+    """A carrier field that changes every step (alternating two fields), graph
+    replays, against the oracle."""
+    ens = ens_small(n=2000, v_jitter=2.0)
+    rng = np.random.default_rng(3)
+    U2 = ens.U * 0.8 + 0.2 * rng.standard_normal(ens.U.shape)
+    sim = sim_of(ens, graphs=True)
+    g = O.Geo.from_mesh(ens.mesh)
+    s = O.state_of(ens)
+    for n in range(6):
+        U = ens.U if n % 2 == 0 else U2
+        sim.set_carrier(0, U)
+        sim.step(1)
+        s = O.step(g, U, s, ens.params, None)
+    gpu = sim.state_np(0)
+    sim.close()
+    err = state_errors(gpu, s, ens.mesh)
+    assert max(err.values()) < 1e-10
