@@ -67,9 +67,9 @@ struct Sizes {
   int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
-  std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk;
-  int plane_max = 0;
-  bool plane_any = false, split_any = false;
+  std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk, ph_blk;
+  int plane_max = 0, half_lds = 0;
+  bool plane_any = false, half_any = false, split_any = false;
   bool pp_any = false;  // some ensemble has 4-way coupling on
   std::vector<int> e_plane;
   std::map<int, int> tw_off;
@@ -80,6 +80,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   S->fp_blk.assign(n_ens + 1, 0);
   S->fz_blk.assign(n_ens + 1, 0);
   S->pl_blk.assign(n_ens + 1, 0);
+  S->ph_blk.assign(n_ens + 1, 0);
   S->tri_blk.assign(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
@@ -135,6 +136,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   // lane R = ceil(ny / G) <= 16 (one launch uses the largest R)
   S->e_wz.assign(n_ens, 2);
   S->e_tm.assign(n_ens, 1);
+  S->e_plane.assign(n_ens, 0);
+  std::vector<int> want_plane(n_ens, 0);
   S->wz = 1;
   S->tri_rows = 1;
   for (int e = 0; e < n_ens; ++e) {
@@ -144,7 +147,9 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     if (it != g_class_tune.end()) {
       if (it->second.fz_cols > 0) t.fz_cols = it->second.fz_cols;
       if (it->second.tri_modes > 0) t.tri_modes = it->second.tri_modes;
+      if (it->second.inv_plane > 0) t.inv_plane = it->second.inv_plane;
     }
+    want_plane[e] = t.inv_plane;
     const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
     // default: the fewest lanes (at least 8) that keep R <= 8
     int lanes = 8;
@@ -170,22 +175,55 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->fp_blk[e + 1] = S->fp_blk[e] + (rows / 2 + 3) / 4;  // row pairs, 4 per block
     S->fz_blk[e + 1] = S->fz_blk[e] + E.ny * ((nh + S->e_wz[e] - 1) / S->e_wz[e]);
     S->tri_blk[e + 1] = S->tri_blk[e] + (((nh + 7) & ~7) * E.nz + S->e_tm[e] - 1) / S->e_tm[e];
-    S->pl_blk[e + 1] = S->pl_blk[e] + E.ny;
   }
-  // fused inverse transforms for the ensembles whose plane (half spectrum and
-  // twiddles) fits one block's LDS
-  S->e_plane.assign(n_ens, 0);
+  // inverse transforms: per y plane in one block when the plane's half
+  // spectrum and twiddles fit its LDS, in two blocks (z-row parity) when half
+  // of it does.  By default the two-block form when an ensemble's 2 ny blocks
+  // do not outnumber the CUs (it then keeps twice as many CUs busy at the cost
+  // of a second read of each plane), else one block, else the z and x kernels.
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
-    const int pts = E.nz * (E.nx / 2 + 1);
-    S->e_plane[e] = pts <= kPlanePts && (size_t)(S->nx_max + S->nz_max + pts) * 16 <= (size_t)kLdsMax;
-    if (S->e_plane[e]) {
+    const int nh = E.nx / 2 + 1, pts = E.nz * nh, hpts = (E.nz / 2) * nh;
+    const bool whole_ok = pts <= kPlanePts && (size_t)(S->nx_max + S->nz_max + pts) * 16 <= (size_t)kLdsMax;
+    const size_t hlds = (size_t)(E.nx + E.nz / 2 + hpts) * 16;
+    FftPlan P;
+    const bool half_ok = E.nz % 4 == 0 && hpts <= kHalfPts && (E.nz / 4) * E.nx <= kHalfXPts &&
+                         hlds <= (size_t)kLdsMax && radix_plan(E.nz / 2, &P);
+    int m;
+    switch (want_plane[e]) {
+      case 1: m = 1; if (!whole_ok) return fail(TF_ESIZE, "inv_plane 1: the plane exceeds a block's LDS"); break;
+      case 2: m = 2; if (!half_ok) return fail(TF_ESIZE, "inv_plane 2: needs nz % 4 == 0 and half a plane within a block"); break;
+      case 3: m = 0; break;
+      default: m = (half_ok && 2 * E.ny <= cus) ? 2 : whole_ok ? 1 : 0; break;
+    }
+    S->e_plane[e] = m;
+    S->pl_blk[e + 1] = S->pl_blk[e] + (m == 1 ? E.ny : 0);
+    S->ph_blk[e + 1] = S->ph_blk[e] + (m == 2 ? 2 * E.ny : 0);
+    if (m == 1) {
       S->plane_any = true;
       S->plane_max = std::max(S->plane_max, pts);
+    } else if (m == 2) {
+      S->half_any = true;
     } else {
       S->split_any = true;
     }
   }
+  // one LDS size for the half-plane launch: the largest pieces over its ensembles
+  int hx = 0, hz = 0, hp = 0;
+  for (int e = 0; e < n_ens; ++e)
+    if (S->e_plane[e] == 2) {
+      hx = std::max(hx, ens[e].nx);
+      hz = std::max(hz, ens[e].nz / 2);
+      hp = std::max(hp, (ens[e].nz / 2) * (ens[e].nx / 2 + 1));
+    }
+  S->half_lds = (hx + hz + hp) * 16;
+  if ((size_t)S->half_lds > (size_t)kLdsMax) return fail(TF_ESIZE, "half-plane tiles exceed the LDS of a block");
   return TF_OK;
 }
 
@@ -217,6 +255,7 @@ struct tf_handle {
   int* d_fz = nullptr;
   int* d_tri = nullptr;
   int* d_pl = nullptr;
+  int* d_ph = nullptr;
   // recorded trajectory
   int traj_cap = 0, traj_len = 0;
   std::vector<TrajBuf> traj;        // traj_cap + 1 states (perm/phi used for the first traj_cap)
@@ -251,6 +290,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   int* fz = cv.take<int>(n_ens + 1);
   int* tri = cv.take<int>(n_ens + 1);
   int* pl = cv.take<int>(n_ens + 1);
+  int* ph = cv.take<int>(n_ens + 1);
   C.yf = cv.take<double>(S.y_tot);
   C.dy = cv.take<double>(S.y_tot);
   C.idy = cv.take<double>(S.y_tot);
@@ -319,6 +359,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     h->d_fz = fz;
     h->d_tri = tri;
     h->d_pl = pl;
+    h->d_ph = ph;
     h->d_ens = (Ens*)C.ens;
     h->traj = traj;
     h->traj_cap = traj_steps;
@@ -416,7 +457,7 @@ int tf_set_tuning(const tf_tuning* t) {
     return TF_OK;
   }
   if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 32)
+      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 3)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
   return TF_OK;
@@ -429,7 +470,8 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     g_class_tune.erase(key);
     return TF_OK;
   }
-  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 32)
+  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 32 || t->inv_plane < 0 ||
+      t->inv_plane > 3)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -549,6 +591,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.fx.tw_off = S.tw_off.at(T.nx);
     radix_plan(T.nz, &E.fz);
     E.fz.tw_off = S.tw_off.at(T.nz);
+    E.fzh = FftPlan{};
+    if (E.plane == 2) radix_plan(T.nz / 2, &E.fzh);  // twiddles: every other one of length nz
     const int ny = T.ny;
     double* Y = &yf[y_off];
     for (int j = 0; j <= ny; ++j) Y[j] = T.y_faces[j];
@@ -614,6 +658,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->d_fz, S.fz_blk);
   UP(h->d_tri, S.tri_blk);
   UP(h->d_pl, S.pl_blk);
+  UP(h->d_ph, S.ph_blk);
   UP(h->C.yf, yf);
   UP(h->C.dy, dy);
   UP(h->C.idy, idy);
@@ -666,7 +711,11 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.d_tri_blk = h->d_tri;
   h->G.pl_blk = h->S.pl_blk.data();
   h->G.d_pl_blk = h->d_pl;
+  h->G.ph_blk = h->S.ph_blk.data();
+  h->G.d_ph_blk = h->d_ph;
   h->G.plane_any = S.plane_any ? 1 : 0;
+  h->G.half_any = S.half_any ? 1 : 0;
+  h->G.half_lds = S.half_lds;
   h->G.pp_any = S.pp_any ? 1 : 0;
   h->G.split_any = S.split_any ? 1 : 0;
   h->G.plane_max = S.plane_max;

@@ -17,6 +17,8 @@
 // push gathers velocity, diameter and id through perm (nearly coalesced) and
 // writes in the new order.  Device-scope atomics are kept out of contended
 // addresses: they are resolved beyond the per-XCD L2 and serialize there.
+#include <type_traits>
+
 #include "tribo_dev.h"
 #include "particle.h"
 
@@ -1150,9 +1152,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_ifftx(Ctx C, Ens Eone, int one,
 // The transforms run in place: every Stockham pass loads its butterflies'
 // inputs into registers, synchronises the block, then writes the outputs.
 // ---------------------------------------------------------------------------
-template <int R, bool INV, int NT, int MAXPTS>
+// element i of line l at a[l * ls + i * es]
+struct LineLd {
+  const double2* a;
+  int ls, es;
+  __device__ double2 operator()(int l, int i) const { return a[l * ls + i * es]; }
+};
+
+template <int R, bool INV, int NT, int MAXPTS, class Ld>
 __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, int ls, int es, int n, int Ns,
-                                        const double2* __restrict__ tw, int tid) {
+                                        const double2* __restrict__ tw, int tid, Ld ld) {
   constexpr int UM = (MAXPTS / R + NT - 1) / NT;
   const int nb = n / R, stride = n / (Ns * R), total = lines * nb;
   const int sin_ = nb * es, sout = Ns * es;  // element steps of a butterfly's inputs and outputs
@@ -1162,9 +1171,14 @@ __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, 
     const int t = tid + u * NT;
     if (t < total) {
       const int jj = fdiv32(t, mlines, lines), line = t - jj * lines;
-      const double2* s = a + line * ls + jj * es;
+      if constexpr (std::is_same<Ld, LineLd>::value) {
+        const double2* s = a + line * ls + jj * es;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = s[r * sin_];
+        for (int r = 0; r < R; ++r) v[u][r] = s[r * sin_];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = ld(line, jj + r * nb);
+      }
     }
   }
   __syncthreads();
@@ -1203,24 +1217,48 @@ __device__ __forceinline__ void ip_pass(double2* a, int lines, unsigned mlines, 
   __syncthreads();
 }
 
+// passes ps0, ps0 + 1, ... of the plan (Ns: product of the earlier radices)
+template <bool INV, int NT, int MAXPTS>
+__device__ void ip_fft_from(double2* a, int lines, int ls, int es, const FftPlan& P, const double2* tw, int tid,
+                            int ps0, int Ns) {
+  const unsigned ml = magic32(lines);
+  const LineLd at{a, ls, es};
+  for (int ps = ps0; ps < P.np_ip; ++ps) {
+    const int R = (int)((P.rc_ip >> (4 * ps)) & 15u) + 1;
+    switch (R) {
+      case 2: ip_pass<2, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+      case 3: ip_pass<3, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+      case 4: ip_pass<4, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+      case 5: ip_pass<5, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+      case 8: ip_pass<8, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+      default: ip_pass<16, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid, at); break;
+    }
+    Ns *= R;
+  }
+}
+
 // `lines` transforms of P.n points, element i of line l at a[l * ls + i * es];
 // plan P.rc_ip: radices 2, 3, 4, 5, 8, 16 (radix - 1 in four bits a pass)
 template <bool INV, int NT, int MAXPTS>
 __device__ void ip_fft(double2* a, int lines, int ls, int es, const FftPlan& P, const double2* tw, int tid) {
+  ip_fft_from<INV, NT, MAXPTS>(a, lines, ls, es, P, tw, tid, 0, 1);
+}
+
+// the same, the first pass taking its inputs from ld(l, i) (element i of line l)
+template <bool INV, int NT, int MAXPTS, class Ld>
+__device__ void ip_fft(double2* a, int lines, int ls, int es, const FftPlan& P, const double2* tw, int tid, Ld ld) {
+  if (P.np_ip < 1) return;
   const unsigned ml = magic32(lines);
-  int Ns = 1;
-  for (int ps = 0; ps < P.np_ip; ++ps) {
-    const int R = (int)((P.rc_ip >> (4 * ps)) & 15u) + 1;
-    switch (R) {
-      case 2: ip_pass<2, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 3: ip_pass<3, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 4: ip_pass<4, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 5: ip_pass<5, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      case 8: ip_pass<8, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-      default: ip_pass<16, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, Ns, tw, tid); break;
-    }
-    Ns *= R;
+  const int R = (int)(P.rc_ip & 15u) + 1;
+  switch (R) {
+    case 2: ip_pass<2, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
+    case 3: ip_pass<3, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
+    case 4: ip_pass<4, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
+    case 5: ip_pass<5, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
+    case 8: ip_pass<8, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
+    default: ip_pass<16, INV, NT, MAXPTS>(a, lines, ml, ls, es, P.n, 1, tw, tid, ld); break;
   }
+  ip_fft_from<INV, NT, MAXPTS>(a, lines, ls, es, P, tw, tid, 1, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1290,7 +1328,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
   Ens E;
   int j;
   block_ens(C, Eone, one, blk_off, blk0, E, j);
-  if (!E.plane) return;  // transformed by the z and x kernels
+  if (E.plane != 1) return;  // split over two blocks, or the z and x kernels
   const int nx = E.nx, nz = E.nz, nh = E.nh, half = nx >> 1, tid = threadIdx.x;
   double2* twz = lds;
   double2* twx = twz + nz;
@@ -1313,36 +1351,19 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
   __syncthreads();
   // inverse z transform of the nh columns
   ip_fft<true, kPlaneThreads, kPlanePts>(pl, nh, 1, nh, E.fz, twz, tid);
-  // rows (2p, 2p+1) as one complex line: Z = X_A + i X_B (Hermitian halves
-  // extended; imaginary parts at m = 0 and nx/2 dropped), written over the pair
-  constexpr int UZ = (kPlanePts + kPlaneThreads - 1) / kPlaneThreads;
+  // inverse x transforms of the rows paired as complex lines (pitch 2 nh >= nx):
+  // the first pass reads Z = X_A + i X_B of rows (2p, 2p+1) (Hermitian halves
+  // extended; imaginary parts at m = 0 and nx/2 dropped) straight from them
   const int npt = (nz >> 1) * nx;
   const unsigned mnx = magic32(nx);
-  double2 z[UZ];
-#pragma unroll
-  for (int u = 0; u < UZ; ++u) {
-    const int t = tid + u * kPlaneThreads;
-    if (t < npt) {
-      const int p = fdiv32(t, mnx, nx), i = t - p * nx;
-      const int m = i <= half ? i : nx - i;
-      const double2 A = pl[(2 * p) * nh + m], B = pl[(2 * p + 1) * nh + m];
-      if (i == 0 || i == half) z[u] = make_double2(A.x, B.x);
-      else if (i < half) z[u] = make_double2(A.x - B.y, A.y + B.x);
-      else z[u] = make_double2(A.x + B.y, B.x - A.y);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < UZ; ++u) {
-    const int t = tid + u * kPlaneThreads;
-    if (t < npt) {
-      const int p = fdiv32(t, mnx, nx), i = t - p * nx;
-      pl[(2 * p) * nh + i] = z[u];
-    }
-  }
-  __syncthreads();
-  // inverse x transform of the nz / 2 packed lines (pitch 2 nh >= nx)
-  ip_fft<true, kPlaneThreads, kPlanePts>(pl, nz >> 1, 2 * nh, 1, E.fx, twx, tid);
+  auto packed = [=](int p, int i) {
+    const int m = i <= half ? i : nx - i;
+    const double2 A = pl[(2 * p) * nh + m], B = pl[(2 * p + 1) * nh + m];
+    if (i == 0 || i == half) return make_double2(A.x, B.x);
+    if (i < half) return make_double2(A.x - B.y, A.y + B.x);
+    return make_double2(A.x + B.y, B.x - A.y);
+  };
+  ip_fft<true, kPlaneThreads, kPlanePts>(pl, nz >> 1, 2 * nh, 1, E.fx, twx, tid, packed);
   const double sc = (1.0 / (double)nz) * (1.0 / (double)nx);
   double* out = phi_out + (E.c_off - phi_shift) + (long long)j * nz * nx;
   for (int t = tid; t < npt; t += kPlaneThreads) {
@@ -1350,6 +1371,97 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
     const double2 v = pl[(2 * p) * nh + i];
     out[(2 * p) * nx + i] = v.x * sc;
     out[(2 * p + 1) * nx + i] = v.y * sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse z and x transforms of one y plane split over two blocks by the
+// parity h of the z row.  With N = nz (a multiple of 4), the rows k = 2r + h
+// of the inverse z transform are the inverse transform of length N/2 of
+//   X[m] + X[m + N/2]                        (h = 0)
+//   (X[m] - X[m + N/2]) exp(2 pi i m / N)     (h = 1),   m < N/2
+// (the radix-2 split of the outputs), so a block holds half the plane in LDS
+// and does half the transforms: twice the blocks, each with 16 waves (at
+// most 128 VGPRs).  Rows 4p + h and 4p + 2 + h then form one complex line of
+// the x transform.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kHalfThreads, 4) void k_plane_half(Ctx C, Ens Eone, int one,
+                                                             const int* __restrict__ blk_off, int blk0,
+                                                             double* __restrict__ phi_out, long long phi_shift,
+                                                             int* __restrict__ far_reset, int bump) {
+  if (far_reset && blockIdx.x == 0) {
+    if (threadIdx.x == 0) *far_reset = 0;
+    if (bump)
+      for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
+  }
+  extern __shared__ double2 lds[];
+  // the two halves of a plane are neighbouring logical blocks: same XCD, so
+  // the second read of the plane's spectrum finds it in that XCD's L2
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+  Ens E;
+  int lb;
+  if (one) {
+    E = Eone;
+    lb = b;
+  } else {
+    const int gb = blk0 + b;
+    const int e = find_off_i(blk_off, C.n_ens + 1, gb);
+    E = C.ens[e];
+    lb = gb - blk_off[e];
+  }
+  if (E.plane != 2) return;
+  const int j = lb >> 1, h = lb & 1;
+  const int nx = E.nx, nz = E.nz, nh = E.nh, nzh = nz >> 1, nzq = nz >> 2, half = nx >> 1, tid = threadIdx.x;
+  double2* twz = lds;      // exp(-2 pi i t / (N/2)) = exp(-2 pi i 2t / N)
+  double2* twx = twz + nzh;
+  double2* pl = twx + nx;  // [nz/2][nh]
+  const double2 tzv = C.tw[E.fz.tw_off + min(2 * tid, nz - 2)];
+  const double2 txv = C.tw[E.fx.tw_off + min(tid, nx - 1)];
+  const double2* sp = C.spec + E.s_off + (long long)j * nz * E.nhp;
+  const double2* twn = C.tw + E.fz.tw_off;
+  const long long shift = (long long)nzh * E.nhp;
+  const unsigned mnh = magic32(nh);
+  struct Fold {
+    double2 a, b, w;
+  };
+  staged_copy<4>(
+      nzh * nh, tid, kHalfThreads,
+      [&](int t) {
+        const int m = fdiv32(t, mnh, nh), i = t - m * nh;
+        const double2* s = sp + m * E.nhp + i;
+        return Fold{s[0], s[shift], h ? twn[m] : make_double2(1.0, 0.0)};
+      },
+      [&](int t, Fold v) {
+        if (h == 0) {
+          pl[t] = make_double2(v.a.x + v.b.x, v.a.y + v.b.y);
+        } else {  // (a - b) conj(w), w = exp(-2 pi i m / N)
+          const double dx = v.a.x - v.b.x, dy = v.a.y - v.b.y;
+          pl[t] = make_double2(dx * v.w.x + dy * v.w.y, dy * v.w.x - dx * v.w.y);
+        }
+      });
+  if (tid < nzh) twz[tid] = tzv;
+  if (tid < nx) twx[tid] = txv;
+  __syncthreads();
+  ip_fft<true, kHalfThreads, kHalfPts>(pl, nh, 1, nh, E.fzh, twz, tid);
+  // x transforms of LDS rows (2p, 2p+1) -- z rows 4p + h, 4p + 2 + h -- paired
+  // as one complex line, packed by the first pass as in k_plane_inv
+  const int npt = nzq * nx;
+  const unsigned mnx = magic32(nx);
+  auto packed = [=](int p, int i) {
+    const int m = i <= half ? i : nx - i;
+    const double2 A = pl[(2 * p) * nh + m], B = pl[(2 * p + 1) * nh + m];
+    if (i == 0 || i == half) return make_double2(A.x, B.x);
+    if (i < half) return make_double2(A.x - B.y, A.y + B.x);
+    return make_double2(A.x + B.y, B.x - A.y);
+  };
+  ip_fft<true, kHalfThreads, kHalfXPts>(pl, nzq, 2 * nh, 1, E.fx, twx, tid, packed);
+  const double sc = (1.0 / (double)nz) * (1.0 / (double)nx);
+  double* out = phi_out + (E.c_off - phi_shift) + (long long)j * nz * nx;
+  for (int t = tid; t < npt; t += kHalfThreads) {
+    const int p = fdiv32(t, mnx, nx), i = t - p * nx;
+    const double2 v = pl[(2 * p) * nh + i];
+    out[(4 * p + h) * nx + i] = v.x * sc;
+    out[(4 * p + 2 + h) * nx + i] = v.y * sc;
   }
 }
 
@@ -1755,22 +1867,34 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
     }
   }
   mark(2);
-  // inverse transforms: one block per y plane for the ensembles whose plane
-  // fits the LDS (counted as the z phase), z then x kernels for the others;
-  // the blocks of the other kind exit at once
-  const bool fused = one ? Eone.plane != 0 : G.plane_any != 0;
+  // inverse transforms (counted as the z phase): one block per y plane, or
+  // two per plane (z-row parity), for the ensembles whose plane fits the LDS;
+  // z then x kernels for the others.  The first of these kernels empties the
+  // far list and counts the step.
+  const bool whole = one ? Eone.plane == 1 : G.plane_any != 0;
+  const bool halves = one ? Eone.plane == 2 : G.half_any != 0;
   const bool split = one ? Eone.plane == 0 : G.split_any != 0;
-  if (fused) {
+  int* fr = far_reset;
+  if (whole) {
     const int p0 = G.pl_blk[e0], np = G.pl_blk[e1] - p0;
     const size_t lp = (size_t)(G.nx_max + G.nz_max + G.plane_max) * sizeof(double2);
-    if (np > 0)
-      k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, far_reset, 1);
+    if (np > 0) {
+      k_plane_inv<<<np, kPlaneThreads, lp, st>>>(C, Eone, one, G.d_pl_blk, p0, phi_out, phi_shift, fr, 1);
+      fr = nullptr;
+    }
+  }
+  if (halves) {
+    const int p0 = G.ph_blk[e0], np = G.ph_blk[e1] - p0;
+    const size_t lp = (size_t)G.half_lds;
+    if (np > 0) {
+      k_plane_half<<<np, kHalfThreads, lp, st>>>(C, Eone, one, G.d_ph_blk, p0, phi_out, phi_shift, fr, 1);
+      fr = nullptr;
+    }
   }
   if (split && nzb > 0) k_z<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.nz_max);
   mark(3);
   if (split && nb > 0)
-    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, far_reset,
-                                         fused ? 0 : 1);
+    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, fr, 1);
   mark(4);
   return hipGetLastError();
 }

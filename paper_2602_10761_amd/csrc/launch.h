@@ -27,16 +27,20 @@ struct LaunchGeo {
   int tri_rows;    // rows per lane of the tridiagonal scans (largest over the ensembles)
   int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
   int pp_any;      // some ensemble has 4-way coupling on
-  int plane_any, split_any;  // some ensembles with / without fused inverse transforms
-  int plane_max;   // largest nz (nx/2 + 1) over the fused ensembles
+  int plane_any, half_any, split_any;  // some ensembles with inverse transforms per plane /
+                                       // per half plane / by the z and x kernels
+  int plane_max;   // largest nz (nx/2 + 1) over the ensembles transformed per plane
+  int half_lds;    // LDS bytes of the half-plane kernel
   const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block
   const int* fz_blk;
   const int* tri_blk;
   const int* d_fp_blk;
   const int* d_fz_blk;
   const int* d_tri_blk;
-  const int* pl_blk;  // fused inverse transforms: one block per y plane
+  const int* pl_blk;  // inverse transforms per plane: one block per y plane
   const int* d_pl_blk;
+  const int* ph_blk;  // per half plane: two blocks per y plane
+  const int* d_ph_blk;
   const Ens* eh;   // host copies of the ensemble descriptors
 };
 

@@ -37,7 +37,8 @@ struct Ens {
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
   int wz, tm;        // tile shapes: z-transform columns, tridiagonal modes per block
-  int plane;         // inverse transforms fused per y plane (the plane fits the LDS)
+  int plane;         // inverse transforms: 1 one block per y plane, 2 two blocks per plane
+                     // (z-row parity), 0 z then x kernels
   double lx, ly, lz, dx, dz;
   double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
   // derived on the host
@@ -53,6 +54,7 @@ struct Ens {
   double pe;                                // (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx] at tf_init (kernels read Ctx::uptr)
   FftPlan fx, fz;
+  FftPlan fzh;       // length nz/2 (plane split over two blocks)
 };
 
 // statistics block (int64) of one ensemble; the per-height sums live per (j,k)
@@ -73,6 +75,11 @@ constexpr int kLdsMax = 163840;
 // fused inverse transforms of a y plane: threads per block, largest nz (nx/2 + 1)
 constexpr int kPlaneThreads = 768;
 constexpr int kPlanePts = 10240;
+// inverse transforms of a y plane split over two blocks: threads per block,
+// largest (nz/2) (nx/2 + 1) (z transforms) and (nz/4) nx (x transforms)
+constexpr int kHalfThreads = 1024;
+constexpr int kHalfPts = 4736;
+constexpr int kHalfXPts = 4096;
 // z transforms: largest tile of wz columns times nz points
 constexpr int kZPts = 2048;
 

@@ -49,7 +49,7 @@ class TfParticles(Structure):
 
 
 class TfTuning(Structure):
-    _fields_ = [("sort_cap", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("reserved", c_int32)]
+    _fields_ = [("sort_cap", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("inv_plane", c_int32)]
 
 
 class TfStatsOut(Structure):
@@ -101,15 +101,15 @@ class TriboError(RuntimeError):
     pass
 
 
-def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0):
+def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0):
     """Tile shapes for every later TriboSim of this process (0 = built-in choice)."""
-    t = TfTuning(sort_cap, fz_cols, tri_modes, 0)
+    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane)
     _check(lib().tf_set_tuning(ctypes.byref(t)))
 
 
-def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0):
+def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0):
     """Tile shapes for ensembles of mesh size (nx, ny, nz) in later TriboSims."""
-    t = TfTuning(0, fz_cols, tri_modes, 0)
+    t = TfTuning(0, fz_cols, tri_modes, inv_plane)
     _check(lib().tf_set_tuning_class(nx, ny, nz, ctypes.byref(t)))
 
 
@@ -170,7 +170,7 @@ class TriboSim:
         self.cfg = cfg
         nbytes = self.L.tf_workspace_size(cfg, self.n_ens, traj_steps)
         if nbytes == 0:
-            raise TriboError("invalid configuration (tf_workspace_size returned 0)")
+            raise TriboError("invalid configuration: " + self.L.tf_last_error().decode())
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.dev)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255

@@ -69,6 +69,45 @@ def test_poisson_parity(shape, stretch):
     sim.close()
 
 
+@pytest.mark.parametrize("shape", [(8, 6, 12), (24, 20, 40), (32, 32, 32), (128, 128, 128), (4, 2, 4)])
+def test_poisson_inverse_layouts(shape):
+    """The three layouts of the inverse transforms (one block per y plane, two
+    blocks per plane by z-row parity, z then x kernels) against the oracle."""
+    from paper_2602_10761_amd import runtime as R
+    nx, ny, nz = shape
+    ens = W.make_ensemble(W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=10, stretch=2.0, n_modes=4))
+    g = O.Geo.from_mesh(ens.mesh)
+    rng = np.random.default_rng(nz * 3 + ny)
+    Q = rng.integers(-(1 << 50), 1 << 50, g.ncell).astype(np.int64)
+    ref = O.poisson(g, Q)
+    phis = {}
+    try:
+        for mode in (1, 2, 3):
+            say("poisson layout", shape, mode)
+            R.set_tuning(inv_plane=mode)
+            sim = sim_of(ens)
+            phis[mode] = sim.poisson(0, Q).cpu().numpy().reshape(ny, nz, nx)
+            sim.close()
+    finally:
+        R.set_tuning()
+    for mode, phi in phis.items():
+        err = np.abs(phi - ref).max() / np.abs(ref).max()
+        say("  layout", mode, "rel err", err)
+        assert err < TOL
+
+
+def test_inverse_layout_refused():
+    """Two blocks per plane need nz % 4 == 0."""
+    from paper_2602_10761_amd import runtime as R
+    ens = W.make_ensemble(W.CONFIGS[1].replace(nx=16, ny=8, nz=10, n_particles=10))
+    try:
+        R.set_tuning(inv_plane=2)
+        with pytest.raises(R.TriboError, match="nz % 4"):
+            sim_of(ens)
+    finally:
+        R.set_tuning()
+
+
 # ---------------------------------------------------------------------------
 # one step from the same initial state
 # ---------------------------------------------------------------------------
@@ -251,15 +290,25 @@ def test_batched_equals_plain():
              W.CONFIGS[1].replace(re_tau=2.0, nx=4, ny=4, nz=4, n_particles=600, precharge=0.3, v_jitter=1.0,
                                   d_choices=(0.5, 1.0), density_ratio=50.0, pp=1, k_pp=2.0)]
     ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
-    sim = sim_of(ens, graphs=True, source=True)
-    sim.step(9)
-    batched = [(sim.state_np(e), sim.stats(e), sim.field(e, 2).cpu().numpy()) for e in range(len(ens))]
-    sim.close()
+    from paper_2602_10761_amd import runtime as R
+    # the first one transformed per whole plane, the fifth by the z and x
+    # kernels, the others per half plane
+    R.set_tuning_class(16, 24, 32, inv_plane=1)
+    try:
+        sim = sim_of(ens, graphs=True, source=True)
+        sim.step(9)
+        batched = [(sim.state_np(e), sim.stats(e), sim.field(e, 2).cpu().numpy()) for e in range(len(ens))]
+        sim.close()
+        plain = []
+        for E in ens:
+            s1 = sim_of(E, source=True)
+            s1.step(9)
+            plain.append((s1.state_np(0), s1.stats(0), s1.field(0, 2).cpu().numpy()))
+            s1.close()
+    finally:
+        R.set_tuning_class(16, 24, 32)
     for e, E in enumerate(ens):
-        s1 = sim_of(E, source=True)
-        s1.step(9)
-        st, ss, fs = s1.state_np(0), s1.stats(0), s1.field(0, 2).cpu().numpy()
-        s1.close()
+        st, ss, fs = plain[e]
         np.testing.assert_array_equal(batched[e][2], fs)
         for k in KEYS:
             np.testing.assert_array_equal(batched[e][0][k], st[k])
