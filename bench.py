@@ -33,8 +33,9 @@ KERNEL_SOURCES = ["paper_2602_10761_amd/csrc/kernels.hip", "paper_2602_10761_amd
 
 
 def plane_fused(nx, nz):
-    """Whether the library runs both inverse transforms of a y plane in one block
-    (half spectrum of the plane and twiddles within 160 KiB, at most 10240 points)."""
+    """Whether the library runs both inverse transforms of a y plane without a
+    pass through memory in between (the plane's half spectrum and twiddles within
+    160 KiB, at most 10240 points: one block per plane, or two by z-row parity)."""
     pts = nz * (nx // 2 + 1)
     return pts <= 10240 and 16 * (nx + nz + pts) <= 163840
 
