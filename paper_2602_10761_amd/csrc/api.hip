@@ -311,6 +311,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.ps = cv.take<int>(S.rows / 2 + 1);
   C.rs_old = cv.take<int>(S.rows + 1);
   C.rs_new = cv.take<int>(S.rows + 1);
+  C.mv = cv.take<int>((size_t)(S.rows / 2) * kMoverCap);
+  C.mv_n = cv.take<int>(S.rows / 2);
   C.far = cv.take<int>(S.n_tot);
   C.far_n = cv.take<int>(2);
   C.uptr = cv.take<const double*>(n_ens);
@@ -679,6 +681,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowacc, 0, sizeof(longlong2) * S.rows, h->stream);
   if (he == hipSuccess && S.c_tot) he = hipMemsetAsync(h->C.count, 0, sizeof(int) * S.c_tot, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.pair_cnt, 0, sizeof(int) * (S.rows / 2), h->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(h->C.mv_n, 0, sizeof(int) * (S.rows / 2), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_old, 0, sizeof(int) * (S.rows + 1), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rs_new, 0, sizeof(int) * (S.rows + 1), h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.far_n, 0, sizeof(int) * 2, h->stream);

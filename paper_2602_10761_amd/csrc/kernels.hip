@@ -266,7 +266,10 @@ __global__ __launch_bounds__(kBlock) void k_rows_from_start(Ctx C) {
   const int e = find_off(C.r_off, C.n_ens + 1, r);
   const Ens& E = C.ens[e];
   C.rs_new[r] = C.start[E.c_off + (r - C.r_off[e]) * E.nx];
-  if ((r & 1) == 0) C.pair_cnt[r >> 1] = 0;
+  if ((r & 1) == 0) {
+    C.pair_cnt[r >> 1] = 0;
+    C.mv_n[r >> 1] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -607,64 +610,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_fftx(Ctx C, Ens Eone, int one, 
 // incremental sort fused with the deposit and the x transform, one wave per
 // row pair (j, k), (j, k+1) of the new order (2 nx consecutive cells).  The
 // state is stored in the previous sort's order, so the pair's members are
-// among the slots of rows (j + dj, k + dk), |dj| <= 1, dk in [-1, 2] (k
-// periodic) -- at most 6 contiguous slot ranges -- plus the far list.  The
-// push counted the members of every row pair (pair_cnt); their scan is ps.
+// the slots of the pair's own range in that order that stayed, plus the
+// pair's mover list and the far list, both written by the push.  The push
+// counted the members of every row pair (pair_cnt); their scan is ps.
 // ---------------------------------------------------------------------------
-struct RowSegs {
-  int a[6], off[7];  // segment u: slots [a[u], a[u] + off[u+1] - off[u])
-};
-
-// two segments per dj (the second one empty unless the k range wraps); all
-// indices static so that the segments stay in registers
-// (slot bounds clamped to [0, n_tot]: memory-safe even for inconsistent ranges)
-__device__ __forceinline__ void pair_segments(const int* __restrict__ rs, long long rb, int ny, int nz, int j,
-                                              int k, int n_tot, RowSegs& S) {
-  S.off[0] = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int j2 = j + d - 1;
-    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
-    if (j2 >= 0 && j2 < ny) {
-      const long long base = rb + (long long)j2 * nz;
-      long long s0, e0, s1 = 0, e1 = 0;  // rows [s0, e0) and [s1, e1)
-      if (k >= 1 && k + 2 <= nz - 1) {
-        s0 = base + k - 1;
-        e0 = base + k + 3;
-      } else if (k == 0) {
-        s0 = base;
-        e0 = base + 3;
-        s1 = base + nz - 1;
-        e1 = base + nz;
-      } else {  // k == nz - 2
-        s0 = base + nz - 3;
-        e0 = base + nz;
-        s1 = base;
-        e1 = base + 1;
-      }
-      a0 = min(max(rs[s0], 0), n_tot);
-      b0 = min(max(rs[e0], 0), n_tot);
-      if (e1 > s1) {
-        a1 = min(max(rs[s1], 0), n_tot);
-        b1 = min(max(rs[e1], 0), n_tot);
-      }
-    }
-    S.a[2 * d] = a0;
-    S.off[2 * d + 1] = S.off[2 * d] + max(b0 - a0, 0);
-    S.a[2 * d + 1] = a1;
-    S.off[2 * d + 2] = S.off[2 * d + 1] + max(b1 - a1, 0);
-  }
-}
-
-// slot of flattened candidate t < S.off[6]
-__device__ __forceinline__ int seg_slot(const RowSegs& S, int t) {
-  int s = S.a[0] + t;
-#pragma unroll
-  for (int u = 1; u < 6; ++u)
-    if (t >= S.off[u]) s = S.a[u] + (t - S.off[u]);
-  return s;
-}
-
 constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight together)
 
 // LDS of one wave: member list {id, old slot} (8 B), member index by cell
@@ -706,23 +655,28 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   const int j = jkA / nz, k = jkA - j * nz;
   const long long rA = E.row_off + jkA;
   const long long c0 = E.c_off + (long long)jkA * nx, c1 = c0 + n2;
-  RowSegs S;
-  int r0 = 0, rm = 0, r1 = 0, T = 0, TT = 0;
+  // candidates t: [0, T) own range from slot a0, [T, TB) mover list mvp,
+  // [TB, TT) far list
+  int a0 = 0, r0 = 0, rm = 0, r1 = 0, T = 0, TB = 0, TT = 0;
+  const int* mvp = C.mv + (rA >> 1) * (long long)kMoverCap;
   if (ok) {
-    pair_segments(C.rs_old, E.row_off, ny, nz, j, k, (int)C.n_tot, S);
+    // (slot bounds clamped to [0, n_tot]: memory-safe even for inconsistent ranges)
+    a0 = min(max(C.rs_old[rA], 0), (int)C.n_tot);
+    T = min(max(C.rs_old[rA + 2], a0), (int)C.n_tot) - a0;
+    TB = T + min(max(C.mv_n[rA >> 1], 0), kMoverCap);
     // the pair's slot range (clamped: writes stay inside the arrays whatever the counts)
     r0 = min(max(C.ps[rA >> 1], 0), (int)C.n_tot);
     r1 = min(max(C.ps[(rA >> 1) + 1], r0), (int)C.n_tot);
-    T = S.off[6];
-    TT = T + min(C.far_n[0], (int)C.n_tot);
+    TT = TB + min(C.far_n[0], (int)C.n_tot);
     for (int i = lane; i < n2; i += 64) {
       cnt[i] = 0;
       Q[i] = 0;
     }
     if (lane == 0) {
       *nmem = 0;
-      // consumed by the pair scan: restart the count for this step's push
+      // consumed by the pair scan and here: restart the counts for this step's push
       C.pair_cnt[rA >> 1] = 0;
+      C.mv_n[rA >> 1] = 0;
     }
   }
   const int M = r1 - r0;
@@ -740,13 +694,14 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
 #pragma unroll
     for (int u = 0; u < kCand; ++u) {
       const int t = t0 + 64 * u;
-      sl[u] = t < T ? seg_slot(S, t) : -1;
+      sl[u] = t < T ? a0 + t : -1;
     }
-    if (tb + 64 * kCand > T && TT > T) {  // the batch reaches the far list
+    if (tb + 64 * kCand > T && TT > T) {  // the batch reaches the mover or far list
 #pragma unroll
       for (int u = 0; u < kCand; ++u) {
         const int t = t0 + 64 * u;
-        if (t >= T && t < TT) sl[u] = C.far[t - T];
+        if (t >= T && t < TB) sl[u] = mvp[t - T];
+        else if (t >= TB && t < TT) sl[u] = C.far[t - TB];
       }
     }
 #pragma unroll
@@ -827,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
 #pragma unroll
       for (int u = 0; u < kCand; ++u) {
         const int t = t0 + 64 * u;
-        sl[u] = t < T ? seg_slot(S, t) : (t < TT ? C.far[t - T] : -1);
+        sl[u] = t < T ? a0 + t : t < TB ? mvp[t - T] : t < TT ? C.far[t - TB] : -1;
       }
 #pragma unroll
       for (int u = 0; u < kCand; ++u) c[u] = sl[u] >= 0 ? in.key[sl[u]] : -1;
@@ -1669,18 +1624,22 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   const int nj = y_cell_from(yf, ny, yr, j);
   const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
   out.key[s] = key;
-  // the next sort gathers row pair (nj, kb), (nj, kb + 1), kb = nk & ~1, from
-  // rows nj + [-1, 1] x kb + [-1, 2] (k periodic); a particle outside goes on
-  // the far list
-  const int kb = nk & ~1;
-  int dk = F.k - kb + 1;  // position of the old k in kb - 1 ... kb + 2 (mod nz)
-  if (dk < 0) dk += nz;
-  else if (dk >= nz) dk -= nz;
-  if (abs(nj - j) > 1 || dk > 3) {
-    const int f = atomicAdd(&C.far_n[0], 1);
-    if (f < C.n_tot) C.far[f] = s;
+  // the next sort takes a row pair's members from the pair's slot range of
+  // this order and from its mover list: a particle whose row pair changes
+  // goes on the mover list of its new pair (on the far list, read by every
+  // pair, when that one is full)
+  const int pnew = (int)((E.row_off + (long long)nj * nz + nk) >> 1);
+  const int pold = (int)((E.row_off + (long long)j * nz + F.k) >> 1);
+  if (pnew != pold) {
+    const int b = atomicAdd(&C.mv_n[pnew], 1);
+    if (b < kMoverCap) {
+      C.mv[(long long)pnew * kMoverCap + b] = s;
+    } else {
+      const int f = atomicAdd(&C.far_n[0], 1);
+      if (f < C.n_tot) C.far[f] = s;
+    }
   }
-  pair_count(C.pair_cnt, (int)((E.row_off + (long long)nj * nz + nk) >> 1));
+  pair_count(C.pair_cnt, pnew);
 }
 
 // four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat

@@ -9,6 +9,7 @@ namespace tf {
 constexpr int kMaxPass = 10;
 constexpr int kNbin = 64;
 constexpr int kBlock = 256;
+constexpr int kMoverCap = 32;  // mover list entries per row pair
 constexpr int kFixDep = 48;
 constexpr int kFixWall = 40;
 constexpr int kFixQcum = 32;
@@ -105,15 +106,17 @@ struct Ctx {
   double* sq;                // [n_tot]   charge of each new slot
   double *sx, *sy, *sz;      // [n_tot]   position of each new slot
   // incremental sort: the state is stored in the previous sort's order, so a
-  // (j, k) row's new members come from the 3 x 3 neighbouring rows of that
-  // order, except the particles listed in `far`
+  // row pair's new members are the ones of its own slot range that stayed
+  // plus the particles that moved in (mover list, far list)
   const long long* r_off;    // [n_ens+1] (j, k) row offsets
   long long n_rows;
   int* pair_cnt;             // [n_rows/2]   members of each row pair (rows 2p, 2p+1) after this step's sort
   int* ps;                   // [n_rows/2+1] slot range of each row pair after this step's sort
   int* rs_old;               // [n_rows+1]   slot range of each row in the stored order
   int* rs_new;               // [n_rows+1]   slot range of each row after this step's sort
-  int* far;                  // [n_tot]    slots of particles whose row moved by 2+ in j or k
+  int* mv;                   // [n_rows/2][kMoverCap] slots of the particles that moved into each row pair
+  int* mv_n;                 // [n_rows/2] entries (the push appends; the sort reads and resets)
+  int* far;                  // [n_tot]    movers beyond a full mover list
   int* far_n;                // [2]        [0]: entries (the push appends; reset before the next push)
   const double** uptr;       // [n_ens]    carrier field of each ensemble (replaced by tf_set_carrier in stream order)
   int* scan_part;            // scan block partials

@@ -164,6 +164,26 @@ def test_multi_step_parity():
     sim.close()
 
 
+@pytest.mark.parametrize("ny", [128, 300])
+def test_many_row_pairs_multi_step(ny):
+    """Incremental sorts on meshes with many row pairs (16384 and 38400: the
+    pair scan over more than one block's chunk) against the oracle over
+    several steps."""
+    say("many row pairs", ny)
+    ens = ens_small(nx=4, ny=ny, nz=256, n=20000, v_jitter=3.0, precharge=0.2, re_tau=40.0, c_el=5.0)
+    n = 4
+    sim = sim_of(ens)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    sim.close()
+    ref, st = oracle_run(ens, n)
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  impacts", st.impacts, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert_stats_equal(gst, st)
+    assert max(err.values()) < 1e-10
+
+
 @pytest.mark.parametrize("graphs", [False, True])
 def test_carrier_replacement(graphs):
     """tf_set_carrier: steps after a new carrier field follow the oracle with
