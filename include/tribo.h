@@ -257,9 +257,9 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  * Tile shapes of the sort and Poisson kernels, used by every later tf_init /
  * tf_workspace_size of the calling process (0 = built-in choice):
  *   sort_cap   members per row pair held in LDS by the fused sort (pairs with
- *              more take a second pass through global memory); 0 = about 2.5
- *              times the mean pair, -1 = none (always two passes), else
- *              1..4096 (clamped to what fits 64 KiB of LDS per block)
+ *              more take a second pass through global memory); 0 = twice
+ *              the mean pair rounded up to 64, -1 = none (always two passes),
+ *              else 1..4096 (clamped to what fits 64 KiB of LDS per block)
  *   fz_cols    spectral columns per block of the z transforms (1..64, and
  *              fz_cols nz <= 2048)
  *   tri_modes  Fourier modes per block of the tridiagonal solves: 4, 8, 16

@@ -1756,26 +1756,19 @@ hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool
 }
 
 int sortdep_cap(const Ctx& C, int nx_max, int want) {
-  // member list per row pair.  Default: at least the mean pair size and what
-  // the FFT buffer it shares leaves free, then as large as possible without
-  // lowering the number of blocks that fit in a CU's 160 KiB of LDS (pairs
-  // above the capacity take the two-pass path).  Always within 64 KiB per block.
+  // member list per row pair (pairs above the capacity take the two-pass
+  // path).  Default: twice the mean pair size rounded up to 64 (pair sizes
+  // follow the cell volumes, which vary across the stretched y rows), at
+  // least what the FFT buffer it shares leaves free.  Always within 64 KiB
+  // per block.
   if (want < 0) return 0;
-  auto block_bytes = [&](long long cap) {
-    return 16LL * nx_max + kPairsPerBlock * (long long)sortdep_wave_bytes(nx_max, (int)cap);
-  };
   const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
   long long cap;
   if (want > 0) {
     cap = want;
   } else {
     const long long mean = C.n_rows > 0 ? (2 * C.n_tot + C.n_rows - 1) / C.n_rows : 0;
-    cap = std::min(std::max<long long>((16LL * nx_max) / 12, ((mean + 63) / 64) * 64), lim);
-    const long long per_cu = 163840 / std::max<long long>(block_bytes(cap), 1);
-    if (per_cu > 0) {
-      const long long grow = ((163840 / per_cu - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
-      cap = std::max(cap, grow);
-    }
+    cap = std::max<long long>((16LL * nx_max) / 12, ((2 * mean + 63) / 64) * 64);
   }
   cap = std::min(cap, lim);
   return (int)std::max<long long>(cap, 0) & ~7;

@@ -184,6 +184,34 @@ def test_many_row_pairs_multi_step(ny):
     assert max(err.values()) < 1e-10
 
 
+def test_sort_capacity_paths():
+    """The fused sort's two paths (member list in LDS, or a second candidate
+    pass through global memory for pairs above the list capacity): bitwise the
+    same results for every capacity, and the oracle's."""
+    from paper_2602_10761_amd import runtime as R
+    say("sort capacity paths")
+    ens = ens_small(nx=16, ny=24, nz=16, n=12000, v_jitter=3.0, precharge=0.2, re_tau=40.0, c_el=5.0)
+    n = 5
+    runs = {}
+    try:
+        for cap in (-1, 8, 64, 0):
+            R.set_tuning(sort_cap=cap)
+            sim = sim_of(ens)
+            sim.step(n)
+            runs[cap] = (sim.state_np(0), sim.stats(0))
+            sim.close()
+    finally:
+        R.set_tuning()
+    ref, st = oracle_run(ens, n)
+    err = state_errors(runs[0][0], ref, ens.mesh)
+    say("  state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert max(err.values()) < 1e-10
+    assert_stats_equal(runs[0][1], st)
+    for cap in (-1, 8, 64):
+        for k in KEYS:
+            np.testing.assert_array_equal(runs[cap][0][k], runs[0][0][k])
+
+
 @pytest.mark.parametrize("graphs", [False, True])
 def test_carrier_replacement(graphs):
     """tf_set_carrier: steps after a new carrier field follow the oracle with
