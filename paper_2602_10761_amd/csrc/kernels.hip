@@ -73,6 +73,33 @@ __device__ __forceinline__ void scan_load(const int* __restrict__ cnt, long long
   }
 }
 
+// exclusive prefix (starting at ex) of v[] into out[base, base + kScanPer)
+// (nothing past n); 16-byte stores when the chunk is whole
+__device__ __forceinline__ void scan_store(int* __restrict__ out, long long base, long long n, const int* v, int ex) {
+  if (base + kScanPer <= n) {
+    int4* o4 = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+    for (int r = 0; r < kScanPer / 4; ++r) {
+      int4 t;
+      t.x = ex;
+      ex += v[4 * r];
+      t.y = ex;
+      ex += v[4 * r + 1];
+      t.z = ex;
+      ex += v[4 * r + 2];
+      t.w = ex;
+      ex += v[4 * r + 3];
+      o4[r] = t;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+      if (base + r < n) out[base + r] = ex;
+      ex += v[r];
+    }
+  }
+}
+
 // per-block totals of the counts
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ cnt, long long n,
                                                         int* __restrict__ part) {
@@ -114,11 +141,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ cnt
   for (int r = 0; r < kScanPer; ++r) s += v[r];
   int tot;
   int ex = block_excl_scan<16>(s, &tot);
-#pragma unroll
-  for (int r = 0; r < kScanPer; ++r) {
-    if (base + r < n) out[base + r] = ex;
-    ex += v[r];
-  }
+  scan_store(out, base, n, v, ex);
   if (threadIdx.x == 0) out[n] = tot;
 }
 
@@ -143,29 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ cn
 #pragma unroll
   for (int r = 0; r < kScanPer; ++r) s += v[r];
   int tot;
-  int ex = block_excl_scan<kBlock / 64>(s, &tot) + pre;
-  if (base + kScanPer <= n) {
-    int4* s4 = reinterpret_cast<int4*>(start + base);
-#pragma unroll
-    for (int r = 0; r < kScanPer / 4; ++r) {
-      int4 t;
-      t.x = ex;
-      ex += v[4 * r];
-      t.y = ex;
-      ex += v[4 * r + 1];
-      t.z = ex;
-      ex += v[4 * r + 2];
-      t.w = ex;
-      ex += v[4 * r + 3];
-      s4[r] = t;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < kScanPer; ++r) {
-      if (base + r < n) start[base + r] = ex;
-      ex += v[r];
-    }
-  }
+  const int ex = block_excl_scan<kBlock / 64>(s, &tot) + pre;
+  scan_store(start, base, n, v, ex);
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) start[n] = pre + tot;
 }
 
