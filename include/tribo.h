@@ -251,6 +251,10 @@ int tf_field(tf_handle* h, int32_t ens, int32_t which, void* out);
  */
 #define TF_NPHASE 7
 int tf_profile_begin(tf_handle* h, int32_t max_steps, uint32_t phase_mask);
+/* The same with events on every `every`-th step only (the first, the
+ * (every+1)-th, ...) until max_steps steps carry them; every >= 1.  The steps
+ * in between run eagerly without events: fewer events in a timed stretch. */
+int tf_profile_begin_every(tf_handle* h, int32_t max_steps, uint32_t phase_mask, int32_t every);
 int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_steps);
 
 /*

@@ -264,6 +264,7 @@ struct tf_handle {
   hipGraphExec_t g_ab = nullptr, g_ba = nullptr;
   // phase timing: TF_NPHASE + 1 events per profiled step
   int prof_cap = 0, prof_n = 0;
+  int prof_every = 1, prof_seen = 0;  // events on every prof_every-th step
   uint32_t prof_mask = 0;           // phases bracketed by events
   std::vector<hipEvent_t> prof_ev;
 };
@@ -382,7 +383,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   // closes phase b - 1; only the boundaries of the bracketed phases are recorded
   hipEvent_t ev[TF_NPHASE + 1] = {};
   bool prof = false;
-  if (h->prof_n < h->prof_cap) {
+  if (h->prof_n < h->prof_cap && (h->prof_seen++ % h->prof_every) == 0) {
     hipEvent_t* all = &h->prof_ev[(size_t)h->prof_n++ * (TF_NPHASE + 1)];
     for (int b = 0; b <= TF_NPHASE; ++b) {
       const bool opens = b < TF_NPHASE && ((h->prof_mask >> b) & 1u);
@@ -974,8 +975,13 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
 }
 
 int tf_profile_begin(tf_handle* h, int32_t max_steps, uint32_t phase_mask) {
+  return tf_profile_begin_every(h, max_steps, phase_mask, 1);
+}
+
+int tf_profile_begin_every(tf_handle* h, int32_t max_steps, uint32_t phase_mask, int32_t every) {
   if (!h) return fail(TF_EINVAL, "handle is NULL");
   if (max_steps < 1 || max_steps > 100000) return fail(TF_EINVAL, "max_steps out of range");
+  if (every < 1 || every > 100000) return fail(TF_EINVAL, "every out of range");
   if (h->prof_cap) return fail(TF_ESTATE, "profiling already active");
   const uint32_t all = (1u << TF_NPHASE) - 1u;
   if (phase_mask & ~all) return fail(TF_EINVAL, "phase_mask has bits beyond the phases");
@@ -984,6 +990,8 @@ int tf_profile_begin(tf_handle* h, int32_t max_steps, uint32_t phase_mask) {
   for (auto& e : h->prof_ev) HIPCHK(hipEventCreate(&e));
   h->prof_cap = max_steps;
   h->prof_n = 0;
+  h->prof_every = every;
+  h->prof_seen = 0;
   return TF_OK;
 }
 

@@ -85,6 +85,7 @@ def lib():
         L.tf_poisson.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
         L.tf_profile_begin.argtypes = [c_void_p, c_int32, ctypes.c_uint32]
+        L.tf_profile_begin_every.argtypes = [c_void_p, c_int32, ctypes.c_uint32, c_int32]
         L.tf_profile_end.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
         L.tf_set_tuning.argtypes = [POINTER(TfTuning)]
         L.tf_set_tuning_class.argtypes = [c_int32, c_int32, c_int32, POINTER(TfTuning)]
@@ -290,12 +291,16 @@ class TriboSim:
         self._sync_out()
         return dth
 
-    def profile_begin(self, max_steps: int, phases=None):
-        """Time the next max_steps steps per phase (phases: names from PHASES, None = all)."""
+    def profile_begin(self, max_steps: int, phases=None, every: int = 1):
+        """Time max_steps steps per phase (phases: names from PHASES, None = all):
+        the next ones, or every `every`-th one from the next."""
         mask = 0
         for p in phases or ():
             mask |= 1 << PHASES.index(p)
-        _check(self.L.tf_profile_begin(self.h, max_steps, mask))
+        if every == 1:
+            _check(self.L.tf_profile_begin(self.h, max_steps, mask))
+        else:
+            _check(self.L.tf_profile_begin_every(self.h, max_steps, mask, every))
 
     def profile_end(self):
         ms = (c_double * TF_NPHASE)()
