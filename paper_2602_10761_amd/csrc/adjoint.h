@@ -28,10 +28,15 @@ struct AdjWork {
   double* radj;             // [c_tot]    -G^T lambda_E (right-hand side of the adjoint Poisson problem)
   double* lamQ;             // [c_tot]    cotangent of the cell charge
   double* dacc;             // [n_ens][3] accumulated d/dtheta
+  double* part;             // [n_ens][nch][3] chunk sums of d/dtheta
+  int nch;                  // chunks of kAdjChunk slots in the largest ensemble
   double* wwall;            // [n_ens][2] cotangent of the wall charge accumulators
 };
 
-AdjWork carve_adjoint(Carver& cv, long long n_tot, long long c_tot, long long s_tot, int n_ens, bool enabled);
+constexpr int kAdjChunk = 2048;  // slots per block of the d/dtheta reduction
+
+AdjWork carve_adjoint(Carver& cv, long long n_tot, long long c_tot, long long s_tot, int n_ens, long long np_max,
+                      bool enabled);
 
 hipError_t run_adjoint(const Ctx& C, const LaunchGeo& G, const AdjWork& W, int n_ens, const Ens* eh,
                        const long long* p_off, const long long* c_off, const TrajStep* steps, int n_steps,

@@ -19,7 +19,7 @@
 
 namespace tf {
 
-AdjWork carve_adjoint(Carver& cv, long long n, long long c, long long, int n_ens, bool enabled) {
+AdjWork carve_adjoint(Carver& cv, long long n, long long c, long long, int n_ens, long long np_max, bool enabled) {
   AdjWork W{};
   W.enabled = enabled;
   if (!enabled) return W;
@@ -44,6 +44,8 @@ AdjWork carve_adjoint(Carver& cv, long long n, long long c, long long, int n_ens
   W.radj = cv.take<double>(c);
   W.lamQ = cv.take<double>(c);
   W.dacc = cv.take<double>(3 * n_ens);
+  W.nch = (int)((np_max + kAdjChunk - 1) / kAdjChunk);
+  W.part = cv.take<double>(3 * (size_t)n_ens * (size_t)(W.nch > 0 ? W.nch : 1));
   W.wwall = cv.take<double>(2 * n_ens);
   return W;
 }
@@ -264,12 +266,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_b(Ctx C, Ens Eone, int one, PSta
   lam0.q[p] = lq;
 }
 
-// d/dtheta of one ensemble, summed in a fixed order (deterministic)
-__global__ __launch_bounds__(kBlock) void k_adj_reduce(const double* __restrict__ dth, long long n,
-                                                       const long long* __restrict__ p_off, double* __restrict__ dacc) {
+// d/dtheta of each ensemble, summed in a fixed order (deterministic) in two
+// stages: block (c, e) sums chunk c (kAdjChunk slots) of ensemble e, then one
+// wavefront per ensemble sums its chunks
+__global__ __launch_bounds__(kBlock) void k_adj_part(const double* __restrict__ dth, long long n,
+                                                     const long long* __restrict__ p_off, int nch,
+                                                     double* __restrict__ part) {
   __shared__ double red[3][kBlock];
-  const int e = blockIdx.x;
-  const long long n0 = p_off[e], n1 = p_off[e + 1];
+  const int c = blockIdx.x, e = blockIdx.y;
+  const long long n0 = p_off[e] + (long long)c * kAdjChunk;
+  const long long n1 = min(p_off[e + 1], n0 + kAdjChunk);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (long long s = n0 + threadIdx.x; s < n1; s += kBlock) {
     a0 += dth[s];
@@ -289,9 +295,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(const double* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    dacc[3 * e] += red[0][0];
-    dacc[3 * e + 1] += red[1][0];
-    dacc[3 * e + 2] += red[2][0];
+    double* o = part + 3 * ((long long)e * nch + c);
+    o[0] = red[0][0];
+    o[1] = red[1][0];
+    o[2] = red[2][0];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_adj_sum(const double* __restrict__ part, int nch, double* __restrict__ dacc) {
+  const int e = blockIdx.x, lane = threadIdx.x;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int c = lane; c < nch; c += 64)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] += part[3 * ((long long)e * nch + c) + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_xor(a[k], o, 64);
+    if (lane == 0) dacc[3 * e + k] += a[k];
   }
 }
 
@@ -366,7 +386,10 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
         hipSuccess)
       return err;
     if (nb > 0) k_adj_b<<<nb, kBlock, 0, st>>>(C, Eone, one, steps[t].st, W, nxt);
-    k_adj_reduce<<<n_ens, kBlock, 0, st>>>(W.dth, n, C.p_off, W.dacc);
+    if (W.nch > 0) {
+      k_adj_part<<<dim3(W.nch, n_ens), kBlock, 0, st>>>(W.dth, n, C.p_off, W.nch, W.part);
+      k_adj_sum<<<n_ens, 64, 0, st>>>(W.part, W.nch, W.dacc);
+    }
     AdjLam tmp = cur;
     cur = nxt;
     nxt = tmp;

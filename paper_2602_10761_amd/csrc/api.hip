@@ -62,7 +62,7 @@ bool radix_plan(int n, FftPlan* P) {
 }
 
 struct Sizes {
-  long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0;
+  long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0, np_max = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
   int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
@@ -114,6 +114,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     long long ncell = (long long)E.nx * E.ny * E.nz;
     int nh = E.nx / 2 + 1, nhp = (nh + 7) & ~7;
     S->n_tot += E.n_particles;
+    S->np_max = std::max<long long>(S->np_max, E.n_particles);
     S->c_tot += ncell;
     S->s_tot += (long long)E.ny * E.nz * nhp;
     S->tf_tot += (long long)E.ny * E.nz * nh;
@@ -350,7 +351,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
       traj.push_back(tb);
     }
   }
-  AdjWork adj = carve_adjoint(cv, S.n_tot, S.c_tot, S.s_tot, n_ens, traj_steps > 0);
+  AdjWork adj = carve_adjoint(cv, S.n_tot, S.c_tot, S.s_tot, n_ens, S.np_max, traj_steps > 0);
   if (h) {
     C.n_ens = n_ens;
     C.n_tot = S.n_tot;
