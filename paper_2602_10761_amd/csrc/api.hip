@@ -337,6 +337,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.fslot = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.n_tot) : nullptr;
   C.fsrc = (flags & TF_INIT_SOURCE) ? cv.take<double>(3 * S.c_tot) : nullptr;
   C.cinc = S.pp_any ? cv.take<double>(4 * S.n_tot) : nullptr;
+  C.chit = S.pp_any ? cv.take<unsigned char>(S.n_tot) : nullptr;
   std::vector<TrajBuf> traj;
   if (traj_steps > 0) {
     for (int t = 0; t <= traj_steps; ++t) {

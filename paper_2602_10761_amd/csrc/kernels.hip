@@ -1903,15 +1903,20 @@ __global__ __launch_bounds__(kBlock) void k_collide(Ctx C, PState in) {
   const int e = find_off(C.c_off, C.n_ens + 1, c);
   const Ens& E = C.ens[e];
   double inc[4] = {0.0, 0.0, 0.0, 0.0};
+  int hit = 0;
   if (E.pp) {
-    const int npp = pp_collide(C, E, in, s, C.perm[s], c, inc);
+    const int npp = pp_collide(C, E, in, s, C.perm[s], c, inc, &hit);
     if (npp) atomicAdd((unsigned long long*)&C.stats[E.st_off + ST_PP], (unsigned long long)npp);
   }
-  const long long n = C.n_tot;
-  C.cinc[s] = inc[0];
-  C.cinc[n + s] = inc[1];
-  C.cinc[2 * n + s] = inc[2];
-  C.cinc[3 * n + s] = inc[3];
+  // the increments only where a collision happened (the push reads the flag)
+  C.chit[s] = (unsigned char)hit;
+  if (hit) {
+    const long long n = C.n_tot;
+    C.cinc[s] = inc[0];
+    C.cinc[n + s] = inc[1];
+    C.cinc[2 * n + s] = inc[2];
+    C.cinc[3 * n + s] = inc[3];
+  }
 }
 
 hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st) {

@@ -170,7 +170,7 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   // 4-way coupling: the collision increments of this slot (pp_collide)
   double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
   if constexpr (PP) {
-    if (E.pp) {
+    if (E.pp && C.chit[s]) {  // increments stored only for the slots with a collision
       const long long n = C.n_tot;
       cvx = C.cinc[s];
       cvy = C.cinc[n + s];
@@ -215,17 +215,29 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
 // 4-way coupling: binary hard-sphere collisions of slot s (cell c, state at
 // the start of the step) with the other particles of its cell, increments
 // summed in ascending id; pairs farther apart than (d + d_max)/2 are skipped
-// before any gather.  Returns the pairs with a partner of larger id (each
-// pair is counted once over the two particles).
+// before any gather, and a slot with no mate closer than d_max (>= that
+// cutoff) reads nothing of its own state.  Returns the pairs with a partner
+// of larger id (each pair is counted once over the two particles); *hit: some
+// pair collided.
 __device__ __forceinline__ int pp_collide(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
-                                          double inc[4]) {
+                                          double inc[4], int* hit) {
   inc[0] = inc[1] = inc[2] = inc[3] = 0.0;
+  *hit = 0;
   const double x = C.sx[s], y = C.sy[s], z = C.sz[s], q = C.sq[s];
+  const double dmax = __longlong_as_double(C.stats[E.st_off + ST_DMAX]);
+  const int a = C.start[c], b = C.start[c + 1];
+  bool near = false;
+  for (int t = a; t < b; ++t) {
+    if (t == s) continue;
+    const double rx = x - C.sx[t], ry = y - C.sy[t], rz = z - C.sz[t];
+    const double r2 = (rx * rx + ry * ry) + rz * rz;
+    near |= r2 < dmax * dmax;
+  }
+  if (!near) return 0;
   const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p], d = in.d[p];
-  const double rc = 0.5 * (d + __longlong_as_double(C.stats[E.st_off + ST_DMAX]));
+  const double rc = 0.5 * (d + dmax);
   const double rcut2 = rc * rc;
   int npp = 0;
-  const int a = C.start[c], b = C.start[c + 1];
   for (int t = a; t < b; ++t) {
     if (t == s) continue;
     const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t];
@@ -234,6 +246,7 @@ __device__ __forceinline__ int pp_collide(const Ctx& C, const Ens& E, const PSta
     if (!(r2 < rcut2)) continue;
     const PPHit h = pp_pair(C.perm[t], in, E.kpp, rx, ry, rz, r2, d, vx, vy, vz, q, C.sq[t]);
     if (h.hit) {
+      *hit = 1;
       if (t > s) ++npp;
       inc[0] += h.dvx;
       inc[1] += h.dvy;

@@ -129,6 +129,7 @@ struct Ctx {
   double* fslot;             // optional [3][n_tot] drag force on the particle of each slot (2-way source)
   double* fsrc;              // optional [3][c_tot] 2-way coupling source of the latest step
   double* cinc;              // optional [4][n_tot] collision increments (vx, vy, vz, q) of each slot
+  unsigned char* chit;       // optional [n_tot] the slot collided this step (cinc valid only there)
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
   const double2* tfac;       // Thomas factors per ensemble: [modes][ny] (1 / pivot, c')
