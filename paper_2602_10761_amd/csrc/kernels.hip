@@ -1866,30 +1866,32 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
 }
 
 // 2-way coupling source: minus the summed drag forces of a cell's particles
-// (its slot range, ascending id) per unit cell volume
+// (its slot range, ascending id) per unit cell volume; two neighbouring cells
+// of one x row per thread (nx is even), 16-byte stores
 __global__ __launch_bounds__(kBlock) void k_source(Ctx C) {
-  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long c = 2 * ((long long)blockIdx.x * kBlock + threadIdx.x);
   if (c >= C.c_tot) return;
   const int e = find_off(C.c_off, C.n_ens + 1, c);
   const Ens& E = C.ens[e];
-  const int j = (int)((c - E.c_off) / ((long long)E.nx * E.nz));
-  const double vol = C.vol[E.y_off + j];
-  const int a = C.start[c], b = C.start[c + 1];
+  const int j = (int)((int)(c - E.c_off) / (E.nx * E.nz));
+  const double iv = 1.0 / C.vol[E.y_off + j];
+  const int a = C.start[c], m = C.start[c + 1], b = C.start[c + 2];
   const long long n = C.n_tot;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
+  double f[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   for (int t = a; t < b; ++t) {
-    fx += C.fslot[t];
-    fy += C.fslot[n + t];
-    fz += C.fslot[2 * n + t];
+    const int h = t >= m ? 1 : 0;
+    f[h][0] += C.fslot[t];
+    f[h][1] += C.fslot[n + t];
+    f[h][2] += C.fslot[2 * n + t];
   }
-  C.fsrc[c] = -fx / vol;
-  C.fsrc[C.c_tot + c] = -fy / vol;
-  C.fsrc[2 * C.c_tot + c] = -fz / vol;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    *reinterpret_cast<double2*>(C.fsrc + k * C.c_tot + c) = make_double2(-f[0][k] * iv, -f[1][k] * iv);
 }
 
 hipError_t launch_source(const Ctx& C, hipStream_t st) {
   if (C.c_tot == 0) return hipSuccess;
-  const int nb = (int)((C.c_tot + kBlock - 1) / kBlock);
+  const int nb = (int)((C.c_tot / 2 + kBlock - 1) / kBlock);
   k_source<<<nb, kBlock, 0, st>>>(C);
   return hipGetLastError();
 }
