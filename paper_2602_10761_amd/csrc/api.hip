@@ -68,6 +68,7 @@ struct Sizes {
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
   std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk, ph_blk;
+  std::vector<int> fps_blk, fzs_blk;  // the same as fp_blk / fz_blk for the ensembles with split inverse transforms
   int plane_max = 0, half_lds = 0;
   bool plane_any = false, half_any = false, split_any = false;
   bool pp_any = false;  // some ensemble has 4-way coupling on
@@ -81,6 +82,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   S->fz_blk.assign(n_ens + 1, 0);
   S->pl_blk.assign(n_ens + 1, 0);
   S->ph_blk.assign(n_ens + 1, 0);
+  S->fps_blk.assign(n_ens + 1, 0);
+  S->fzs_blk.assign(n_ens + 1, 0);
   S->tri_blk.assign(n_ens + 1, 0);
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
@@ -206,6 +209,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->e_plane[e] = m;
     S->pl_blk[e + 1] = S->pl_blk[e] + (m == 1 ? E.ny : 0);
     S->ph_blk[e + 1] = S->ph_blk[e] + (m == 2 ? 2 * E.ny : 0);
+    S->fps_blk[e + 1] = S->fps_blk[e] + (m == 0 ? S->fp_blk[e + 1] - S->fp_blk[e] : 0);
+    S->fzs_blk[e + 1] = S->fzs_blk[e] + (m == 0 ? S->fz_blk[e + 1] - S->fz_blk[e] : 0);
     if (m == 1) {
       S->plane_any = true;
       S->plane_max = std::max(S->plane_max, pts);
@@ -257,6 +262,8 @@ struct tf_handle {
   int* d_tri = nullptr;
   int* d_pl = nullptr;
   int* d_ph = nullptr;
+  int* d_fps = nullptr;
+  int* d_fzs = nullptr;
   // recorded trajectory
   int traj_cap = 0, traj_len = 0;
   std::vector<TrajBuf> traj;        // traj_cap + 1 states (perm/phi used for the first traj_cap)
@@ -293,6 +300,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   int* tri = cv.take<int>(n_ens + 1);
   int* pl = cv.take<int>(n_ens + 1);
   int* ph = cv.take<int>(n_ens + 1);
+  int* fps = cv.take<int>(n_ens + 1);
+  int* fzs = cv.take<int>(n_ens + 1);
   C.yf = cv.take<double>(S.y_tot);
   C.dy = cv.take<double>(S.y_tot);
   C.idy = cv.take<double>(S.y_tot);
@@ -365,6 +374,8 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     h->d_tri = tri;
     h->d_pl = pl;
     h->d_ph = ph;
+    h->d_fps = fps;
+    h->d_fzs = fzs;
     h->d_ens = (Ens*)C.ens;
     h->traj = traj;
     h->traj_cap = traj_steps;
@@ -664,6 +675,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->d_tri, S.tri_blk);
   UP(h->d_pl, S.pl_blk);
   UP(h->d_ph, S.ph_blk);
+  UP(h->d_fps, S.fps_blk);
+  UP(h->d_fzs, S.fzs_blk);
   UP(h->C.yf, yf);
   UP(h->C.dy, dy);
   UP(h->C.idy, idy);
@@ -719,6 +732,10 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.d_pl_blk = h->d_pl;
   h->G.ph_blk = h->S.ph_blk.data();
   h->G.d_ph_blk = h->d_ph;
+  h->G.fps_blk = h->S.fps_blk.data();
+  h->G.d_fps_blk = h->d_fps;
+  h->G.fzs_blk = h->S.fzs_blk.data();
+  h->G.d_fzs_blk = h->d_fzs;
   h->G.plane_any = S.plane_any ? 1 : 0;
   h->G.half_any = S.half_any ? 1 : 0;
   h->G.half_lds = S.half_lds;

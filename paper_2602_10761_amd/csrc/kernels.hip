@@ -1845,10 +1845,13 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
       fr = nullptr;
     }
   }
-  if (split && nzb > 0) k_z<true><<<nzb, kBlock, lz, st>>>(C, Eone, one, G.d_fz_blk, z0, G.nz_max);
+  // (blocks only for the ensembles transformed this way)
+  const int zs0 = G.fzs_blk[e0], nzs = G.fzs_blk[e1] - zs0;
+  const int bs0 = G.fps_blk[e0], nbs = G.fps_blk[e1] - bs0;
+  if (split && nzs > 0) k_z<true><<<nzs, kBlock, lz, st>>>(C, Eone, one, G.d_fzs_blk, zs0, G.nz_max);
   mark(3);
-  if (split && nb > 0)
-    k_pair_ifftx<<<nb, kBlock, lx, st>>>(C, Eone, one, G.d_fp_blk, b0, G.nx_max, phi_out, phi_shift, fr, 1);
+  if (split && nbs > 0)
+    k_pair_ifftx<<<nbs, kBlock, lx, st>>>(C, Eone, one, G.d_fps_blk, bs0, G.nx_max, phi_out, phi_shift, fr, 1);
   mark(4);
   return hipGetLastError();
 }

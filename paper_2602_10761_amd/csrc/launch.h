@@ -41,6 +41,10 @@ struct LaunchGeo {
   const int* d_pl_blk;
   const int* ph_blk;  // per half plane: two blocks per y plane
   const int* d_ph_blk;
+  const int* fps_blk;  // fp_blk / fz_blk restricted to the ensembles whose inverse
+  const int* d_fps_blk;  // transforms run as the z then x kernels
+  const int* fzs_blk;
+  const int* d_fzs_blk;
   const Ens* eh;   // host copies of the ensemble descriptors
 };
 
