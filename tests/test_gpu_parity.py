@@ -164,6 +164,30 @@ def test_multi_step_parity():
     sim.close()
 
 
+def test_long_run_profiles():
+    """1000 steps with wall impacts and charging: the accumulated concentration
+    and charge profiles over the y rows, the impact counts and the wall charge
+    agree with the oracle's within 1 % (normwise)."""
+    say("long run profiles")
+    ens = ens_small(nx=16, ny=24, nz=16, n=3000, v_jitter=3.0, precharge=0.2, re_tau=40.0, c_el=5.0,
+                    density_ratio=30.0)
+    ens.params["k_c"] = 0.02
+    n = 1000
+    sim = sim_of(ens)
+    sim.step(n)
+    gst = sim.stats(0)
+    sim.close()
+    _, st = oracle_run(ens, n)
+    assert gst["steps"] == st.steps == n
+    assert st.impacts.sum() > 200
+    for k, ref in (("crel_y", st.crel_y), ("qcum_y", st.qcum_y), ("impacts", st.impacts), ("wallq", st.wallq)):
+        g = np.asarray(gst[k], dtype=np.float64)
+        o = np.asarray(ref, dtype=np.float64)
+        err = np.abs(g - o).max() / np.abs(o).max()
+        say(f"  {k}: normwise rel diff {err:.2e}")
+        assert err < 0.01, k
+
+
 @pytest.mark.parametrize("ny", [128, 300])
 def test_many_row_pairs_multi_step(ny):
     """Incremental sorts on meshes with many row pairs (16384 and 38400: the
