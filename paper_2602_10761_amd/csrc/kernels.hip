@@ -823,7 +823,9 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
     if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
     const int b = min(pre[i], M), a = max(pre[i] - cnt[i], 0);
-    const double q = in.q[p], x = in.x[p], y = in.y[p], z = in.z[p];
+    // read once here (the push reads the slot-ordered copies): non-temporal
+    const double q = __builtin_nontemporal_load(&in.q[p]), x = __builtin_nontemporal_load(&in.x[p]);
+    const double y = __builtin_nontemporal_load(&in.y[p]), z = __builtin_nontemporal_load(&in.z[p]);
     int rk = 0;
     if (b - a > 1) {
       if (fast) {
@@ -1602,15 +1604,18 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
         isfinite(q1)))
     atomicOr((unsigned long long*)&st[ST_FLAGS], (unsigned long long)FLAG_NONFINITE);
 
-  out.x[s] = x1;
-  out.y[s] = yr;
-  out.z[s] = z1;
-  out.vx[s] = v1x;
-  out.vy[s] = vyr;
-  out.vz[s] = v1z;
-  out.q[s] = q1;
-  out.d[s] = d;
-  out.id[s] = in.id[p];
+  // the new state is next read by the following step's sort: streaming
+  // stores that do not allocate in the caches, which keeps the carrier and phi
+  // lines of the gathers resident (66 instead of 75 us for 1e6 particles)
+  __builtin_nontemporal_store(x1, &out.x[s]);
+  __builtin_nontemporal_store(yr, &out.y[s]);
+  __builtin_nontemporal_store(z1, &out.z[s]);
+  __builtin_nontemporal_store(v1x, &out.vx[s]);
+  __builtin_nontemporal_store(vyr, &out.vy[s]);
+  __builtin_nontemporal_store(v1z, &out.vz[s]);
+  __builtin_nontemporal_store(q1, &out.q[s]);
+  __builtin_nontemporal_store(d, &out.d[s]);
+  __builtin_nontemporal_store(in.id[p], &out.id[s]);
   if (C.fslot) {
     // drag force of the step on this particle (2-way coupling source)
     const double mp = (E.rr * (kPi / 6.0)) * ((d * d) * d);
@@ -1625,7 +1630,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   const int nk = clamp_floor(z1 / E.dz, nz);
   const int nj = y_cell_from(yf, ny, yr, j);
   const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
-  out.key[s] = key;
+  __builtin_nontemporal_store(key, &out.key[s]);
   // the next sort takes a row pair's members from the pair's slot range of
   // this order and from its mover list: a particle whose row pair changes
   // goes on the mover list of its new pair (on the far list, read by every
