@@ -1892,9 +1892,12 @@ __global__ __launch_bounds__(kBlock) void k_source(Ctx C) {
     f[h][1] += C.fslot[n + t];
     f[h][2] += C.fslot[2 * n + t];
   }
+  // an output of the step, not read again within it: non-temporal stores
+  // (otherwise its 48 MB displace the next push's carrier and phi lines)
+  typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    *reinterpret_cast<double2*>(C.fsrc + k * C.c_tot + c) = make_double2(-f[0][k] * iv, -f[1][k] * iv);
+    __builtin_nontemporal_store(d2v{-f[0][k] * iv, -f[1][k] * iv}, reinterpret_cast<d2v*>(C.fsrc + k * C.c_tot + c));
 }
 
 hipError_t launch_source(const Ctx& C, hipStream_t st) {
