@@ -1,17 +1,21 @@
 // Forward-step kernels of libtribo.so (gfx950, FP64, wave64).
 //
 // Per step (launch order):
-//   scan_reduce / [scan_part] / scan_down  count -> start (exclusive prefix)
-//   place                                  unordered slot per particle in its cell run
-//   rank                                   order each cell run by particle id -> perm,
-//                                          slot-ordered copies of charge and position
-//   dep_fftx                               cell charge from the sorted runs (exact int64),
-//                                          rho = Q 2^-48 / V, forward FFT along x
-//   fftz<fwd>                              forward FFT along z
-//   tri                                    one tridiagonal y-solve per Fourier mode
-//   fftz<inv>, ifftx                       back to phi on the cells
-//   push                                   per particle: forces, integration, wall
-//                                          impact and charging, wrap, next cell key
+//   scan_small            row-pair prefix of the member counts the last push made
+//   row_sort_dep          per row pair: members from its own slot range and its
+//                         mover list, ranked by (cell, id) -> perm, slot-ordered
+//                         copies of charge and position; exact int64 cell charge,
+//                         rho = Q 2^-48 / V, forward FFT along x of the two rows
+//   z<fwd>                forward FFT along z
+//   tri                   one tridiagonal y-solve per Fourier mode
+//   plane_half / plane_inv  inverse FFTs along z and x per y plane (two blocks or
+//                         one), or z<inv> then pair_ifftx: phi on the cells
+//   [collide]             4-way coupling: per-slot collision increments
+//   push                  per particle: forces, integration, wall impact and
+//                         charging, wrap, next cell key, row-pair counts, movers
+//   [source]              2-way coupling source per cell
+// After an upload of particles the sort is a full counting sort instead
+// (count, scan_*, place, rank) followed by pair_fftx.
 //
 // Particle state is stored in the slot order of the previous step's sort; the
 // push gathers velocity, diameter and id through perm (nearly coalesced) and
