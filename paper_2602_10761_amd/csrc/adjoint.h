@@ -23,7 +23,7 @@ struct AdjWork {
   AdjLam lamA, lamB, lamP;  // cotangents: two state buffers and the per-slot local part
   double* lamE;             // [3][n_tot] per-slot field cotangent ke * lambda_a
   double* lamS;             // [3][n_tot] per-slot cotangent of the same-cell Coulomb sum
-  double* dth;              // [3][n_tot] per-slot d/d(k_c, dU, e)
+  double* dth;              // [3][n_tot] per-slot d/d(k_c, dU, e), summed over a segment's steps
   double* lamEc;            // [3][c_tot] field cotangent per cell
   double* radj;             // [c_tot]    -G^T lambda_E (right-hand side of the adjoint Poisson problem)
   double* lamQ;             // [c_tot]    cotangent of the cell charge

@@ -167,9 +167,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(Ctx C, Ens Eone, int one, PSta
   W.lamP.vy[s] = lvdy;
   W.lamP.vz[s] = lvdz;
   W.lamP.q[s] = lqd;
-  W.dth[s] = dkc;
-  W.dth[n + s] = ddu;
-  W.dth[2 * n + s] = de;
+  // summed per slot over the segment's steps (a slot stays inside its
+  // ensemble's range, so the per-ensemble totals are unchanged)
+  W.dth[s] += dkc;
+  W.dth[n + s] += ddu;
+  W.dth[2 * n + s] += de;
 }
 
 // field cotangent per cell: sum over the cell's run of slots, in slot order
@@ -363,6 +365,7 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
   if ((err = hipMemcpyAsync(W.wwall, w_wall, sizeof(double) * 2 * n_ens, hipMemcpyHostToDevice, st)) != hipSuccess)
     return err;
   if ((err = hipMemsetAsync(W.dacc, 0, sizeof(double) * 3 * n_ens, st)) != hipSuccess) return err;
+  if (n > 0 && (err = hipMemsetAsync(W.dth, 0, sizeof(double) * 3 * n, st)) != hipSuccess) return err;
   AdjLam cur = W.lamA, nxt = W.lamB;
   for (int e = 0; e < n_ens; ++e) {
     const int np = (int)(p_off[e + 1] - p_off[e]);
@@ -386,13 +389,14 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
         hipSuccess)
       return err;
     if (nb > 0) k_adj_b<<<nb, kBlock, 0, st>>>(C, Eone, one, steps[t].st, W, nxt);
-    if (W.nch > 0) {
-      k_adj_part<<<dim3(W.nch, n_ens), kBlock, 0, st>>>(W.dth, n, C.p_off, W.nch, W.part);
-      k_adj_sum<<<n_ens, 64, 0, st>>>(W.part, W.nch, W.dacc);
-    }
     AdjLam tmp = cur;
     cur = nxt;
     nxt = tmp;
+  }
+  // d/dtheta of the segment: the per-slot sums over its steps, per ensemble
+  if (W.nch > 0) {
+    k_adj_part<<<dim3(W.nch, n_ens), kBlock, 0, st>>>(W.dth, n, C0.p_off, W.nch, W.part);
+    k_adj_sum<<<n_ens, 64, 0, st>>>(W.part, W.nch, W.dacc);
   }
   for (int e = 0; e < n_ens; ++e) {
     const int np = (int)(p_off[e + 1] - p_off[e]);

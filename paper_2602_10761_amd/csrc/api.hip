@@ -414,18 +414,9 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   if ((e = launch_poisson(h->C, h->G, 0, h->n_ens, in.q, in.key, nullptr, 0, h->C.phi, 0, 1, h->stream,
                           prof ? ev + 2 : nullptr, nullptr, !full, h->C.far_n)) != hipSuccess)
     return e;
-  if (rec) {
-    const size_t n = h->C.n_tot, nc = h->C.c_tot;
-    if ((e = hipMemcpyAsync(rec->skey, h->C.skey, sizeof(int) * n, hipMemcpyDeviceToDevice, h->stream)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipMemcpyAsync(rec->start, h->C.start, sizeof(int) * (nc + 1), hipMemcpyDeviceToDevice, h->stream)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipMemcpyAsync(rec->phi, h->C.phi, sizeof(double) * nc, hipMemcpyDeviceToDevice, h->stream)) !=
-        hipSuccess)
-      return e;
-  }
+  if (rec && (e = launch_record(rec->skey, h->C.skey, h->C.n_tot, rec->start, h->C.start, rec->phi, h->C.phi,
+                                h->C.c_tot, h->stream)) != hipSuccess)
+    return e;
   if (h->C.cinc && (e = launch_collide(h->C, in, h->stream)) != hipSuccess) return e;
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)

@@ -1943,6 +1943,28 @@ hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st) {
   return hipGetLastError();
 }
 
+// the recorded step's sorted keys, cell starts and potential in one launch
+// (grid-stride over the longest of the three)
+__global__ __launch_bounds__(kBlock) void k_record(int* __restrict__ skey_d, const int* __restrict__ skey,
+                                                   long long n, int* __restrict__ start_d,
+                                                   const int* __restrict__ start, double* __restrict__ phi_d,
+                                                   const double* __restrict__ phi, long long nc) {
+  const long long m = n > nc + 1 ? n : nc + 1;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < m; t += (long long)gridDim.x * kBlock) {
+    if (t < n) skey_d[t] = skey[t];
+    if (t <= nc) start_d[t] = start[t];
+    if (t < nc) phi_d[t] = phi[t];
+  }
+}
+
+hipError_t launch_record(int* skey_d, const int* skey, long long n, int* start_d, const int* start, double* phi_d,
+                         const double* phi, long long nc, hipStream_t st) {
+  const long long m = n > nc + 1 ? n : nc + 1;
+  const int nb = (int)std::min<long long>((m + kBlock - 1) / kBlock, 4096);
+  k_record<<<nb, kBlock, 0, st>>>(skey_d, skey, n, start_d, start, phi_d, phi, nc);
+  return hipGetLastError();
+}
+
 __global__ void k_set_ptr(const double** slot, const double* value) { *slot = value; }
 
 hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st) {

@@ -62,6 +62,9 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
                        signed char* wall_rec, hipStream_t st);
 // 4-way coupling: per-slot collision increments (before the push)
 hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st);
+// copies of a recorded step's sorted keys [n], cell starts [nc + 1] and phi [nc]
+hipError_t launch_record(int* skey_d, const int* skey, long long n, int* start_d, const int* start, double* phi_d,
+                         const double* phi, long long nc, hipStream_t st);
 // *slot = value, in stream order (a kernel: usable between captured graphs)
 hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st);
 // 2-way coupling source per cell from the push's per-slot drag forces
