@@ -37,6 +37,9 @@ def test_profile_phases_and_stride():
     assert ms2["push"] > 0.0
     assert all(v == 0.0 for k, v in ms2.items() if k != "push")
     prof = sim.state_np(0)
+    from paper_2602_10761_amd.runtime import TriboError
+    with pytest.raises(TriboError, match="every"):
+        sim.profile_begin(2, every=0)
     sim.close()
     plain = TriboSim([ens])
     plain.step(10)
