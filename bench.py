@@ -7,7 +7,8 @@ push with wall charging) with inputs resident in HBM.  Prints one JSON line:
 the headline is particle-steps/s on the 10^6-particle 128^3 channel with the
 Poisson solve every step; it also carries the batched-vs-plain time on 64
 independent ensembles, the adjoint/forward time ratio, the roofline of the
-dominant kernel and the CPU oracle baseline.
+dominant kernel (its launch duration from HIP events around every 10th launch
+in the timed region, --event-every) and the CPU oracle baseline.
 """
 import argparse
 import hashlib
