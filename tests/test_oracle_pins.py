@@ -369,6 +369,97 @@ def test_coulomb_pair_repels_like_charges():
 
 
 # --------------------------------------------------------------------------
+# Electric acceleration (Sec. 2.2, hybrid scheme): the velocity a charged
+# particle gains in one step from rest in still fluid, u = g = 0.  With
+# Re_p = 0 the drag factor is 1 and the semi-implicit update gives
+# v1 = dt a / (1 + dt / tau_p), tau_p = rho_r d^2 / 18, so the specific
+# electric force a is read back from v1 and compared with Coulomb's and
+# Gauss' laws evaluated here by hand.  In normalised units (eps = 1) the
+# specific force of a field E on a particle of charge q and diameter d is
+# c_el q E / d^3 (the particle mass grows as d^3).
+# --------------------------------------------------------------------------
+def _accel_from_v1(v1, d, dt, rr):
+    return v1 * (1.0 + dt * 18.0 / (rr * d * d)) / dt
+
+
+@pytest.mark.parametrize("q1,q2", [(0.3, 0.5), (0.4, -0.7), (-0.2, -0.6)])
+def test_coulomb_pair_acceleration(q1, q2):
+    # a y-centred cell of a wall-symmetric mesh (ny odd, faces mirror about
+    # the centre plane): the charge of the cell is mirror-symmetric about its
+    # centre in x, y and z, so the Gauss (mesh) field at the cell vanishes and
+    # only the pair's Coulomb force remains
+    g = small_geo(5, 7, 3, h=4.0, stretch=2.0)
+    jc = g.ny // 2
+    assert abs(g.yc[jc] - 0.5 * g.ly) < 1e-12 * g.ly
+    xc, zc = (2 + 0.5) * g.dx, (1 + 0.5) * g.dz
+    s = zero_state(2)
+    s["x"][:] = [xc - 0.11 * g.dx, xc + 0.23 * g.dx]
+    s["y"][:] = [g.yc[jc] + 0.17 * g.dy[jc], g.yc[jc] - 0.05 * g.dy[jc]]
+    s["z"][:] = [zc + 0.2 * g.dz, zc - 0.09 * g.dz]
+    s["q"][:] = [q1, q2]
+    s["d"][:] = [1.0, 0.5]
+    U = np.zeros((3, g.ny + 1, g.nz, g.nx))
+    prm = dict(BASE, dt=0.05, density_ratio=800.0, c_el=2.5)
+    want = {}
+    out = O.step(g, U, s, prm, want=want)
+    assert len(set(want["cid"].tolist())) == 1
+    # Coulomb's law between the two, eps = 1: force on particle a from b is
+    # q_a q_b / (4 pi r^2) along the unit vector from b to a (repulsive for
+    # like charges)
+    pos = np.stack([s["x"], s["y"], s["z"]], axis=1)
+    for a, b in ((0, 1), (1, 0)):
+        sep = pos[a] - pos[b]
+        r = math.sqrt(float(sep @ sep))
+        force = s["q"][a] * s["q"][b] / (4.0 * math.pi * r * r) * (sep / r)
+        expect = prm["c_el"] * force / s["d"][a] ** 3
+        got = np.array([_accel_from_v1(out[k][a], s["d"][a], prm["dt"], prm["density_ratio"])
+                        for k in ("vx", "vy", "vz")])
+        np.testing.assert_allclose(got, expect, rtol=1e-11, atol=1e-13 * np.abs(expect).max())
+        # direction: away from the partner for like charges, toward it otherwise
+        assert np.sign(got @ sep) == np.sign(s["q"][a] * s["q"][b])
+
+
+@pytest.mark.parametrize("j0,q", [(0, 0.6), (0, -0.3), (4, 0.45), (4, -0.8)])
+def test_lone_charge_pulled_to_grounded_wall(j0, q):
+    # one charged particle in a wall cell, nothing else: its only force is the
+    # Gauss part, E of its own cell from the potential of a charge q/V in that
+    # cell between grounded walls.  The potential comes from the dense
+    # face-by-face operator (not the oracle's transform solver); the cell
+    # gradient takes face values interpolated linearly between cell centres
+    # and phi = 0 on the wall faces.
+    g = small_geo(4, 5, 6, h=2.0, stretch=2.0)
+    i0, k0 = 1, 4
+    s = zero_state(1)
+    s["x"][:] = (i0 + 0.37) * g.dx
+    s["z"][:] = (k0 + 0.61) * g.dz
+    s["y"][:] = g.yf[j0] + 0.55 * g.dy[j0]
+    s["q"][:] = q
+    s["d"][:] = 0.02
+    U = np.zeros((3, g.ny + 1, g.nz, g.nx))
+    prm = dict(BASE, dt=1e-3, density_ratio=500.0, c_el=0.7)
+    out = O.step(g, U, s, prm)
+    rho = np.zeros((g.ny, g.nz, g.nx))
+    qfix = float(np.rint(q * 2.0 ** 48)) * 2.0 ** -48      # the deposit's fixed-point charge
+    rho[j0, k0, i0] = qfix / g.vol[j0]
+    phi = np.linalg.solve(dense_operator(g), rho.ravel()).reshape(rho.shape)
+    col = phi[:, k0, i0]
+    def face(f):  # potential on y face f
+        if f == 0 or f == g.ny:
+            return 0.0
+        w = (g.yf[f] - g.yc[f - 1]) / (g.yc[f] - g.yc[f - 1])
+        return col[f - 1] + w * (col[f] - col[f - 1])
+    Ey = -(face(j0 + 1) - face(j0)) / g.dy[j0]
+    ay = prm["c_el"] * q * Ey / s["d"][0] ** 3
+    got = [_accel_from_v1(out[k][0], s["d"][0], prm["dt"], prm["density_ratio"]) for k in ("vx", "vy", "vz")]
+    np.testing.assert_allclose(got[1], ay, rtol=1e-10)
+    # attraction by the image charge: toward the nearer wall whatever the sign
+    toward = -1.0 if j0 == 0 else 1.0
+    assert toward * got[1] > 0.0
+    # the cell's charge is mirror-symmetric in x and z: no periodic-direction force
+    assert abs(got[0]) < 1e-10 * abs(got[1]) and abs(got[2]) < 1e-10 * abs(got[1])
+
+
+# --------------------------------------------------------------------------
 # Whole-step invariants on a synthetic channel
 # --------------------------------------------------------------------------
 def test_channel_invariants():
