@@ -225,8 +225,9 @@ def adjoint_ratio(torch, W, R, autotune, seg, log):
     sim.synchronize()
     t0 = time.perf_counter()
     ev0.record(sim.stream)
+    dth = torch.zeros((1, 3), dtype=torch.float64, device=sim.dev)
     sim.step(seg, record=True)
-    sim.adjoint(lam, np.zeros((1, 2)))
+    sim.adjoint(lam, np.zeros((1, 2)), dtheta=dth)   # asynchronous on the library's stream
     ev1.record(sim.stream)
     sim.synchronize()
     ms_bwd = ev0.elapsed_time(ev1)

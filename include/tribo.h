@@ -35,8 +35,8 @@
  * by tf_init and released by tf_destroy.
  *
  * Streams.  All device work of a handle is enqueued on the stream given to
- * tf_init, asynchronously.  tf_stats and tf_adjoint_step synchronise that
- * stream before returning host data.
+ * tf_init, asynchronously.  tf_stats synchronises that stream before
+ * returning host data; tf_init and tf_set_params synchronise it too.
  *
  * Errors.  Every int-returning call returns TF_OK (0) or a negative TF_E*
  * code; tf_last_error() describes the most recent failure of the calling
@@ -72,7 +72,14 @@ typedef struct tf_handle tf_handle;
 /* tf_step flags */
 #define TF_STEP_RECORD 1u         /* record the steps for tf_adjoint_step (needs trajectory capacity) */
 
-/* sticky device flags (tf_stats_out.flags) */
+/* sticky device flags (tf_stats_out.flags); a step that raises one still runs
+ * to completion on every particle:
+ *   TF_FLAG_NONFINITE  a particle's new position, velocity or charge is not finite
+ *   TF_FLAG_OVERFLOW   a fixed-point conversion (deposit q 2^48, charge profile
+ *                      q 2^32, wall charge -dq 2^40) rounds to a magnitude of
+ *                      2^62 or more, or is not finite; that entry contributes 0
+ *   TF_FLAG_OUTSIDE    a particle is still outside [d/2, ly - d/2] in y after
+ *                      its wall rebound (a penetration deeper than the channel) */
 #define TF_FLAG_NONFINITE 1
 #define TF_FLAG_OVERFLOW 2
 #define TF_FLAG_OUTSIDE 4
@@ -199,7 +206,10 @@ int tf_set_state(tf_handle* h, int32_t ens, const tf_particles* in);
  * ensemble out of range), TF_ESTATE (a recorded trajectory is pending), TF_EHIP. */
 int tf_set_carrier(tf_handle* h, int32_t ens, const double* u_nodes);
 
-/* Replace (k_c, delta_u, e) of every ensemble: host array [n_ens][3]. */
+/* Replace (k_c, delta_u, e) of every ensemble: host array [n_ens][3], each
+ * finite with 0 < e <= 1 (else TF_EINVAL, nothing changed).  Steps queued
+ * before the call use the old values.  TF_ESTATE while a recorded trajectory
+ * is pending: its reverse step needs the parameters it was recorded with. */
 int tf_set_params(tf_handle* h, const double* theta);
 
 /*
@@ -208,11 +218,15 @@ int tf_set_params(tf_handle* h, const double* theta);
  *   lambda   device arrays, id order, one tf_particles per ensemble: on entry
  *            dJ/d(state) at the end of the recorded steps, on return dJ/d(state)
  *            at their start (the d member is ignored)
- *   w_wall   host [n_ens][2]: dJ/d(charge received by the lower/upper wall)
- *            over the recorded steps (the wall accumulators never feed back)
- *   dtheta   host [n_ens][3]: dJ/d(k_c, delta_u, e) is ADDED to it
- * Consumes the recorded trajectory.  The fixed-point deposit is treated as
- * the identity (its derivative is zero almost everywhere).
+ *   w_wall   device [n_ens][2]: dJ/d(charge received by the lower/upper wall)
+ *            over the recorded steps (the wall accumulators never feed back);
+ *            read on the stream
+ *   dtheta   device [n_ens][3]: dJ/d(k_c, delta_u, e) is ADDED to it on the stream
+ * Asynchronous on the handle's stream: the caller's buffers must stay valid
+ * until the queued work has run.  Consumes the recorded trajectory (a later
+ * tf_step may record again).  The fixed-point deposit is treated as the
+ * identity (its derivative is zero almost everywhere).  Errors: TF_EINVAL
+ * (NULL pointer), TF_ESTATE (nothing recorded), TF_EHIP.
  */
 int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wall, double* dtheta);
 

@@ -61,6 +61,21 @@ def fixed(v: np.ndarray, shift: int) -> np.ndarray:
     return np.rint(np.asarray(v, dtype=np.float64) * (2.0 ** shift)).astype(np.int64)
 
 
+FIX_LIMIT = 2.0 ** 62   # fixed-point values must stay below this magnitude
+
+
+def fixed_checked(v: np.ndarray, shift: int):
+    """rne(v * 2^shift) into int64 where its magnitude stays below 2^62.
+
+    An entry at or beyond 2^62, or not finite, contributes 0 (so that sums of
+    many entries cannot wrap) and the conversion reports an overflow, which
+    the step turns into the sticky F_OVERFLOW flag.  Returns (values, overflowed).
+    """
+    s = np.rint(np.asarray(v, dtype=np.float64) * (2.0 ** shift))
+    ok = np.abs(s) < FIX_LIMIT
+    return np.where(ok, s, 0.0).astype(np.int64), bool(not ok.all())
+
+
 # ----------------------------------------------------------------------------
 # Mesh geometry (Sec. 3.1: periodic x, z; walls at y = 0 and y = 2h)
 # ----------------------------------------------------------------------------
@@ -106,7 +121,7 @@ def cell_index(g: Geo, i, j, k):
 # ----------------------------------------------------------------------------
 def deposit(g: Geo, q, cid) -> np.ndarray:
     Q = np.zeros(g.ncell, dtype=np.int64)
-    np.add.at(Q, cid, fixed(q, FIX_DEP))
+    np.add.at(Q, cid, fixed_checked(q, FIX_DEP)[0])
     return Q
 
 
@@ -502,15 +517,17 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
         i, j, k = locate(g, x, y, z)
     cid = cell_index(g, i, j, k)
 
-    # deposit q^n and its statistics
-    fq = fixed(q, FIX_DEP)
+    # deposit q^n and its statistics (a charge beyond the fixed-point range
+    # deposits nothing and raises the overflow flag)
+    fq, ovf_dep = fixed_checked(q, FIX_DEP)
     Q = np.zeros(g.ncell, dtype=np.int64)
     np.add.at(Q, cid, fq)
     if stats is not None:
+        q32, ovf_cum = fixed_checked(q, FIX_QCUM)
         stats.crel_y += np.bincount(j, minlength=g.ny).astype(np.int64)
-        stats.qcum_y += _sum_by(j, fixed(q, FIX_QCUM), g.ny)
+        stats.qcum_y += _sum_by(j, q32, g.ny)
         stats.qnow_y = _sum_by(j, fq, g.ny)
-        if np.any(np.abs(q) * 2.0 ** FIX_DEP >= 2.0 ** 62):
+        if ovf_dep or ovf_cum:
             stats.flags |= F_OVERFLOW
 
     # 4-way coupling: collisions act on the velocities and charges at the start
@@ -591,14 +608,17 @@ def step(g: Geo, U: np.ndarray, s: Dict[str, np.ndarray], prm: dict, stats: Opti
         for w in (0, 1):
             m = wall == w
             stats.impacts[w] += int(m.sum())
-            stats.wallq[w] += int(fixed(-dq[m], FIX_WALL).sum())
+            wq, ovf_w = fixed_checked(-dq[m], FIX_WALL)
+            stats.wallq[w] += int(wq.sum())
+            if ovf_w:
+                stats.flags |= F_OVERFLOW
             stats.wallq_f[w] += float((-dq[m]).sum())
         b = np.minimum((un[hit] / un_bin).astype(np.int64), N_UNBIN - 1)
         stats.unhist += np.bincount(b, minlength=N_UNBIN).astype(np.int64)
         if replay is None:
             if np.any((yr < r) | (yr > top)):
                 stats.flags |= F_OUTSIDE
-        if not (np.all(np.isfinite(x1)) and np.all(np.isfinite(v1x)) and np.all(np.isfinite(q1))):
+        if not all(np.all(np.isfinite(a)) for a in (x1, yr, z1, v1x, vyr, v1z, q1)):
             stats.flags |= F_NONFINITE
 
     if record is not None:

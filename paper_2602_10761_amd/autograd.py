@@ -52,6 +52,7 @@ class TriboRun(torch.autograd.Function):
             done += k
         J = objectives(sim, wall0, n_steps)
         ctx.sim = sim
+        ctx.theta = th.copy()       # backward re-runs the segments at this theta
         ctx.ckpts = ckpts
         ctx.lens = lens
         ctx.final = [sim.state(e) for e in range(sim.n_ens)]
@@ -72,15 +73,21 @@ class TriboRun(torch.autograd.Function):
                 L["q"].fill_(g[e, 0] / n)
             lam.append(L)
             w_wall[e, :] = g[e, 1] / (ctx.n_steps * sim.ens[e].params["dt"])
-        dth = np.zeros((sim.n_ens, 3))
+        # the segments are re-run at the theta of this forward (another apply or
+        # set_params on the same simulation may have changed it since); the
+        # simulation's parameters are restored afterwards
+        theta_before = sim.theta.copy()
+        sim.set_params(ctx.theta)
+        dth = torch.zeros((sim.n_ens, 3), dtype=torch.float64, device=dev)
         for ck, k in zip(reversed(ctx.ckpts), reversed(ctx.lens)):
             for e in range(sim.n_ens):
                 sim.set_state(e, ck[e])
             sim.step(k, record=True)
-            dth += sim.adjoint(lam, w_wall)
+            sim.adjoint(lam, w_wall, dtheta=dth)
         for e in range(sim.n_ens):
             sim.set_state(e, ctx.final[e])
-        return torch.as_tensor(dth), None, None, None
+        sim.set_params(theta_before)
+        return dth.cpu(), None, None, None
 
 
 def charging_gradient(sim: TriboSim, theta: np.ndarray, n_steps: int, segment: int = 50):

@@ -27,10 +27,9 @@ struct AdjWork {
   double* lamEc;            // [3][c_tot] field cotangent per cell
   double* radj;             // [c_tot]    -G^T lambda_E (right-hand side of the adjoint Poisson problem)
   double* lamQ;             // [c_tot]    cotangent of the cell charge
-  double* dacc;             // [n_ens][3] accumulated d/dtheta
   double* part;             // [n_ens][nch][3] chunk sums of d/dtheta
   int nch;                  // chunks of kAdjChunk slots in the largest ensemble
-  double* wwall;            // [n_ens][2] cotangent of the wall charge accumulators
+  double* wwall;            // [n_ens][2] cotangent of the wall charge accumulators (copied from the caller)
 };
 
 constexpr int kAdjChunk = 2048;  // slots per block of the d/dtheta reduction

@@ -43,7 +43,6 @@ AdjWork carve_adjoint(Carver& cv, long long n, long long c, long long, int n_ens
   W.lamEc = cv.take<double>(3 * c);
   W.radj = cv.take<double>(c);
   W.lamQ = cv.take<double>(c);
-  W.dacc = cv.take<double>(3 * n_ens);
   W.nch = (int)((np_max + kAdjChunk - 1) / kAdjChunk);
   W.part = cv.take<double>(3 * (size_t)n_ens * (size_t)(W.nch > 0 ? W.nch : 1));
   W.wwall = cv.take<double>(2 * n_ens);
@@ -362,9 +361,8 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
   const long long n = C0.n_tot, nc = C0.c_tot;
   const int one = (n_ens == 1) ? 1 : 0;
   const Ens Eone = eh[0];
-  if ((err = hipMemcpyAsync(W.wwall, w_wall, sizeof(double) * 2 * n_ens, hipMemcpyHostToDevice, st)) != hipSuccess)
+  if ((err = hipMemcpyAsync(W.wwall, w_wall, sizeof(double) * 2 * n_ens, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return err;
-  if ((err = hipMemsetAsync(W.dacc, 0, sizeof(double) * 3 * n_ens, st)) != hipSuccess) return err;
   if (n > 0 && (err = hipMemsetAsync(W.dth, 0, sizeof(double) * 3 * n, st)) != hipSuccess) return err;
   AdjLam cur = W.lamA, nxt = W.lamB;
   for (int e = 0; e < n_ens; ++e) {
@@ -394,9 +392,10 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
     nxt = tmp;
   }
   // d/dtheta of the segment: the per-slot sums over its steps, per ensemble
+  // (added to the caller's device dtheta)
   if (W.nch > 0) {
     k_adj_part<<<dim3(W.nch, n_ens), kBlock, 0, st>>>(W.dth, n, C0.p_off, W.nch, W.part);
-    k_adj_sum<<<n_ens, 64, 0, st>>>(W.part, W.nch, W.dacc);
+    k_adj_sum<<<n_ens, 64, 0, st>>>(W.part, W.nch, dtheta);
   }
   for (int e = 0; e < n_ens; ++e) {
     const int np = (int)(p_off[e + 1] - p_off[e]);
@@ -405,10 +404,7 @@ hipError_t run_adjoint(const Ctx& C0, const LaunchGeo& G, const AdjWork& W, int 
     UserLam u{(double*)L[0], (double*)L[1], (double*)L[2], (double*)L[3], (double*)L[4], (double*)L[5], (double*)L[6]};
     k_lam_out<<<(np + kBlock - 1) / kBlock, kBlock, 0, st>>>(cur, u, steps[0].st.id, p_off[e], np);
   }
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-  if ((err = hipMemcpyAsync(dtheta, W.dacc, sizeof(double) * 3 * n_ens, hipMemcpyDeviceToHost, st)) != hipSuccess)
-    return err;
-  return hipStreamSynchronize(st);
+  return hipGetLastError();
 }
 
 }  // namespace tf

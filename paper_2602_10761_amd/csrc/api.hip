@@ -908,6 +908,9 @@ int tf_set_carrier(tf_handle* h, int32_t e, const double* u_nodes) {
 
 int tf_set_params(tf_handle* h, const double* theta) {
   if (!h || !theta) return fail(TF_EINVAL, "NULL argument");
+  // the reverse step reads the charging parameters of the descriptor: they
+  // must stay those of the recorded steps
+  if (h->traj_len > 0) return fail(TF_ESTATE, "a recorded trajectory is pending (tf_adjoint_step first)");
   for (int e = 0; e < h->n_ens; ++e) {
     const double kc = theta[3 * e], du = theta[3 * e + 1], ee = theta[3 * e + 2];
     if (!std::isfinite(kc) || !std::isfinite(du) || !(ee > 0 && ee <= 1))
@@ -975,11 +978,9 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
     steps[t].phi = h->traj[t].phi;
     steps[t].wall = h->traj[t].wall;
   }
-  std::vector<double> dth(3 * (size_t)h->n_ens, 0.0);
   hipError_t he = run_adjoint(h->C, h->G, h->adj, h->n_ens, h->eh.data(), h->p_off.data(), h->c_off.data(),
-                              steps.data(), h->traj_len, lam.data(), w_wall, dth.data(), h->stream);
+                              steps.data(), h->traj_len, lam.data(), w_wall, dtheta, h->stream);
   if (he != hipSuccess) return fail(TF_EHIP, std::string("adjoint: ") + hipGetErrorString(he));
-  for (size_t i = 0; i < dth.size(); ++i) dtheta[i] += dth[i];
   h->traj_len = 0;
   return TF_OK;
 }

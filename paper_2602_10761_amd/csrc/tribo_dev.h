@@ -188,9 +188,12 @@ __device__ __forceinline__ void divmod(int a, int d, double inv_d, int* q, int* 
   *r = rr;
 }
 
+// rne(v 2^shift) as int64.  A value whose rounded magnitude reaches 2^62, or
+// that is not finite, contributes 0 (sums of many entries cannot wrap) and sets
+// *ovf, which the callers raise as the sticky overflow flag.
 __device__ __forceinline__ long long fixed_round(double v, int shift, bool* ovf) {
   double s = rint(v * (double)(1ULL << shift));
-  if (!(fabs(s) < 4.0e18)) { *ovf = true; return 0; }
+  if (!(fabs(s) < 0x1p62)) { *ovf = true; return 0; }
   return (long long)s;
 }
 

@@ -81,7 +81,7 @@ def lib():
         L.tf_set_state.argtypes = [c_void_p, c_int32, POINTER(TfParticles)]
         L.tf_set_params.argtypes = [c_void_p, POINTER(c_double)]
         L.tf_set_carrier.argtypes = [c_void_p, c_int32, c_void_p]
-        L.tf_adjoint_step.argtypes = [c_void_p, POINTER(TfParticles), POINTER(c_double), POINTER(c_double)]
+        L.tf_adjoint_step.argtypes = [c_void_p, POINTER(TfParticles), c_void_p, c_void_p]
         L.tf_poisson.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
         L.tf_profile_begin.argtypes = [c_void_p, c_int32, ctypes.c_uint32]
@@ -183,6 +183,9 @@ class TriboSim:
                               c_void_p(self.stream.cuda_stream), flags, ctypes.byref(h)))
         self.h = h
         self.traj_steps = traj_steps
+        # charging parameters (k_c, delta_u, e) per ensemble as last set
+        self.theta = np.array([[E.params["k_c"], E.params["delta_u"], E.params["e"]] for E in self.ens],
+                              dtype=np.float64).reshape(self.n_ens, 3)
 
     # ------------------------------------------------------------------
     def _sync_in(self):
@@ -232,6 +235,7 @@ class TriboSim:
     def set_params(self, theta: np.ndarray):
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.n_ens, 3)
         _check(self.L.tf_set_params(self.h, th.ctypes.data_as(POINTER(c_double))))
+        self.theta = th.copy()
 
     def set_carrier(self, e: int, U):
         """Replace the carrier velocity of ensemble e (array [3][ny+1][nz][nx])."""
@@ -270,8 +274,12 @@ class TriboSim:
         self.stream.synchronize()
         return out
 
-    def adjoint(self, lambdas: List[Dict[str, "object"]], w_wall: np.ndarray) -> np.ndarray:
-        """Reverse the recorded steps; lambdas (id order, device) are updated in place."""
+    def adjoint(self, lambdas: List[Dict[str, "object"]], w_wall: np.ndarray, dtheta=None):
+        """Reverse the recorded steps; lambdas (id order, device) are updated in place.
+
+        With dtheta (a device float64 [n_ens, 3] tensor) d/dtheta is added to it
+        asynchronously and dtheta is returned; without, a host array of
+        d/dtheta is returned (synchronises)."""
         P = (TfParticles * self.n_ens)()
         keep = []
         for e in range(self.n_ens):
@@ -283,13 +291,20 @@ class TriboSim:
                 tns = lam[k]
                 keep.append(tns)
                 setattr(P[e], k, tns.data_ptr())
-        ww = np.ascontiguousarray(w_wall, dtype=np.float64).reshape(self.n_ens, 2)
-        dth = np.zeros((self.n_ens, 3))
+        ww = self.torch.as_tensor(np.ascontiguousarray(w_wall, dtype=np.float64).reshape(self.n_ens, 2)).to(self.dev)
+        acc = dtheta if dtheta is not None else self.torch.zeros((self.n_ens, 3), dtype=self.torch.float64,
+                                                                   device=self.dev)
+        if acc.dtype != self.torch.float64 or acc.device != self.dev or not acc.is_contiguous() or \
+                acc.numel() != 3 * self.n_ens:
+            raise ValueError("dtheta must be a contiguous float64 [n_ens, 3] tensor on the simulation's device")
         self._sync_in()
-        _check(self.L.tf_adjoint_step(self.h, P, ww.ctypes.data_as(POINTER(c_double)),
-                                      dth.ctypes.data_as(POINTER(c_double))))
+        _check(self.L.tf_adjoint_step(self.h, P, c_void_p(ww.data_ptr()), c_void_p(acc.data_ptr())))
+        # the library reads w_wall on its stream: keep it alive until then
+        ww.record_stream(self.stream)
         self._sync_out()
-        return dth
+        if dtheta is not None:
+            return dtheta
+        return acc.cpu().numpy()
 
     def profile_begin(self, max_steps: int, phases=None, every: int = 1):
         """Time max_steps steps per phase (phases: names from PHASES, None = all):

@@ -121,3 +121,49 @@ def test_adjoint_matches_gpu_central_differences(seed):
     err = np.abs(G[0, 0] - fd).max() / np.abs(fd).max()
     say("fd", fd, "rel err", err)
     assert err < 1e-5
+
+
+def test_set_params_refused_while_recording_pending():
+    from paper_2602_10761_amd.runtime import TriboError, TriboSim
+    ens = small_charged(4)
+    sim = TriboSim([ens], traj_steps=5)
+    th = np.array([[0.03, 1.0, 0.9]])
+    sim.step(3, record=True)
+    with pytest.raises(TriboError, match="recorded trajectory"):
+        sim.set_params(th)
+    lam = [{k: torch.zeros(ens.n, dtype=torch.float64, device=sim.dev) for k in
+            ("x", "y", "z", "vx", "vy", "vz", "q", "d")}]
+    dev = torch.zeros((1, 3), dtype=torch.float64, device=sim.dev)
+    out = sim.adjoint(lam, np.zeros((1, 2)), dtheta=dev)   # asynchronous, device dtheta
+    assert out is dev
+    sim.set_params(th)                                       # allowed once consumed
+    sim.close()
+
+
+def test_autograd_backward_uses_its_forward_theta():
+    """Two applies on one simulation before the first one's backward: the
+    first gradient is the one of its own theta, not of the later apply's."""
+    from paper_2602_10761_amd.autograd import TriboRun
+    from paper_2602_10761_amd.runtime import TriboSim
+    ens = small_charged(5)
+    th_a = np.array([[ens.params["k_c"], ens.params["delta_u"], ens.params["e"]]])
+    th_b = th_a * np.array([[3.0, 0.5, 0.9]])
+    n = 24
+
+    def grad_of(th, sim, then_other=False):
+        t = torch.tensor(th, requires_grad=True)
+        J = TriboRun.apply(t, sim, n, 8)
+        if then_other:
+            TriboRun.apply(torch.tensor(th_b), sim, n, 8)   # advances the state at another theta
+        (g,) = torch.autograd.grad(J[:, 0].sum(), t)
+        return J.detach().numpy(), g.numpy()
+
+    sim1 = TriboSim([ens], traj_steps=8)
+    J1, g1 = grad_of(th_a, sim1)
+    sim1.close()
+    sim2 = TriboSim([ens], traj_steps=8)
+    J2, g2 = grad_of(th_a, sim2, then_other=True)
+    assert np.allclose(sim2.theta, th_b)       # restored after the backward
+    sim2.close()
+    np.testing.assert_array_equal(J1, J2)
+    np.testing.assert_allclose(g2, g1, rtol=1e-13, atol=1e-300)
