@@ -4,11 +4,14 @@ python bench.py [--steps K] [--warmup W] [--config C] [--no-cpu] [--no-batched] 
 
 One step = the whole per-step particle phase (sort, deposit, Poisson solve,
 push with wall charging) with inputs resident in HBM.  Prints one JSON line:
-the headline is particle-steps/s on the 10^6-particle 128^3 channel with the
-Poisson solve every step; it also carries the batched-vs-plain time on 64
-independent ensembles, the adjoint/forward time ratio, the roofline of the
+the headline is particle-steps/s on the 4e6-particle 192x160x192 Re_tau = 550
+channel with the Poisson solve every step (the largest single-GPU workload);
+it also carries the 1e6-particle 128^3 workload, the batched-vs-plain time on
+64 independent ensembles, the adjoint/forward time ratio, the roofline of the
 dominant kernel (its launch duration from HIP events around every 10th launch
-in the timed region, --event-every) and the CPU oracle baseline.
+in the timed region, --event-every, against the method's own bytes; the
+measured HBM bytes come from the committed rocprofv3 summary of the workload)
+and the CPU oracle baseline.
 """
 import argparse
 import hashlib
@@ -28,7 +31,6 @@ WORKLOAD_NAME = {
     2: "Re_tau=180 channel 128^3 (tanh y, 2.0), 1e6 particles d+ in {0.25,0.5,1}, rho_p/rho=1000, dt+=0.1",
     3: "Re_tau=550 channel 192x160x192 (tanh y, 2.0), 4e6 particles d+ in {0.5,1,2}, dt+=0.05",
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_config2.txt")
 KERNEL_SOURCES = ["paper_2602_10761_amd/csrc/kernels.hip", "paper_2602_10761_amd/csrc/particle.h",
                   "paper_2602_10761_amd/csrc/tribo_dev.h"]
 
@@ -41,8 +43,28 @@ def plane_fused(nx, nz):
     return pts <= 10240 and 16 * (nx + nz + pts) <= 163840
 
 
-def algorithmic_bytes(phase, n_p, nx, ny, nz):
-    """Bytes each kernel group must move per launch (FP64 state, int32 keys)."""
+def algorithmic_step_bytes(n_p, nx, ny, nz):
+    """Bytes the method itself must move per step (FP64): particle state read
+    (x, v, q, d: 64 B) and written (x, v, q: 56 B); the carrier at most once per
+    cell or 8 nodes per particle; the charge deposit write; the Poisson solve's
+    density read and potential write; the potential stencil read for E.  Sort
+    keys, particle ids and FFT intermediates are design overhead, not counted."""
+    n_c = nx * ny * nz
+    return (120 * n_p + min(24 * n_c, 192 * n_p) + min(8 * n_c, 8 * n_p) + 8 * n_c + 8 * n_c +
+            min(8 * n_c, 56 * n_p))
+
+
+def algorithmic_push_bytes(n_p, nx, ny, nz):
+    """The push's share of the step's algorithmic bytes: particle state in and
+    out, carrier gathers, potential stencil."""
+    n_c = nx * ny * nz
+    return 120 * n_p + min(24 * n_c, 192 * n_p) + min(8 * n_c, 56 * n_p)
+
+
+def design_bytes(phase, n_p, nx, ny, nz):
+    """Bytes each kernel group of this design moves per launch at the least
+    (FP64 state, int32 keys): the algorithmic bytes plus the design's own
+    traffic (sort bookkeeping, ids, spectra, Thomas factors)."""
     n_c = nx * ny * nz
     n_nodes = nx * (ny + 1) * nz
     nh = nx // 2 + 1
@@ -69,6 +91,10 @@ def algorithmic_bytes(phase, n_p, nx, ny, nz):
     }[phase]
 
 
+def traffic_file(config):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_config{config}.txt")
+
+
 def source_hash():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -77,13 +103,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, if it
-    was taken on the current kernel sources (else None)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from the committed PMC summary of this
+    workload, if it was taken on the current kernel sources (else None)."""
+    path = traffic_file(config)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.split("#", 1)[0].strip()
@@ -93,7 +120,20 @@ def measured_traffic(kernel):
     return float(v) if v else None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(ens, n_steps):
+    """The oracle as it stands (numpy, FP64; its FFT and scatter-adds run on one
+    thread) over the first n_steps steps of the workload."""
     import oracle as O
 
     g = O.Geo.from_mesh(ens.mesh)
@@ -239,13 +279,87 @@ def adjoint_ratio(torch, W, R, autotune, seg, log):
             "adjoint_over_forward": ms_bwd / ms_fwd, "wall_ms_record_plus_adjoint": wall_bwd}
 
 
+def plain_run(torch, W, R, autotune, config, args, log):
+    """One ensemble of a plain workload: warm-up, an untimed phase pass (an
+    event at every phase boundary), then the timed region with HIP events only
+    around the dominant kernel on every args.event_every-th step (on the
+    library's stream).  Returns the measurement and the workload."""
+    ens = W.make_workload(config)[0]
+    m = ens.mesh
+    log(f"workload config {config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
+    tuned = autotune.ensure_tuned(autotune.meshes_of([ens]))
+    log(f"tiles: {tuned}")
+    sim = R.TriboSim([ens], device="cuda:0", graphs=args.graphs)
+    sim.step(args.warmup)
+    sim.profile_begin(args.phase_steps)
+    sim.step(args.phase_steps)
+    phase_ms, nprof = sim.profile_end()
+    per_phase = {k: v / nprof for k, v in phase_ms.items()}
+    dom = max(per_phase, key=per_phase.get)
+    sim.synchronize()
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    if not args.graphs:
+        sim.profile_begin((args.steps + args.event_every - 1) // args.event_every, phases=[dom],
+                          every=args.event_every)
+    ev0.record(sim.stream)
+    sim.step(args.steps)
+    ev1.record(sim.stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    dom_ms = None
+    if not args.graphs:
+        ph_t, n_t = sim.profile_end()
+        dom_ms = ph_t[dom] / n_t
+    st = sim.stats(0)
+    sim.close()
+    del sim
+    ms_step = total_ms / args.steps
+    log(f"config {config}: timed {args.steps} steps: {ms_step * 1e3:.1f} us/step")
+
+    dms = dom_ms if dom_ms is not None else per_phase[dom]
+    if dom == "push":
+        ab = algorithmic_push_bytes(ens.n, m.nx, m.ny, m.nz)
+    else:   # no kernel but the push carries a share of the method's own bytes
+        ab = design_bytes(dom, ens.n, m.nx, m.ny, m.nz)
+    achieved = ab / (dms * 1e-3) / 1e9
+    tr = measured_traffic(dom, config)
+    B = algorithmic_step_bytes(ens.n, m.nx, m.ny, m.nz)
+    res = {
+        "value": ens.n * args.steps / (total_ms * 1e-3),
+        "ms_per_step": ms_step,
+        "config": {"workload": WORKLOAD_NAME[config], "n_particles": ens.n, "mesh": [m.nx, m.ny, m.nz],
+                   "poisson_every": 1},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if tr is None else tr / (dms * 1e-3) / 1e9,
+                     "algorithmic_bytes_per_launch": ab,
+                     "design_bytes_per_launch": design_bytes(dom, ens.n, m.nx, m.ny, m.nz),
+                     "measured_bytes_per_launch": tr, "avg_launch_us": 1e3 * dms,
+                     "launch_timing": (f"timed region, every {args.event_every}th launch"
+                                       if dom_ms is not None else "phase pass")},
+        "step": {"algorithmic_bytes": B, "algorithmic_GBs": B / (ms_step * 1e-3) / 1e9,
+                 "algorithmic_frac": B / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "design_bytes": sum(design_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_phase)},
+        "phase_us": {k: 1e3 * v for k, v in per_phase.items()},
+        "impacts": [int(v) for v in st["impacts"]],
+        "flags": int(st["flags"]),
+    }
+    return res, ens
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3),
+                    help="headline workload (3: the largest single-GPU one)")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the CPU baseline (0: 5 for the 4e6-particle workload, else 8)")
     ap.add_argument("--phase-steps", type=int, default=10, help="untimed steps of the per-phase breakdown")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
@@ -253,6 +367,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-source", action="store_true", help="skip the 2-way coupling source timing")
     ap.add_argument("--no-fourway", action="store_true", help="skip the 4-way coupling timing")
+    ap.add_argument("--no-second", action="store_true",
+                    help="skip the 1e6-particle 128^3 workload measured beside the headline")
     ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
     ap.add_argument("--event-every", type=int, default=10,
                     help="timed region: HIP events around the dominant kernel on every n-th step")
@@ -279,78 +395,30 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    ens = W.make_workload(args.config)[0]
-    m = ens.mesh
-    log(f"workload config {args.config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
-    tuned = autotune.ensure_tuned(autotune.meshes_of([ens]))
-    log(f"tiles: {tuned}")
-    sim = R.TriboSim([ens], device="cuda:0", graphs=args.graphs)
-    sim.step(args.warmup)
-    # untimed pass with an event at every phase boundary: the phase breakdown
-    # and the dominant kernel (every event costs a few microseconds of the step)
-    sim.profile_begin(args.phase_steps)
-    sim.step(args.phase_steps)
-    phase_ms, nprof = sim.profile_end()
-    per_phase = {k: v / nprof for k, v in phase_ms.items()}
-    dom = max(per_phase, key=per_phase.get)
-    sim.synchronize()
-    torch.cuda.synchronize()
-
-    # timed region: events only around the dominant kernel (its live launch
-    # duration), on every args.event_every-th step (two events cost about 6 us)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    if not args.graphs:
-        sim.profile_begin((args.steps + args.event_every - 1) // args.event_every, phases=[dom],
-                          every=args.event_every)
-    ev0.record(sim.stream)
-    sim.step(args.steps)
-    ev1.record(sim.stream)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    dom_ms = None
-    if not args.graphs:
-        ph_t, n_t = sim.profile_end()
-        dom_ms = ph_t[dom] / n_t
-    st = sim.stats(0)
-    sim.close()
-    del sim
-    log(f"timed {args.steps} steps: {total_ms / args.steps * 1e3:.1f} us/step")
-
-    ms_step = total_ms / args.steps
-    value = ens.n * args.steps / (total_ms * 1e-3)
+    head, ens = plain_run(torch, W, R, autotune, args.config, args, log)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_NAME[args.config], "n_particles": ens.n,
-                   "mesh": [m.nx, m.ny, m.nz], "poisson_every": 1},
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "step": head["step"],
+        "phase_us": head["phase_us"],
+        "impacts": head["impacts"],
+        "flags": head["flags"],
     }
-    dms = dom_ms if dom_ms is not None else per_phase[dom]
-    ab = algorithmic_bytes(dom, ens.n, m.nx, m.ny, m.nz)
-    achieved = ab / (dms * 1e-3) / 1e9
-    tr = measured_traffic(dom) if args.config == 2 else None
-    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": None if tr is None else tr / (dms * 1e-3) / 1e9,
-                       "algorithmic_bytes_per_launch": ab, "avg_launch_us": 1e3 * dms,
-                       "launch_timing": (f"timed region, every {args.event_every}th launch"
-                                         if dom_ms is not None else "phase pass")}
-    out["phase_us"] = {k: 1e3 * v for k, v in per_phase.items()}
-    step_bytes = sum(algorithmic_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_phase)
-    out["step_algorithmic_GBs"] = step_bytes / (ms_step * 1e-3) / 1e9
-    out["impacts"] = [int(v) for v in st["impacts"]]
-    out["flags"] = int(st["flags"])
+    if not args.no_second and args.config != 2:
+        second, _ = plain_run(torch, W, R, autotune, 2, args, log)
+        out["config2"] = second
     if not args.no_batched:
         out["batched"] = batched_vs_plain(torch, W, R, autotune, args.batched_steps, log)
     if not args.no_adjoint:
@@ -361,10 +429,11 @@ def main():
         out["four_way"] = four_way_cost(torch, W, R, 50, log)
         out["carrier_every_step"] = carrier_stream_cost(torch, W, R, 50, log)
     if not args.no_cpu:
-        v, secs = cpu_baseline(ens, args.cpu_steps)
+        n_cpu = args.cpu_steps or (5 if ens.n >= 2_000_000 else 8)
+        v, secs = cpu_baseline(ens, n_cpu)
         out["cpu_baseline"] = {"value": v, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {args.cpu_steps} steps of the same workload "
-                                         f"({secs:.1f} s, numpy, one thread)"}
+                               "sample": f"first {n_cpu} steps of the same workload ({secs:.1f} s)",
+                               "cpu_model": cpu_model(), "host_threads": len(os.sched_getaffinity(0))}
     print(json.dumps(out), flush=True)
 
 

@@ -294,7 +294,7 @@ class TriboSim:
         ww = self.torch.as_tensor(np.ascontiguousarray(w_wall, dtype=np.float64).reshape(self.n_ens, 2)).to(self.dev)
         acc = dtheta if dtheta is not None else self.torch.zeros((self.n_ens, 3), dtype=self.torch.float64,
                                                                    device=self.dev)
-        if acc.dtype != self.torch.float64 or acc.device != self.dev or not acc.is_contiguous() or \
+        if acc.dtype != self.torch.float64 or acc.device != self.ws.device or not acc.is_contiguous() or \
                 acc.numel() != 3 * self.n_ens:
             raise ValueError("dtheta must be a contiguous float64 [n_ens, 3] tensor on the simulation's device")
         self._sync_in()

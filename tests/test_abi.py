@@ -91,13 +91,29 @@ def test_bench_traffic_file_parsing(tmp_path, monkeypatch):
     import bench
     f = tmp_path / "traffic.txt"
     f.write_text("# header\nsource_hash: abc\npush_bytes: 123   # fetch 1 KiB raw\nsort_bytes: 7\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "traffic_file", lambda config: str(f))
     monkeypatch.setattr(bench, "source_hash", lambda: "abc")
-    assert bench.measured_traffic("push") == 123.0
-    assert bench.measured_traffic("sort") == 7.0
-    assert bench.measured_traffic("tridiag") is None
+    assert bench.measured_traffic("push", 3) == 123.0
+    assert bench.measured_traffic("sort", 3) == 7.0
+    assert bench.measured_traffic("tridiag", 3) is None
     monkeypatch.setattr(bench, "source_hash", lambda: "other")
-    assert bench.measured_traffic("push") is None
+    assert bench.measured_traffic("push", 3) is None
+
+
+def test_bench_byte_accounting():
+    # the method's own bytes per step at the 4e6-particle 192x160x192 workload
+    # (N_p < N_c): 120 N_p + 24 N_c (carrier) + 8 N_p (deposit) + 16 N_c
+    # (Poisson) + 8 N_c (stencil) = 795.1 MB
+    import bench
+    n_p, nx, ny, nz = 4_000_000, 192, 160, 192
+    n_c = nx * ny * nz
+    assert bench.algorithmic_step_bytes(n_p, nx, ny, nz) == 128 * n_p + 48 * n_c
+    assert abs(bench.algorithmic_step_bytes(n_p, nx, ny, nz) / 1e6 - 795.1) < 0.05
+    assert bench.algorithmic_push_bytes(n_p, nx, ny, nz) == 120 * n_p + 32 * n_c
+    # sparse particles: carrier and stencil by particle
+    assert bench.algorithmic_push_bytes(10, 64, 64, 64) == 120 * 10 + 192 * 10 + 56 * 10
+    # the design moves at least the method's bytes
+    assert bench.design_bytes("push", n_p, nx, ny, nz) > bench.algorithmic_push_bytes(n_p, nx, ny, nz)
 
 
 def test_struct_layouts_match_header(tmp_path):
