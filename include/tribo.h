@@ -236,6 +236,25 @@ int tf_adjoint_step(tf_handle* h, const tf_particles* lambda, const double* w_wa
  * scratch; asynchronous on the stream. */
 int tf_poisson(tf_handle* h, int32_t ens, const int64_t* q_fixed, double* phi);
 
+/*
+ * Allocation-free variant of tf_poisson, for callers that cannot allocate
+ * device memory or that must make no allocating call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, result and stream semantics as tf_poisson; the spectrum scratch
+ * is a static device array of TF_NOALLOC_MAX_SPECTRUM_BYTES held by the
+ * library on each GPU it runs on until the process ends (its address is taken
+ * at tf_init).  The call allocates nothing, host or device.
+ *   Limit: 16 ny nz nhp bytes of spectrum, nhp = nx/2 + 1 rounded up to a
+ *   multiple of 8; larger ensembles give TF_ESIZE.
+ *   Concurrency: every call on one GPU shares that GPU's scratch, which keeps
+ *   the last call's contents (the result depends only on entries the call
+ *   writes first, so no clearing is needed); calls whose queued work overlaps
+ *   on one GPU (several streams or handles at once) race.
+ * Errors: TF_EINVAL (NULL pointer, ensemble out of range), TF_ESIZE, TF_EHIP.
+ */
+#define TF_NOALLOC_MAX_SPECTRUM_BYTES (64u << 20)
+int tf_poisson_noalloc(tf_handle* h, int32_t ens, const int64_t* q_fixed, double* phi);
+
 /* Copy a field of the latest step of ensemble `ens` to device memory `out`:
  * TF_FIELD_PHI (double [ncell]); with TF_INIT_KEEP_DEPOSIT, TF_FIELD_DEPOSIT
  * (int64 [ncell]); with TF_INIT_SOURCE, TF_FIELD_SOURCE (double [3][ncell],

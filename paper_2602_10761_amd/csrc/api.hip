@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -18,11 +19,19 @@ using namespace tf;
 namespace {
 
 thread_local std::string g_err;
+thread_local const char* g_err_lit = nullptr;  // set by fail_lit (no allocation), cleared by fail
 tf_tuning g_tune = {0, 0, 0, 0};
 std::map<std::tuple<int, int, int>, tf_tuning> g_class_tune;  // per (nx, ny, nz)
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
+  g_err_lit = nullptr;
+  return code;
+}
+
+// the same with a string literal, for entry points that must not allocate
+int fail_lit(int code, const char* msg) {
+  g_err_lit = msg;
   return code;
 }
 
@@ -233,6 +242,38 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   return TF_OK;
 }
 
+// Spectrum scratch of tf_poisson_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// its device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and kept in g_scratch.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double2 scratch[TF_NOALLOC_MAX_SPECTRUM_BYTES / sizeof(double2)];
+
+namespace {
+
+// device address of `scratch` on the current device (looked up once per device)
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TF_EHIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(TF_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return TF_OK;
+}
+
 }  // namespace
 
 struct TrajBuf {
@@ -270,6 +311,8 @@ struct tf_handle {
   AdjWork adj{};
   // graphs: one step A->B and one B->A
   hipGraphExec_t g_ab = nullptr, g_ba = nullptr;
+  // this device's copy of the static spectrum scratch (tf_poisson_noalloc)
+  double2* scratch = nullptr;
   // phase timing: TF_NPHASE + 1 events per profiled step
   int prof_cap = 0, prof_n = 0;
   int prof_every = 1, prof_seen = 0;  // events on every prof_every-th step
@@ -456,7 +499,7 @@ const char* tf_error_string(int code) {
   }
 }
 
-const char* tf_last_error(void) { return g_err.c_str(); }
+const char* tf_last_error(void) { return g_err_lit ? g_err_lit : g_err.c_str(); }
 
 int tf_set_tuning(const tf_tuning* t) {
   if (!t) {
@@ -509,7 +552,13 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
       return fail(TF_EINVAL, "initial particle pointer is NULL");
   }
 
+  // the static scratch of tf_poisson_noalloc on this device (set up once per device)
+  void* scr = nullptr;
+  rc = scratch_address(&scr);
+  if (rc != TF_OK) return rc;
+
   tf_handle* h = new tf_handle();
+  h->scratch = (double2*)scr;
   h->n_ens = n_ens;
   h->flags = flags;
   h->stream = (hipStream_t)stream;
@@ -934,6 +983,22 @@ int tf_poisson(tf_handle* h, int32_t e, const int64_t* q_fixed, double* phi) {
   if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
   HIPCHK(launch_poisson(h->C, h->G, e, e + 1, nullptr, nullptr, (const long long*)q_fixed, h->c_off[e], phi, h->c_off[e], 0,
                         h->stream));
+  return TF_OK;
+}
+
+int tf_poisson_noalloc(tf_handle* h, int32_t e, const int64_t* q_fixed, double* phi) {
+  // no allocation on any path: errors carry string literals
+  if (!h || !q_fixed || !phi) return fail_lit(TF_EINVAL, "NULL argument");
+  if (e < 0 || e >= h->n_ens) return fail_lit(TF_EINVAL, "ensemble index out of range");
+  const Ens& E = h->eh[e];
+  const size_t need = (size_t)E.ny * E.nz * E.nhp * sizeof(double2);
+  if (need > (size_t)TF_NOALLOC_MAX_SPECTRUM_BYTES)
+    return fail_lit(TF_ESIZE, "the ensemble's spectrum exceeds TF_NOALLOC_MAX_SPECTRUM_BYTES");
+  if (!h->scratch) return fail_lit(TF_ESTATE, "no static scratch on this handle's device");
+  const hipError_t he = launch_poisson(h->C, h->G, e, e + 1, nullptr, nullptr, (const long long*)q_fixed,
+                                       h->c_off[e], phi, h->c_off[e], 0, h->stream, nullptr, nullptr, false,
+                                       nullptr, h->scratch);
+  if (he != hipSuccess) return fail_lit(TF_EHIP, "kernel launch failed");
   return TF_OK;
 }
 

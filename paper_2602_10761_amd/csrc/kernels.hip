@@ -1795,17 +1795,24 @@ hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, 
   return hipGetLastError();
 }
 
-hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
+hipError_t launch_poisson(const Ctx& C0, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev, const double* r_in, bool x_done,
-                          int* far_reset) {
+                          int* far_reset, double2* spec1) {
   (void)key;
   (void)q;
   auto mark = [&](int i) {  // ev: 5 phase-boundary events, null entries skipped
     if (ev && ev[i]) hipEventRecord(ev[i], st);
   };
   const int one = (e1 - e0 == 1) ? 1 : 0;
-  const Ens Eone = G.eh[e0];
+  if (spec1 && !one) return hipErrorInvalidValue;
+  Ens Eone = G.eh[e0];
+  Ctx C = C0;
+  if (spec1) {
+    // single-ensemble launch: every kernel takes the descriptor by value
+    C.spec = spec1;
+    Eone.s_off = 0;
+  }
   const int b0 = G.fp_blk[e0], nb = G.fp_blk[e1] - b0;
   const size_t lx = (size_t)(1 + 2 * kPairsPerBlock) * G.nx_max * sizeof(double2);
   if (nb > 0 && !x_done)

@@ -53,11 +53,13 @@ struct LaunchGeo {
 // last push (the sort itself then runs fused with the deposit: launch_sort_dep)
 hipError_t launch_sort(const Ctx& C, const LaunchGeo& G, const PState& cur, bool full, hipStream_t st);
 hipError_t launch_sort_dep(const Ctx& C, const LaunchGeo& G, const PState& cur, hipStream_t st);
-// x_done: the deposit and x transform already ran (launch_sort_dep)
+// x_done: the deposit and x transform already ran (launch_sort_dep).
+// spec1: a single-ensemble launch (e1 == e0 + 1) keeps that ensemble's
+// spectrum at spec1 instead of its place in C.spec.
 hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, const double* q, const int* key,
                           const long long* q_in, long long q_shift, double* phi_out, long long phi_shift,
                           int do_stats, hipStream_t st, hipEvent_t* ev = nullptr, const double* r_in = nullptr,
-                          bool x_done = false, int* far_reset = nullptr);
+                          bool x_done = false, int* far_reset = nullptr, double2* spec1 = nullptr);
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st);
 // 4-way coupling: per-slot collision increments (before the push)

@@ -83,6 +83,7 @@ def lib():
         L.tf_set_carrier.argtypes = [c_void_p, c_int32, c_void_p]
         L.tf_adjoint_step.argtypes = [c_void_p, POINTER(TfParticles), c_void_p, c_void_p]
         L.tf_poisson.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+        L.tf_poisson_noalloc.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
         L.tf_field.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
         L.tf_profile_begin.argtypes = [c_void_p, c_int32, ctypes.c_uint32]
         L.tf_profile_begin_every.argtypes = [c_void_p, c_int32, ctypes.c_uint32, c_int32]
@@ -260,6 +261,15 @@ class TriboSim:
         self._sync_out()
         self.stream.synchronize()
         return phi
+
+    def poisson_into(self, e: int, q_fixed, phi, noalloc: bool = False):
+        """Potential of the fixed-point cell charges q_fixed (device int64 [ncell])
+        into phi (device float64 [ncell]), asynchronously on the library's stream;
+        noalloc: through tf_poisson_noalloc (static scratch, no allocation)."""
+        self._sync_in()
+        fn = self.L.tf_poisson_noalloc if noalloc else self.L.tf_poisson
+        _check(fn(self.h, e, c_void_p(q_fixed.data_ptr()), c_void_p(phi.data_ptr())))
+        self._sync_out()
 
     def field(self, e: int, which: int) -> "object":
         """Latest step's field of ensemble e: phi [ncell], the fixed-point deposit
