@@ -38,9 +38,14 @@ KERNEL_SOURCES = ["paper_2602_10761_amd/csrc/kernels.hip", "paper_2602_10761_amd
 def plane_fused(nx, nz):
     """Whether the library runs both inverse transforms of a y plane without a
     pass through memory in between (the plane's half spectrum and twiddles within
-    160 KiB, at most 10240 points: one block per plane, or two by z-row parity)."""
-    pts = nz * (nx // 2 + 1)
-    return pts <= 10240 and 16 * (nx + nz + pts) <= 163840
+    160 KiB, at most 10240 points: one block per plane, or two by z-row parity;
+    else four blocks by z-row residue mod 4, each with a quarter plane of at
+    most 4736 points)."""
+    nh = nx // 2 + 1
+    pts = nz * nh
+    whole = pts <= 10240 and 16 * (nx + nz + pts) <= 163840
+    quarter = nz % 8 == 0 and (nz // 4) * nh <= 4736 and (nz // 8) * nx <= 4736
+    return whole or quarter
 
 
 def algorithmic_step_bytes(n_p, nx, ny, nz):

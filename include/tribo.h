@@ -304,10 +304,11 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  *              mode's lanes must cover ny with at most 16 rows each)
  *   inv_plane  inverse z and x transforms: 1 = one block per y plane (the
  *              plane's half spectrum in LDS), 2 = two blocks per y plane (even
- *              and odd z rows; needs nz % 4 == 0), 3 = a z kernel then an x
- *              kernel through global memory; 0 = 2 when it fits and 2 ny
- *              does not exceed the GPU's CU count, else 1 when the plane fits
- *              a block, else 3
+ *              and odd z rows; needs nz % 4 == 0), 4 = four blocks per y plane
+ *              (z rows by residue mod 4; needs nz % 8 == 0), 3 = a z kernel
+ *              then an x kernel through global memory; 0 = 2 when it fits and
+ *              2 ny does not exceed the GPU's CU count, else 1 when the plane
+ *              fits a block, else 4 when a quarter plane does, else 3
  * Values whose LDS need exceeds a block's LDS are rejected at tf_init.
  * Results do not depend on sort_cap or fz_cols (bitwise); tri_modes and
  * inv_plane set the association order of the tridiagonal scans or of the

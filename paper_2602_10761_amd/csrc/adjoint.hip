@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_a(Ctx C, Ens Eone, int one, PSta
   Ens E;
   ens_of_cell(C, Eone, one, c, &e, &E);
   Fwd F;
-  eval_particle<false>(C, E, in, s, p, c, F);
+  eval_particle<false>(C, E, in, s, p, c, C.start[c], C.start[c + 1], F);
 
   const double lx = lam1.x[s], ly = lam1.y[s], lz = lam1.z[s];
   const double lvx = lam1.vx[s], lvy = lam1.vy[s], lq = lam1.q[s], lvz = lam1.vz[s];

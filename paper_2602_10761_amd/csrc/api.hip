@@ -75,11 +75,12 @@ struct Sizes {
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
   int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
+  long long up_tot = 0;         // padded carrier copies (doubles)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
-  std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk, ph_blk;
+  std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk, ph_blk, pq_blk;
   std::vector<int> fps_blk, fzs_blk;  // the same as fp_blk / fz_blk for the ensembles with split inverse transforms
-  int plane_max = 0, half_lds = 0;
-  bool plane_any = false, half_any = false, split_any = false;
+  int plane_max = 0, half_lds = 0, quarter_lds = 0;
+  bool plane_any = false, half_any = false, quarter_any = false, split_any = false;
   bool pp_any = false;  // some ensemble has 4-way coupling on
   std::vector<int> e_plane;
   std::map<int, int> tw_off;
@@ -91,6 +92,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   S->fz_blk.assign(n_ens + 1, 0);
   S->pl_blk.assign(n_ens + 1, 0);
   S->ph_blk.assign(n_ens + 1, 0);
+  S->pq_blk.assign(n_ens + 1, 0);
   S->fps_blk.assign(n_ens + 1, 0);
   S->fzs_blk.assign(n_ens + 1, 0);
   S->tri_blk.assign(n_ens + 1, 0);
@@ -130,6 +132,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->c_tot += ncell;
     S->s_tot += (long long)E.ny * E.nz * nhp;
     S->tf_tot += (long long)E.ny * E.nz * nh;
+    S->up_tot += 3LL * (E.ny + 1) * E.nz * (E.nx + 2);
     S->rows += (long long)E.ny * E.nz;
     S->y_tot += E.ny + 1;
     S->kx_tot += nh;
@@ -208,16 +211,22 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     FftPlan P;
     const bool half_ok = E.nz % 4 == 0 && hpts <= kHalfPts && (E.nz / 4) * E.nx <= kHalfXPts &&
                          hlds <= (size_t)kLdsMax && radix_plan(E.nz / 2, &P);
+    const int qpts = (E.nz / 4) * nh;
+    const size_t qlds = (size_t)(E.nx + E.nz / 4 + qpts) * 16;
+    const bool quarter_ok = E.nz % 8 == 0 && qpts <= kHalfPts && (E.nz / 8) * E.nx <= kQuarterXPts &&
+                            qlds <= (size_t)kLdsMax && radix_plan(E.nz / 4, &P);
     int m;
     switch (want_plane[e]) {
       case 1: m = 1; if (!whole_ok) return fail(TF_ESIZE, "inv_plane 1: the plane exceeds a block's LDS"); break;
       case 2: m = 2; if (!half_ok) return fail(TF_ESIZE, "inv_plane 2: needs nz % 4 == 0 and half a plane within a block"); break;
       case 3: m = 0; break;
-      default: m = (half_ok && 2 * E.ny <= cus) ? 2 : whole_ok ? 1 : 0; break;
+      case 4: m = 4; if (!quarter_ok) return fail(TF_ESIZE, "inv_plane 4: needs nz % 8 == 0 and a quarter plane within a block"); break;
+      default: m = (half_ok && 2 * E.ny <= cus) ? 2 : whole_ok ? 1 : quarter_ok ? 4 : 0; break;
     }
     S->e_plane[e] = m;
     S->pl_blk[e + 1] = S->pl_blk[e] + (m == 1 ? E.ny : 0);
     S->ph_blk[e + 1] = S->ph_blk[e] + (m == 2 ? 2 * E.ny : 0);
+    S->pq_blk[e + 1] = S->pq_blk[e] + (m == 4 ? 4 * E.ny : 0);
     S->fps_blk[e + 1] = S->fps_blk[e] + (m == 0 ? S->fp_blk[e + 1] - S->fp_blk[e] : 0);
     S->fzs_blk[e + 1] = S->fzs_blk[e] + (m == 0 ? S->fz_blk[e + 1] - S->fz_blk[e] : 0);
     if (m == 1) {
@@ -225,6 +234,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       S->plane_max = std::max(S->plane_max, pts);
     } else if (m == 2) {
       S->half_any = true;
+    } else if (m == 4) {
+      S->quarter_any = true;
     } else {
       S->split_any = true;
     }
@@ -239,6 +250,16 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     }
   S->half_lds = (hx + hz + hp) * 16;
   if ((size_t)S->half_lds > (size_t)kLdsMax) return fail(TF_ESIZE, "half-plane tiles exceed the LDS of a block");
+  int qx = 0, qz = 0, qp = 0;
+  for (int e = 0; e < n_ens; ++e)
+    if (S->e_plane[e] == 4) {
+      qx = std::max(qx, ens[e].nx);
+      qz = std::max(qz, ens[e].nz / 4);
+      qp = std::max(qp, (ens[e].nz / 4) * (ens[e].nx / 2 + 1));
+    }
+  S->quarter_lds = (qx + qz + qp) * 16;
+  if ((size_t)S->quarter_lds > (size_t)kLdsMax)
+    return fail(TF_ESIZE, "quarter-plane tiles exceed the LDS of a block");
   return TF_OK;
 }
 
@@ -303,6 +324,7 @@ struct tf_handle {
   int* d_tri = nullptr;
   int* d_pl = nullptr;
   int* d_ph = nullptr;
+  int* d_pq = nullptr;
   int* d_fps = nullptr;
   int* d_fzs = nullptr;
   // recorded trajectory
@@ -343,6 +365,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   int* tri = cv.take<int>(n_ens + 1);
   int* pl = cv.take<int>(n_ens + 1);
   int* ph = cv.take<int>(n_ens + 1);
+  int* pq = cv.take<int>(n_ens + 1);
   int* fps = cv.take<int>(n_ens + 1);
   int* fzs = cv.take<int>(n_ens + 1);
   C.yf = cv.take<double>(S.y_tot);
@@ -370,6 +393,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.far = cv.take<int>(S.n_tot);
   C.far_n = cv.take<int>(2);
   C.uptr = cv.take<const double*>(n_ens);
+  C.upad = cv.take<double>(S.up_tot);
   PState A = carve_state(cv, S.n_tot);
   PState B = carve_state(cv, S.n_tot);
   C.count = cv.take<int>(S.c_tot);
@@ -417,6 +441,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     h->d_tri = tri;
     h->d_pl = pl;
     h->d_ph = ph;
+    h->d_pq = pq;
     h->d_fps = fps;
     h->d_fzs = fzs;
     h->d_ens = (Ens*)C.ens;
@@ -507,7 +532,7 @@ int tf_set_tuning(const tf_tuning* t) {
     return TF_OK;
   }
   if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 3)
+      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
   return TF_OK;
@@ -521,7 +546,7 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     return TF_OK;
   }
   if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 32 || t->inv_plane < 0 ||
-      t->inv_plane > 3)
+      t->inv_plane > 4)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -580,7 +605,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->p_off.assign(n_ens + 1, 0);
   h->c_off.assign(n_ens + 1, 0);
   int y_off = 0, kx_off = 0, kz_off = 0, st_off = 0;
-  long long s_off = 0, row_off = 0, tf_off = 0;
+  long long s_off = 0, row_off = 0, tf_off = 0, up_off = 0;
   // Thomas factors of the y-systems, per Fourier mode (fixed by the mesh):
   // tfac[tf_off + mode * ny + j] = (1 / pivot_j, c'_j)
   std::vector<double2> tfac(S.tf_tot);
@@ -643,12 +668,16 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.fe = T.k_c * std::pow(1.0 + T.e, 0.4);
     E.pe = std::pow(1.0 + T.e, 0.4);
     E.U = T.u_nodes;
+    E.nxp = T.nx + 2;
+    E.up_off = up_off;
+    up_off += 3LL * (T.ny + 1) * T.nz * E.nxp;
     radix_plan(T.nx, &E.fx);
     E.fx.tw_off = S.tw_off.at(T.nx);
     radix_plan(T.nz, &E.fz);
     E.fz.tw_off = S.tw_off.at(T.nz);
     E.fzh = FftPlan{};
-    if (E.plane == 2) radix_plan(T.nz / 2, &E.fzh);  // twiddles: every other one of length nz
+    if (E.plane == 2 || E.plane == 4)
+      radix_plan(T.nz / E.plane, &E.fzh);  // twiddles: every plane-th one of length nz
     const int ny = T.ny;
     double* Y = &yf[y_off];
     for (int j = 0; j <= ny; ++j) Y[j] = T.y_faces[j];
@@ -715,6 +744,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->d_tri, S.tri_blk);
   UP(h->d_pl, S.pl_blk);
   UP(h->d_ph, S.ph_blk);
+  UP(h->d_pq, S.pq_blk);
   UP(h->d_fps, S.fps_blk);
   UP(h->d_fzs, S.fzs_blk);
   UP(h->C.yf, yf);
@@ -732,6 +762,9 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   UP(h->C.uptr, uptr);
   UP(h->C.tfac, tfac);
 #undef UP
+  for (int e = 0; e < n_ens && he == hipSuccess; ++e)
+    he = launch_pad_carrier(h->C.upad + h->eh[e].up_off, ens[e].u_nodes, ens[e].nx, ens[e].ny, ens[e].nz,
+                            h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.stats, 0, sizeof(long long) * S.st_tot, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowq, 0, sizeof(long long) * S.rows, h->stream);
   if (he == hipSuccess) he = hipMemsetAsync(h->C.rowacc, 0, sizeof(longlong2) * S.rows, h->stream);
@@ -772,6 +805,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.d_pl_blk = h->d_pl;
   h->G.ph_blk = h->S.ph_blk.data();
   h->G.d_ph_blk = h->d_ph;
+  h->G.pq_blk = h->S.pq_blk.data();
+  h->G.d_pq_blk = h->d_pq;
   h->G.fps_blk = h->S.fps_blk.data();
   h->G.d_fps_blk = h->d_fps;
   h->G.fzs_blk = h->S.fzs_blk.data();
@@ -779,6 +814,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.plane_any = S.plane_any ? 1 : 0;
   h->G.half_any = S.half_any ? 1 : 0;
   h->G.half_lds = S.half_lds;
+  h->G.quarter_any = S.quarter_any ? 1 : 0;
+  h->G.quarter_lds = S.quarter_lds;
   h->G.pp_any = S.pp_any ? 1 : 0;
   h->G.split_any = S.split_any ? 1 : 0;
   h->G.plane_max = S.plane_max;
@@ -949,8 +986,11 @@ int tf_set_carrier(tf_handle* h, int32_t e, const double* u_nodes) {
   if (e < 0 || e >= h->n_ens) return fail(TF_EINVAL, "ensemble index out of range");
   if (h->traj_len > 0) return fail(TF_ESTATE, "a recorded trajectory is pending (tf_adjoint_step first)");
   h->eh[e].U = u_nodes;
-  // kernels read the pointer from the device table: one tiny kernel in stream
-  // order, no synchronisation, captured graphs stay valid
+  // the step reads the padded copy, refreshed in stream order; the reverse
+  // step reads the field through the device pointer table, replaced by one
+  // tiny kernel.  No synchronisation; captured graphs stay valid.
+  const Ens& E = h->eh[e];
+  HIPCHK(launch_pad_carrier(h->C.upad + E.up_off, u_nodes, E.nx, E.ny, E.nz, h->stream));
   HIPCHK(launch_set_ptr(h->C.uptr + e, u_nodes, h->stream));
   return TF_OK;
 }

@@ -1338,28 +1338,31 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_inv(Ctx C, Ens Eone, in
 }
 
 // ---------------------------------------------------------------------------
-// inverse z and x transforms of one y plane split over two blocks by the
-// parity h of the z row.  With N = nz (a multiple of 4), the rows k = 2r + h
-// of the inverse z transform are the inverse transform of length N/2 of
-//   X[m] + X[m + N/2]                        (h = 0)
-//   (X[m] - X[m + N/2]) exp(2 pi i m / N)     (h = 1),   m < N/2
-// (the radix-2 split of the outputs), so a block holds half the plane in LDS
-// and does half the transforms: twice the blocks, each with 16 waves (at
-// most 128 VGPRs).  Rows 4p + h and 4p + 2 + h then form one complex line of
-// the x transform.
+// inverse z and x transforms of one y plane split over Q blocks (Q = 2 or 4)
+// by the residue h of the z row modulo Q.  With N = nz (a multiple of 2Q),
+// the rows k = Q r + h of the inverse z transform are the inverse transform of
+// length N/Q of
+//   Y_h[m] = exp(2 pi i m h / N) sum_{s<Q} X[m + s N/Q] exp(2 pi i s h / Q),
+// m < N/Q (the radix-Q split of the outputs; for Q = 2: X[m] + X[m + N/2] and
+// (X[m] - X[m + N/2]) exp(2 pi i m / N)), so a block holds 1/Q of the plane in
+// LDS and does 1/Q of the transforms, the fold done while the plane streams
+// in.  The Q blocks of a plane are neighbouring logical blocks (one XCD), so
+// the plane's later reads find it in that XCD's L2.  LDS rows (2p, 2p+1), z
+// rows Q 2p + h and Q (2p + 1) + h, then form one complex line of the x
+// transform.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kHalfThreads, 4) void k_plane_half(Ctx C, Ens Eone, int one,
+template <int Q, int XPTS, int NT>
+__global__ __launch_bounds__(NT, 4) void k_plane_part(Ctx C, Ens Eone, int one,
                                                              const int* __restrict__ blk_off, int blk0,
                                                              double* __restrict__ phi_out, long long phi_shift,
                                                              int* __restrict__ far_reset, int bump) {
+  static_assert(Q == 2 || Q == 4, "two or four blocks per plane");
   if (far_reset && blockIdx.x == 0) {
     if (threadIdx.x == 0) *far_reset = 0;
     if (bump)
       for (int e = threadIdx.x; e < C.n_ens; e += blockDim.x) C.stats[C.ens[e].st_off + ST_STEPS] += 1;
   }
   extern __shared__ double2 lds[];
-  // the two halves of a plane are neighbouring logical blocks: same XCD, so
-  // the second read of the plane's spectrum finds it in that XCD's L2
   const int b = (int)xcd_block(blockIdx.x, gridDim.x);
   Ens E;
   int lb;
@@ -1372,43 +1375,77 @@ __global__ __launch_bounds__(kHalfThreads, 4) void k_plane_half(Ctx C, Ens Eone,
     E = C.ens[e];
     lb = gb - blk_off[e];
   }
-  if (E.plane != 2) return;
-  const int j = lb >> 1, h = lb & 1;
-  const int nx = E.nx, nz = E.nz, nh = E.nh, nzh = nz >> 1, nzq = nz >> 2, half = nx >> 1, tid = threadIdx.x;
-  double2* twz = lds;      // exp(-2 pi i t / (N/2)) = exp(-2 pi i 2t / N)
-  double2* twx = twz + nzh;
-  double2* pl = twx + nx;  // [nz/2][nh]
-  const double2 tzv = C.tw[E.fz.tw_off + min(2 * tid, nz - 2)];
+  if (E.plane != Q) return;
+  const int j = lb / Q, h = lb - j * Q;
+  const int nx = E.nx, nz = E.nz, nh = E.nh, nzp = nz / Q, npair = nzp >> 1, half = nx >> 1, tid = threadIdx.x;
+  double2* twz = lds;      // exp(-2 pi i t / (N/Q)) = exp(-2 pi i Q t / N)
+  double2* twx = twz + nzp;
+  double2* pl = twx + nx;  // [nz/Q][nh]
+  const double2 tzv = C.tw[E.fz.tw_off + min(Q * tid, nz - Q)];
   const double2 txv = C.tw[E.fx.tw_off + min(tid, nx - 1)];
   const double2* sp = C.spec + E.s_off + (long long)j * nz * E.nhp;
-  const double2* twn = C.tw + E.fz.tw_off;
-  const long long shift = (long long)nzh * E.nhp;
+  const double2* twn = C.tw + E.fz.tw_off;   // exp(-2 pi i t / N), t < N
+  const long long shift = (long long)nzp * E.nhp;
   const unsigned mnh = magic32(nh);
-  struct Fold {
-    double2 a, b, w;
-  };
-  staged_copy<4>(
-      nzh * nh, tid, kHalfThreads,
-      [&](int t) {
-        const int m = fdiv32(t, mnh, nh), i = t - m * nh;
-        const double2* s = sp + m * E.nhp + i;
-        return Fold{s[0], s[shift], h ? twn[m] : make_double2(1.0, 0.0)};
-      },
-      [&](int t, Fold v) {
-        if (h == 0) {
-          pl[t] = make_double2(v.a.x + v.b.x, v.a.y + v.b.y);
-        } else {  // (a - b) conj(w), w = exp(-2 pi i m / N)
-          const double dx = v.a.x - v.b.x, dy = v.a.y - v.b.y;
-          pl[t] = make_double2(dx * v.w.x + dy * v.w.y, dy * v.w.x - dx * v.w.y);
-        }
-      });
-  if (tid < nzh) twz[tid] = tzv;
+  if constexpr (Q == 2) {
+    struct Fold {
+      double2 a, b, w;
+    };
+    staged_copy<4>(
+        nzp * nh, tid, NT,
+        [&](int t) {
+          const int m = fdiv32(t, mnh, nh), i = t - m * nh;
+          const double2* s = sp + m * E.nhp + i;
+          return Fold{s[0], s[shift], h ? twn[m] : make_double2(1.0, 0.0)};
+        },
+        [&](int t, Fold v) {
+          if (h == 0) {
+            pl[t] = make_double2(v.a.x + v.b.x, v.a.y + v.b.y);
+          } else {  // (a - b) conj(w), w = exp(-2 pi i m / N)
+            const double dx = v.a.x - v.b.x, dy = v.a.y - v.b.y;
+            pl[t] = make_double2(dx * v.w.x + dy * v.w.y, dy * v.w.x - dx * v.w.y);
+          }
+        });
+  } else {
+    struct Fold {
+      double2 a0, a1, a2, a3, w;
+    };
+    staged_copy<2>(
+        nzp * nh, tid, NT,
+        [&](int t) {
+          const int m = fdiv32(t, mnh, nh), i = t - m * nh;
+          const double2* s = sp + m * E.nhp + i;
+          return Fold{s[0], s[shift], s[2 * shift], s[3 * shift], h ? twn[m * h] : make_double2(1.0, 0.0)};
+        },
+        [&](int t, Fold v) {
+          // sum_s X_s i^(s h): the radix-4 butterfly output h
+          const double2 p02 = make_double2(v.a0.x + v.a2.x, v.a0.y + v.a2.y);
+          const double2 m02 = make_double2(v.a0.x - v.a2.x, v.a0.y - v.a2.y);
+          const double2 p13 = make_double2(v.a1.x + v.a3.x, v.a1.y + v.a3.y);
+          const double2 m13 = make_double2(v.a1.x - v.a3.x, v.a1.y - v.a3.y);
+          double2 y;
+          if (h == 0) {
+            y = make_double2(p02.x + p13.x, p02.y + p13.y);
+          } else if (h == 2) {
+            y = make_double2(p02.x - p13.x, p02.y - p13.y);
+          } else if (h == 1) {  // m02 + i m13
+            y = make_double2(m02.x - m13.y, m02.y + m13.x);
+          } else {              // m02 - i m13
+            y = make_double2(m02.x + m13.y, m02.y - m13.x);
+          }
+          if (h) {  // times conj(w), w = exp(-2 pi i m h / N)
+            y = make_double2(y.x * v.w.x + y.y * v.w.y, y.y * v.w.x - y.x * v.w.y);
+          }
+          pl[t] = y;
+        });
+  }
+  if (tid < nzp) twz[tid] = tzv;
   if (tid < nx) twx[tid] = txv;
   __syncthreads();
-  ip_fft<true, kHalfThreads, kHalfPts>(pl, nh, 1, nh, E.fzh, twz, tid);
-  // x transforms of LDS rows (2p, 2p+1) -- z rows 4p + h, 4p + 2 + h -- paired
-  // as one complex line, packed by the first pass as in k_plane_inv
-  const int npt = nzq * nx;
+  ip_fft<true, NT, kHalfPts>(pl, nh, 1, nh, E.fzh, twz, tid);
+  // x transforms of LDS rows (2p, 2p+1) paired as one complex line, packed by
+  // the first pass as in k_plane_inv
+  const int npt = npair * nx;
   const unsigned mnx = magic32(nx);
   auto packed = [=](int p, int i) {
     const int m = i <= half ? i : nx - i;
@@ -1417,14 +1454,14 @@ __global__ __launch_bounds__(kHalfThreads, 4) void k_plane_half(Ctx C, Ens Eone,
     if (i < half) return make_double2(A.x - B.y, A.y + B.x);
     return make_double2(A.x + B.y, B.x - A.y);
   };
-  ip_fft<true, kHalfThreads, kHalfXPts>(pl, nzq, 2 * nh, 1, E.fx, twx, tid, packed);
+  ip_fft<true, NT, XPTS>(pl, npair, 2 * nh, 1, E.fx, twx, tid, packed);
   const double sc = (1.0 / (double)nz) * (1.0 / (double)nx);
   double* out = phi_out + (E.c_off - phi_shift) + (long long)j * nz * nx;
-  for (int t = tid; t < npt; t += kHalfThreads) {
+  for (int t = tid; t < npt; t += NT) {
     const int p = fdiv32(t, mnx, nx), i = t - p * nx;
     const double2 v = pl[(2 * p) * nh + i];
-    out[(4 * p + h) * nx + i] = v.x * sc;
-    out[(4 * p + 2 + h) * nx + i] = v.y * sc;
+    out[(Q * 2 * p + h) * nx + i] = v.x * sc;
+    out[(Q * (2 * p + 1) + h) * nx + i] = v.y * sc;
   }
 }
 
@@ -1549,9 +1586,9 @@ __device__ double ssm_dq(const Ens& E, double q, double d, double un, int id, un
 
 template <bool PP>
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
-                                         int p, int c, signed char* __restrict__ wall_rec) {
+                                         int p, int c, int ra, int rb, signed char* __restrict__ wall_rec) {
   Fwd F;
-  eval_particle<true, PP>(C, E, in, s, p, c, F);
+  eval_particle<true, PP>(C, E, in, s, p, c, ra, rb, F);
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int j = F.j;
   const double q = F.qc, d = F.d;  // charge after any particle-particle exchange
@@ -1653,6 +1690,24 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   pair_count(C.pair_cnt, pnew);
 }
 
+// Slots [ra, rb) of cell c, from the sorted keys of the wave's lanes (which
+// hold consecutive slots s, so a cell's slots are a run of equal keys).  A run
+// that reaches the first or last lane may continue in the neighbouring wave:
+// then ra or rb is -1 and the caller reads the cell start.  Every lane of the
+// wave must take part.
+__device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int kp = __shfl_up(c, 1, 64);
+  const unsigned long long heads = __ballot(lane == 0 || kp != c);
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all for lane 63)
+  const int hl = 63 - __clzll(heads & upto);              // lane 0 is always a head
+  const unsigned long long after = heads & ~upto;
+  const int el = after ? __ffsll((long long)after) - 1 : 64;
+  const int s0 = s - lane;
+  *ra = hl == 0 ? -1 : s0 + hl;
+  *rb = el == 64 ? -1 : s0 + el;
+}
+
 // four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat
 // the few spilled registers
 template <bool PP>
@@ -1662,12 +1717,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
     C.rs_old[r] = C.rs_new[r];
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
-  if (s < C.n_tot) {
+  const bool act = s < C.n_tot;
+  const int c = act ? C.skey[s] : 0x7fffffff;
+  // the slots of the lane's cell from the wave's keys (every lane takes part)
+  int ra, rb;
+  cell_run(s, c, &ra, &rb);
+  if (act) {
     const int p = C.perm[s];
     if (perm_rec) perm_rec[s] = p;
-    const int c = C.skey[s];
+    if (ra < 0) ra = C.start[c];
+    if (rb < 0) rb = C.start[c + 1];
     if (one) {
-      push_one<PP>(C, Eone, in, out, s, p, c, wall_rec);
+      push_one<PP>(C, Eone, in, out, s, p, c, ra, rb, wall_rec);
     } else {
       const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
       // waterfall over the ensembles present in this wave (usually one)
@@ -1675,7 +1736,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
       while (!done) {
         const int e = __builtin_amdgcn_readfirstlane(e_lane);
         if (e_lane == e) {
-          push_one<PP>(C, C.ens[e], in, out, s, p, c, wall_rec);
+          push_one<PP>(C, C.ens[e], in, out, s, p, c, ra, rb, wall_rec);
           done = true;
         }
       }
@@ -1843,6 +1904,7 @@ hipError_t launch_poisson(const Ctx& C0, const LaunchGeo& G, int e0, int e1, con
   // far list and counts the step.
   const bool whole = one ? Eone.plane == 1 : G.plane_any != 0;
   const bool halves = one ? Eone.plane == 2 : G.half_any != 0;
+  const bool quarters = one ? Eone.plane == 4 : G.quarter_any != 0;
   const bool split = one ? Eone.plane == 0 : G.split_any != 0;
   int* fr = far_reset;
   if (whole) {
@@ -1857,7 +1919,17 @@ hipError_t launch_poisson(const Ctx& C0, const LaunchGeo& G, int e0, int e1, con
     const int p0 = G.ph_blk[e0], np = G.ph_blk[e1] - p0;
     const size_t lp = (size_t)G.half_lds;
     if (np > 0) {
-      k_plane_half<<<np, kHalfThreads, lp, st>>>(C, Eone, one, G.d_ph_blk, p0, phi_out, phi_shift, fr, 1);
+      k_plane_part<2, kHalfXPts, kHalfThreads><<<np, kHalfThreads, lp, st>>>(C, Eone, one, G.d_ph_blk, p0, phi_out,
+                                                                             phi_shift, fr, 1);
+      fr = nullptr;
+    }
+  }
+  if (quarters) {
+    const int p0 = G.pq_blk[e0], np = G.pq_blk[e1] - p0;
+    const size_t lp = (size_t)G.quarter_lds;
+    if (np > 0) {
+      k_plane_part<4, kQuarterXPts, kQuarterThreads><<<np, kQuarterThreads, lp, st>>>(
+          C, Eone, one, G.d_pq_blk, p0, phi_out, phi_shift, fr, 1);
       fr = nullptr;
     }
   }
@@ -1974,8 +2046,28 @@ hipError_t launch_record(int* skey_d, const int* skey, long long n, int* start_d
 
 __global__ void k_set_ptr(const double** slot, const double* value) { *slot = value; }
 
+// carrier copy with periodic ghost nodes: rows of nx nodes -> rows of nxp =
+// nx + 2 (nodes 0..nx-1, then nodes 0 and 1)
+__global__ __launch_bounds__(kBlock) void k_pad_carrier(double* __restrict__ dst, const double* __restrict__ src,
+                                                        int nx, int nxp, long long rows) {
+  const long long total = rows * nxp;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
+    const long long r = t / nxp;
+    const int i = (int)(t - r * nxp);
+    dst[t] = src[r * nx + (i < nx ? i : i - nx)];
+  }
+}
+
 hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st) {
   k_set_ptr<<<1, 1, 0, st>>>(slot, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_carrier(double* dst, const double* src, int nx, int ny, int nz, hipStream_t st) {
+  const long long rows = 3LL * (ny + 1) * nz;
+  const long long total = rows * (nx + 2);
+  const int nb = (int)std::min<long long>((total + kBlock - 1) / kBlock, 8192);
+  k_pad_carrier<<<nb, kBlock, 0, st>>>(dst, src, nx, nx + 2, rows);
   return hipGetLastError();
 }
 

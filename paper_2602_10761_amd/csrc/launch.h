@@ -29,8 +29,10 @@ struct LaunchGeo {
   int pp_any;      // some ensemble has 4-way coupling on
   int plane_any, half_any, split_any;  // some ensembles with inverse transforms per plane /
                                        // per half plane / by the z and x kernels
+  int quarter_any;                     // ... per quarter plane
   int plane_max;   // largest nz (nx/2 + 1) over the ensembles transformed per plane
   int half_lds;    // LDS bytes of the half-plane kernel
+  int quarter_lds; // LDS bytes of the quarter-plane kernel
   const int* fp_blk;  // x transforms and the fused sort: kPairsPerBlock row pairs per block
   const int* fz_blk;
   const int* tri_blk;
@@ -41,6 +43,8 @@ struct LaunchGeo {
   const int* d_pl_blk;
   const int* ph_blk;  // per half plane: two blocks per y plane
   const int* d_ph_blk;
+  const int* pq_blk;  // per quarter plane: four blocks per y plane
+  const int* d_pq_blk;
   const int* fps_blk;  // fp_blk / fz_blk restricted to the ensembles whose inverse
   const int* d_fps_blk;  // transforms run as the z then x kernels
   const int* fzs_blk;
@@ -69,6 +73,9 @@ hipError_t launch_record(int* skey_d, const int* skey, long long n, int* start_d
                          const double* phi, long long nc, hipStream_t st);
 // *slot = value, in stream order (a kernel: usable between captured graphs)
 hipError_t launch_set_ptr(const double** slot, const double* value, hipStream_t st);
+// copy of a carrier field [3][ny+1][nz][nx] with two periodic ghost nodes per
+// node row ([3][ny+1][nz][nx+2]), in stream order
+hipError_t launch_pad_carrier(double* dst, const double* src, int nx, int ny, int nz, hipStream_t st);
 // 2-way coupling source per cell from the push's per-slot drag forces
 hipError_t launch_source(const Ctx& C, hipStream_t st);
 hipError_t launch_bin(const Ctx& C, const PState& S, long long n0, long long n1, hipStream_t st);

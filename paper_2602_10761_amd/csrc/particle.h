@@ -69,9 +69,10 @@ __device__ __forceinline__ PPHit pp_pair(int pj, const PState& in, double kpp, d
 }
 
 // PP: compiled with the 4-way coupling (particle-particle collisions)
+// [ra, rb): the slots of cell c (its particles, s among them)
 template <bool SORTED, bool PP = false>
 __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
-                                              Fwd& F) {
+                                              int ra, int rb, Fwd& F) {
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int cl = c - (int)E.c_off;
   int jk, i, j, k;
@@ -97,31 +98,34 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   const int plane = (ny + 1) * nxz;
   const int n00 = (j * nz + k) * nx, n01 = (j * nz + k1) * nx;
   const int n10 = n00 + nxz, n11 = n01 + nxz;
+  // nodes i and i + 1 of the four node rows of the cell, each pair one
+  // 16-byte load from the padded copy (its ghost nodes make the periodic row
+  // end an ordinary load): twelve loads with no branch between them, all in
+  // flight together
   double uc[3];
+  {
+    const int nxp = E.nxp, rowp = nz * nxp, planep = (ny + 1) * rowp;
+    const int p00 = (j * nz + k) * nxp + i, p01 = (j * nz + k1) * nxp + i;
+    const double* __restrict__ ub = C.upad + E.up_off;
+    d2u u[3][4];
 #pragma unroll
-  for (int cc = 0; cc < 3; ++cc) {
-    const double* __restrict__ b = C.uptr[E.ei] + cc * plane;
-    // nodes i and i + 1 of a row as one 16-byte load (8-byte aligned) away
-    // from the periodic end of the row: half the gather instructions
-    d2u u00, u01, u10, u11;
-    if (i1 == i + 1) {
-      u00 = *reinterpret_cast<const d2u*>(b + n00 + i);
-      u01 = *reinterpret_cast<const d2u*>(b + n01 + i);
-      u10 = *reinterpret_cast<const d2u*>(b + n10 + i);
-      u11 = *reinterpret_cast<const d2u*>(b + n11 + i);
-    } else {
-      u00 = d2u{b[n00 + i], b[n00 + i1]};
-      u01 = d2u{b[n01 + i], b[n01 + i1]};
-      u10 = d2u{b[n10 + i], b[n10 + i1]};
-      u11 = d2u{b[n11 + i], b[n11 + i1]};
+    for (int cc = 0; cc < 3; ++cc) {
+      const double* __restrict__ b = ub + cc * planep;
+      u[cc][0] = *reinterpret_cast<const d2u*>(b + p00);
+      u[cc][1] = *reinterpret_cast<const d2u*>(b + p01);
+      u[cc][2] = *reinterpret_cast<const d2u*>(b + p00 + rowp);
+      u[cc][3] = *reinterpret_cast<const d2u*>(b + p01 + rowp);
     }
-    const double c00 = u00.x * (1.0 - tx) + u00.y * tx;
-    const double c01 = u01.x * (1.0 - tx) + u01.y * tx;
-    const double c10 = u10.x * (1.0 - tx) + u10.y * tx;
-    const double c11 = u11.x * (1.0 - tx) + u11.y * tx;
-    const double c0 = c00 * (1.0 - tz) + c01 * tz;
-    const double c1 = c10 * (1.0 - tz) + c11 * tz;
-    uc[cc] = c0 * (1.0 - ty) + c1 * ty;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const double c00 = u[cc][0].x * (1.0 - tx) + u[cc][0].y * tx;
+      const double c01 = u[cc][1].x * (1.0 - tx) + u[cc][1].y * tx;
+      const double c10 = u[cc][2].x * (1.0 - tx) + u[cc][2].y * tx;
+      const double c11 = u[cc][3].x * (1.0 - tx) + u[cc][3].y * tx;
+      const double c0 = c00 * (1.0 - tz) + c01 * tz;
+      const double c1 = c10 * (1.0 - tz) + c11 * tz;
+      uc[cc] = c0 * (1.0 - ty) + c1 * ty;
+    }
   }
 
   // Gauss part: cell-centred E = -grad(phi), Gauss-linear, phi = 0 on the walls
@@ -131,15 +135,13 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   const double pc = ph[cl];
   const double Ex = -(ph[n00 + i1] - ph[n00 + im]) * E.inv_2dx;
   const double Ez = -(ph[n01 + i] - ph[(j * nz + km) * nx + i]) * E.inv_2dz;
-  double ftop = 0.0, fbot = 0.0;
-  if (j < ny - 1) {
-    const double pn = ph[n00 + nxz + i];
-    ftop = pc + C.beta[E.y_off + j + 1] * (pn - pc);
-  }
-  if (j > 0) {
-    const double pm = ph[n00 - nxz + i];
-    fbot = pm + C.beta[E.y_off + j] * (pc - pm);
-  }
+  // wall-normal neighbours from clamped rows (no branch around the loads);
+  // the wall faces take phi = 0
+  const bool has_top = j < ny - 1, has_bot = j > 0;
+  const double pn = ph[n00 + (has_top ? nxz : 0) + i];
+  const double pm = ph[n00 - (has_bot ? nxz : 0) + i];
+  const double ftop = has_top ? pc + C.beta[E.y_off + j + 1] * (pn - pc) : 0.0;
+  const double fbot = has_bot ? pm + C.beta[E.y_off + j] * (pc - pm) : 0.0;
   const double Ey = -(ftop - fbot) * idy[j];
 
   // near field: Coulomb's law with the other particles of the cell, ascending id
@@ -156,12 +158,36 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
     }
   };
   {
-    const int a = C.start[c], b = C.start[c + 1];
-    for (int t = a; t < b; ++t) {
-      if (t == s) continue;
-      if constexpr (SORTED) {
-        coulomb(C.sx[t], C.sy[t], C.sz[t], C.sq[t]);
-      } else {
+    const int a = ra, b = rb;
+    if constexpr (SORTED) {
+      // The lanes of a wave hold consecutive slots and a cell's particles
+      // are consecutive slots, so most cell mates sit in this wave: their
+      // position and charge come from their lanes (cross-lane reads), the
+      // others (cells across the wave's ends) from memory.  Mates in
+      // ascending id, as in the plain loop; the loop runs while some lane of
+      // the wave has a mate left.
+      const int lane = (int)(threadIdx.x & 63u);
+      const int s0 = s - lane;
+      const int n = b - a;
+      for (int kk = 0; __any(kk < n); ++kk) {
+        const int t = a + kk;
+        const int src = t - s0;
+        const bool inw = src >= 0 && src < 64;
+        double ox = __shfl(x, src & 63, 64), oy = __shfl(y, src & 63, 64);
+        double oz = __shfl(z, src & 63, 64), oq = __shfl(q, src & 63, 64);
+        if (kk < n && t != s) {
+          if (!inw) {
+            ox = C.sx[t];
+            oy = C.sy[t];
+            oz = C.sz[t];
+            oq = C.sq[t];
+          }
+          coulomb(ox, oy, oz, oq);
+        }
+      }
+    } else {
+      for (int t = a; t < b; ++t) {
+        if (t == s) continue;
         const int pj = C.perm[t];
         coulomb(in.x[pj], in.y[pj], in.z[pj], in.q[pj]);
       }

@@ -38,8 +38,8 @@ struct Ens {
   int kx_off, kz_off;
   int st_off;        // first int64 of the statistics block
   int wz, tm;        // tile shapes: z-transform columns, tridiagonal modes per block
-  int plane;         // inverse transforms: 1 one block per y plane, 2 two blocks per plane
-                     // (z-row parity), 0 z then x kernels
+  int plane;         // inverse transforms: 1 one block per y plane, 2 or 4 blocks per plane
+                     // (z-row residue mod 2 or 4), 0 z then x kernels
   double lx, ly, lz, dx, dz;
   double dt, rr, kc, dU, e, cel, gp0, gp1, gp2, un_bin;
   // derived on the host
@@ -54,8 +54,10 @@ struct Ens {
   double sdq0, smu0, ssig0, sgam0, scsat, sd0, sun0;  // SSM reference impact
   double pe;                                // (1 + e)^(2/5)
   const double* U;   // carrier velocity nodes [3][ny+1][nz][nx] at tf_init (kernels read Ctx::uptr)
+  long long up_off;  // first entry of the ensemble's padded carrier copy in Ctx::upad
+  int nxp;           // padded node-row length nx + 2 (nodes 0..nx-1, then nodes 0 and 1 again)
   FftPlan fx, fz;
-  FftPlan fzh;       // length nz/2 (plane split over two blocks)
+  FftPlan fzh;       // length nz/plane (plane split over 2 or 4 blocks)
 };
 
 // statistics block (int64) of one ensemble; the per-height sums live per (j,k)
@@ -81,6 +83,12 @@ constexpr int kPlanePts = 10240;
 constexpr int kHalfThreads = 1024;
 constexpr int kHalfPts = 4736;
 constexpr int kHalfXPts = 4096;
+// split over four blocks (z-row residue mod 4): the same z-transform limit,
+// and (nz/8) nx points of the x transforms
+constexpr int kQuarterXPts = 4736;
+// threads per quarter-plane block: two blocks (and their 78 KB of LDS for the
+// 192 x 192 plane) share a CU at up to 128 VGPRs
+constexpr int kQuarterThreads = 512;
 // z transforms: largest tile of wz columns times nz points
 constexpr int kZPts = 2048;
 
@@ -119,6 +127,9 @@ struct Ctx {
   int* far;                  // [n_tot]    movers beyond a full mover list
   int* far_n;                // [2]        [0]: entries (the push appends; reset before the next push)
   const double** uptr;       // [n_ens]    carrier field of each ensemble (replaced by tf_set_carrier in stream order)
+  // the carrier of every ensemble copied with periodic ghost nodes, [3][ny+1][nz][nx+2]:
+  // the x-neighbour pair (i, i+1) of a node row is always one 16-byte load
+  double* upad;
   int* scan_part;            // scan block partials
   double2* spec;             // spectra
   double* phi;               // [c_tot]   potential of the latest step

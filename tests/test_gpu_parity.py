@@ -69,10 +69,28 @@ def test_poisson_parity(shape, stretch):
     sim.close()
 
 
-@pytest.mark.parametrize("shape", [(8, 6, 12), (24, 20, 40), (32, 32, 32), (128, 128, 128), (4, 2, 4)])
+def inverse_layouts(nx, nz):
+    """Layouts of the inverse transforms that fit a mesh: 1 one block per y
+    plane, 2 two blocks (z-row parity), 4 four blocks (z-row residue mod 4),
+    3 z then x kernels."""
+    nh = nx // 2 + 1
+    modes = []
+    if nz * nh <= 10240 and 16 * (nx + nz + nz * nh) <= 163840:
+        modes.append(1)
+    if nz % 4 == 0 and (nz // 2) * nh <= 4736 and (nz // 4) * nx <= 4096:
+        modes.append(2)
+    modes.append(3)
+    if nz % 8 == 0 and (nz // 4) * nh <= 4736 and (nz // 8) * nx <= 4736:
+        modes.append(4)
+    return modes
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 12), (24, 20, 40), (32, 32, 32), (128, 128, 128), (4, 2, 4),
+                                   (192, 160, 192), (160, 24, 200), (64, 10, 48)])
 def test_poisson_inverse_layouts(shape):
-    """The three layouts of the inverse transforms (one block per y plane, two
-    blocks per plane by z-row parity, z then x kernels) against the oracle."""
+    """Every layout of the inverse transforms that fits the mesh (one block per
+    y plane, two or four blocks per plane by z-row residue, z then x kernels)
+    against the oracle."""
     from paper_2602_10761_amd import runtime as R
     nx, ny, nz = shape
     ens = W.make_ensemble(W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=10, stretch=2.0, n_modes=4))
@@ -82,7 +100,7 @@ def test_poisson_inverse_layouts(shape):
     ref = O.poisson(g, Q)
     phis = {}
     try:
-        for mode in (1, 2, 3):
+        for mode in inverse_layouts(nx, nz):
             say("poisson layout", shape, mode)
             R.set_tuning(inv_plane=mode)
             sim = sim_of(ens)
@@ -97,13 +115,17 @@ def test_poisson_inverse_layouts(shape):
 
 
 def test_inverse_layout_refused():
-    """Two blocks per plane need nz % 4 == 0."""
+    """Two blocks per plane need nz % 4 == 0, four need nz % 8 == 0."""
     from paper_2602_10761_amd import runtime as R
     ens = W.make_ensemble(W.CONFIGS[1].replace(nx=16, ny=8, nz=10, n_particles=10))
+    ens4 = W.make_ensemble(W.CONFIGS[1].replace(nx=16, ny=8, nz=12, n_particles=10))
     try:
         R.set_tuning(inv_plane=2)
         with pytest.raises(R.TriboError, match="nz % 4"):
             sim_of(ens)
+        R.set_tuning(inv_plane=4)
+        with pytest.raises(R.TriboError, match="nz % 8"):
+            sim_of(ens4)
     finally:
         R.set_tuning()
 
@@ -360,12 +382,15 @@ def test_batched_equals_plain():
              W.CONFIGS[1].replace(nx=256, ny=6, nz=96, n_particles=3000, v_jitter=2.0),
              # 4-way coupling on for this one only (the others run the collision-enabled push)
              W.CONFIGS[1].replace(re_tau=2.0, nx=4, ny=4, nz=4, n_particles=600, precharge=0.3, v_jitter=1.0,
-                                  d_choices=(0.5, 1.0), density_ratio=50.0, pp=1, k_pp=2.0)]
+                                  d_choices=(0.5, 1.0), density_ratio=50.0, pp=1, k_pp=2.0),
+             W.CONFIGS[1].replace(re_tau=100.0, nx=64, ny=10, nz=48, n_particles=4000, v_jitter=2.0, precharge=0.1)]
     ens = [W.make_ensemble(s, 4, 0, sub=m) for m, s in enumerate(specs)]
     from paper_2602_10761_amd import runtime as R
     # the first one transformed per whole plane, the fifth by the z and x
-    # kernels, the others per half plane
+    # kernels, the last per quarter plane, the others per half plane
     R.set_tuning_class(16, 24, 32, inv_plane=1)
+    R.set_tuning_class(256, 6, 96, inv_plane=3)
+    R.set_tuning_class(64, 10, 48, inv_plane=4)
     try:
         sim = sim_of(ens, graphs=True, source=True)
         sim.step(9)
@@ -379,6 +404,8 @@ def test_batched_equals_plain():
             s1.close()
     finally:
         R.set_tuning_class(16, 24, 32)
+        R.set_tuning_class(256, 6, 96)
+        R.set_tuning_class(64, 10, 48)
     for e, E in enumerate(ens):
         st, ss, fs = plain[e]
         np.testing.assert_array_equal(batched[e][2], fs)
