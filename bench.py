@@ -165,7 +165,7 @@ def timed_steps(torch, sim, k):
 def batched_vs_plain(torch, W, R, autotune, steps, log):
     ens = W.make_workload(4)
     n_tot = sum(E.n for E in ens)
-    autotune.ensure_tuned(autotune.meshes_of(ens))
+    autotune.ensure_tuned_workload(ens)
     log(f"batched: {len(ens)} ensembles, {n_tot} particles")
     sim = R.TriboSim(ens, graphs=True)
     sim.step(3)
@@ -292,7 +292,7 @@ def plain_run(torch, W, R, autotune, config, args, log):
     ens = W.make_workload(config)[0]
     m = ens.mesh
     log(f"workload config {config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
-    tuned = autotune.ensure_tuned(autotune.meshes_of([ens]))
+    tuned = autotune.ensure_tuned_workload([ens])
     log(f"tiles: {tuned}")
     sim = R.TriboSim([ens], device="cuda:0", graphs=args.graphs)
     sim.step(args.warmup)

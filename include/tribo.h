@@ -322,7 +322,10 @@ int tf_set_tuning(const tf_tuning* t);
 /* Tile shapes for the ensembles of one mesh-size class (nx, ny, nz); they take
  * precedence over tf_set_tuning for those ensembles (t == NULL removes the
  * entry).  Ensembles of different classes in one handle keep their own tiles
- * within the same launches. */
+ * within the same launches.  The sort's member capacity is one per handle:
+ * the class's sort_cap (>= 0 here, 0 = no choice) applies when every ensemble
+ * of the handle has that mesh and tf_set_tuning set none; a handle with
+ * several mesh classes takes the built-in rule over all its row pairs. */
 int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t);
 
 void tf_destroy(tf_handle* h);

@@ -74,7 +74,9 @@ struct Sizes {
   long long n_tot = 0, c_tot = 0, s_tot = 0, rows = 0, np_max = 0;
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
   int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
+  int sort_cap = 0;             // member capacity of the fused sort for this handle
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
+  std::vector<int> tf_src;      // ensemble whose factor table an ensemble uses (the first of its mesh)
   long long up_tot = 0;         // padded carrier copies (doubles)
   std::vector<int> e_wz, e_tm;  // per-ensemble tile shapes
   std::vector<int> fp_blk, fz_blk, tri_blk, pl_blk, ph_blk, pq_blk;
@@ -88,6 +90,7 @@ struct Sizes {
 
 int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   if (!ens || n_ens < 1 || n_ens > 4096) return fail(TF_EINVAL, "n_ens must be in [1, 4096]");
+  S->tf_src.clear();
   S->fp_blk.assign(n_ens + 1, 0);
   S->fz_blk.assign(n_ens + 1, 0);
   S->pl_blk.assign(n_ens + 1, 0);
@@ -131,7 +134,16 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->np_max = std::max<long long>(S->np_max, E.n_particles);
     S->c_tot += ncell;
     S->s_tot += (long long)E.ny * E.nz * nhp;
-    S->tf_tot += (long long)E.ny * E.nz * nh;
+    // ensembles on the same mesh (sizes, lengths, y faces) share one factor table
+    int src = e;
+    for (int o = 0; o < e && src == e; ++o) {
+      const tf_ensemble& F = ens[o];
+      if (F.nx == E.nx && F.ny == E.ny && F.nz == E.nz && F.lx == E.lx && F.lz == E.lz &&
+          std::memcmp(F.y_faces, E.y_faces, sizeof(double) * (E.ny + 1)) == 0)
+        src = S->tf_src[o];
+    }
+    S->tf_src.push_back(src);
+    if (src == e) S->tf_tot += (long long)E.ny * E.nz * nh;
     S->up_tot += 3LL * (E.ny + 1) * E.nz * (E.nx + 2);
     S->rows += (long long)E.ny * E.nz;
     S->y_tot += E.ny + 1;
@@ -156,6 +168,13 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   std::vector<int> want_plane(n_ens, 0);
   S->wz = 1;
   S->tri_rows = 1;
+  // the fused sort holds one member capacity per handle: the global choice,
+  // else the one set for the mesh class when every ensemble has that mesh
+  // (a batch of several classes takes the built-in rule over the whole batch)
+  S->sort_cap = g_tune.sort_cap;
+  bool one_class = true;
+  for (int e = 1; e < n_ens; ++e)
+    one_class = one_class && ens[e].nx == ens[0].nx && ens[e].ny == ens[0].ny && ens[e].nz == ens[0].nz;
   for (int e = 0; e < n_ens; ++e) {
     const tf_ensemble& E = ens[e];
     tf_tuning t = g_tune;
@@ -164,6 +183,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       if (it->second.fz_cols > 0) t.fz_cols = it->second.fz_cols;
       if (it->second.tri_modes > 0) t.tri_modes = it->second.tri_modes;
       if (it->second.inv_plane > 0) t.inv_plane = it->second.inv_plane;
+      if (g_tune.sort_cap == 0 && one_class && it->second.sort_cap > 0) S->sort_cap = it->second.sort_cap;
     }
     want_plane[e] = t.inv_plane;
     const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
@@ -545,8 +565,8 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     g_class_tune.erase(key);
     return TF_OK;
   }
-  if (t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 || t->tri_modes > 32 || t->inv_plane < 0 ||
-      t->inv_plane > 4)
+  if (t->sort_cap < 0 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
+      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -622,7 +642,8 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     E.p_off = h->p_off[e];
     E.c_off = h->c_off[e];
     E.s_off = s_off;
-    E.tf_off = tf_off;
+    // (a mesh seen before shares that ensemble's factor table)
+    E.tf_off = S.tf_src[e] == e ? tf_off : h->eh[S.tf_src[e]].tf_off;
     E.row_off = row_off;
     E.y_off = y_off;
     E.ei = e;
@@ -702,7 +723,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     h->p_off[e + 1] = h->p_off[e] + T.n_particles;
     h->c_off[e + 1] = h->c_off[e] + (long long)T.nx * T.ny * T.nz;
     s_off += (long long)ny * T.nz * E.nhp;
-    {
+    if (S.tf_src[e] == e) {
       const int nm = E.nh * T.nz;
       const double* AM = &am[y_off];
       const double* AP = &ap[y_off];
@@ -794,7 +815,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.wz = S.wz;
   h->G.ny_max = S.ny_max;
   h->G.tri_rows = S.tri_rows;
-  h->G.sort_cap = g_tune.sort_cap;
+  h->G.sort_cap = S.sort_cap;
   h->G.fp_blk = h->S.fp_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
   h->G.tri_blk = h->S.tri_blk.data();

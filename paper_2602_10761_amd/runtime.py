@@ -109,9 +109,10 @@ def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0, inv_plan
     _check(lib().tf_set_tuning(ctypes.byref(t)))
 
 
-def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0):
+def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0,
+                     sort_cap: int = 0):
     """Tile shapes for ensembles of mesh size (nx, ny, nz) in later TriboSims."""
-    t = TfTuning(0, fz_cols, tri_modes, inv_plane)
+    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane)
     _check(lib().tf_set_tuning_class(nx, ny, nz, ctypes.byref(t)))
 
 

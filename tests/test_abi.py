@@ -142,3 +142,19 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f in cls._fields_:
             assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{name}.{f[0]}"
+
+
+def test_autotune_candidates():
+    # the layouts the tuner tries are the ones the library accepts (mirrored
+    # limits), and the sort capacities bracket the mean row-pair population
+    from paper_2602_10761_amd import autotune as A
+    from paper_2602_10761_amd import workload as W
+    assert A.inverse_layouts(192, 192) == [4, 3]
+    assert A.inverse_layouts(128, 128) == [1, 2, 4, 3]
+    assert A.inverse_layouts(8, 12) == [1, 2, 3]
+    for n in (300_000, 2_000_000):
+        ens = W.make_workload(3, n_particles=n)[0]
+        mean = n / (160 * 192 // 2)
+        caps = A.sort_cap_candidates(ens)
+        assert min(caps) <= max(mean, 64) < max(caps) <= max(2.5 * mean + 64, 128)
+    assert all(c % 8 == 0 for c in caps)

@@ -12,6 +12,7 @@ import pytest
 import oracle as O
 from helpers import KEYS, oracle_run, state_errors
 from paper_2602_10761_amd import workload as W
+from paper_2602_10761_amd.autotune import inverse_layouts
 
 pytestmark = pytest.mark.gpu
 
@@ -69,22 +70,6 @@ def test_poisson_parity(shape, stretch):
     sim.close()
 
 
-def inverse_layouts(nx, nz):
-    """Layouts of the inverse transforms that fit a mesh: 1 one block per y
-    plane, 2 two blocks (z-row parity), 4 four blocks (z-row residue mod 4),
-    3 z then x kernels."""
-    nh = nx // 2 + 1
-    modes = []
-    if nz * nh <= 10240 and 16 * (nx + nz + nz * nh) <= 163840:
-        modes.append(1)
-    if nz % 4 == 0 and (nz // 2) * nh <= 4736 and (nz // 4) * nx <= 4096:
-        modes.append(2)
-    modes.append(3)
-    if nz % 8 == 0 and (nz // 4) * nh <= 4736 and (nz // 8) * nx <= 4736:
-        modes.append(4)
-    return modes
-
-
 @pytest.mark.parametrize("shape", [(8, 6, 12), (24, 20, 40), (32, 32, 32), (128, 128, 128), (4, 2, 4),
                                    (192, 160, 192), (160, 24, 200), (64, 10, 48)])
 def test_poisson_inverse_layouts(shape):
@@ -100,7 +85,7 @@ def test_poisson_inverse_layouts(shape):
     ref = O.poisson(g, Q)
     phis = {}
     try:
-        for mode in inverse_layouts(nx, nz):
+        for mode in inverse_layouts(nx, nz):  # every layout the library accepts for the mesh
             say("poisson layout", shape, mode)
             R.set_tuning(inv_plane=mode)
             sim = sim_of(ens)
