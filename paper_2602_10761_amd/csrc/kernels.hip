@@ -281,6 +281,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_from_start(Ctx C) {
 // ---------------------------------------------------------------------------
 // FFT in LDS: Stockham autosort, mixed radix 2/3/4/5, runtime plan
 // ---------------------------------------------------------------------------
+// orders the LDS accesses of one wave (phases that use only that wave's LDS
+// region need no block barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -425,9 +432,9 @@ __device__ __forceinline__ void fft_pass(const double2* __restrict__ a, double2*
 }
 
 // Transforms `rows` lines of length P.n (row pitch `pitch`) held in a, with
-// scratch b, by threads tid = 0..nthr-1; returns the buffer holding the
-// result.  Every thread of the block calls it (block barrier between passes);
-// caller must __syncthreads() before the call.
+// scratch b, by the 64 lanes tid of one wave on its own buffers (a
+// wavefront-level fence between passes); returns the buffer holding the
+// result.  The caller orders the buffers' and twiddles' writes before the call.
 template <bool INV>
 __device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const FftPlan& P, const double2* tw,
                             int tid, int nthr) {
@@ -441,7 +448,7 @@ __device__ double2* lds_fft(double2* a, double2* b, int rows, int pitch, const F
       case 4: fft_pass<4, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
       default: fft_pass<5, INV>(a, b, rows, n, pitch, Ns, tw, tid, nthr); break;
     }
-    __syncthreads();
+    wave_sync();
     double2* t = a;
     a = b;
     b = t;
@@ -689,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   const bool fast = M <= cap;  // wave-uniform
   const unsigned long long below = (1ull << lane) - 1ull;
   int nlist = 0;               // wave-uniform length of the member list
-  __syncthreads();
+  wave_sync();
   // pass 1: cell counts; the fast path also lists the members (positions by
   // ballot: no same-address LDS atomics); the loop is wave-uniform
   // loads are unconditional from a clamped slot (no branches around them)
@@ -738,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   if (lane == 0) *nmem = nlist;
-  __syncthreads();
+  wave_sync();
   if (ok) {
     // exclusive scan of the pair's cell counts: lane owns cells [lane*mm, lane*mm + mm)
     const int mm = (n2 + 63) >> 6;
@@ -764,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
     if (rA + 2 == C.n_rows && lane == 0) C.start[c1] = r1;
   }
-  __syncthreads();
+  wave_sync();
   if (ok) {
     // row slot ranges of the new order (the stored order of the next step)
     rm = r0 + min(pre[nx], M);
@@ -803,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   // twiddles of the x transform (nx <= kBlock): loaded now, stored after this phase
   const double2 twv = C.tw[E.fx.tw_off + min((int)threadIdx.x, nx - 1)];
   // rank each member by id inside its cell; write the sorted arrays; deposit
@@ -859,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;
     atomicAdd(reinterpret_cast<unsigned long long*>(&Q[i]), (unsigned long long)Qd);
   }
-  __syncthreads();  // member lists read: the FFT buffers may overwrite them
+  wave_sync();  // member lists read: the FFT buffers may overwrite them
   const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
   long long rq48[2] = {0, 0};
   if (ok) {
