@@ -8,8 +8,8 @@
 //                         rho = Q 2^-48 / V, forward FFT along x of the two rows
 //   z<fwd>                forward FFT along z
 //   tri                   one tridiagonal y-solve per Fourier mode
-//   plane_half / plane_inv  inverse FFTs along z and x per y plane (two blocks or
-//                         one), or z<inv> then pair_ifftx: phi on the cells
+//   plane_part / plane_inv  inverse FFTs along z and x per y plane (two or four
+//                         blocks, or one), or z<inv> then pair_ifftx: phi on the cells
 //   [collide]             4-way coupling: per-slot collision increments
 //   push                  per particle: forces, integration, wall impact and
 //                         charging, wrap, next cell key, row-pair counts, movers
@@ -19,7 +19,8 @@
 //
 // Particle state is stored in the slot order of the previous step's sort; the
 // push gathers velocity, diameter and id through perm (nearly coalesced) and
-// writes in the new order.  Device-scope atomics are kept out of contended
+// writes in the new order.  The carrier is read from a copy with periodic
+// ghost nodes (pad_carrier, at init and on every carrier replacement).  Device-scope atomics are kept out of contended
 // addresses: they are resolved beyond the per-XCD L2 and serialize there.
 #include <type_traits>
 
