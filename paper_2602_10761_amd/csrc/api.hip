@@ -453,6 +453,7 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     C.n_ens = n_ens;
     C.n_tot = S.n_tot;
     C.c_tot = S.c_tot;
+    C.copies = S.pp_any ? 1 : 0;
     h->C = C;
     h->A = A;
     h->B = B;

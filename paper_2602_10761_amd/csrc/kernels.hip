@@ -835,9 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
     if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
     const int b = min(pre[i], M), a = max(pre[i] - cnt[i], 0);
-    // read once here (the push reads the slot-ordered copies): non-temporal
-    const double q = __builtin_nontemporal_load(&in.q[p]), x = __builtin_nontemporal_load(&in.x[p]);
-    const double y = __builtin_nontemporal_load(&in.y[p]), z = __builtin_nontemporal_load(&in.z[p]);
+    const double q = in.q[p];
     int rk = 0;
     if (b - a > 1) {
       if (fast) {
@@ -858,10 +856,12 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     const int o = r0 + a + rk;
     C.perm[o] = p;
     C.skey[o] = (int)c0 + i;
-    C.sq[o] = q;
-    C.sx[o] = x;
-    C.sy[o] = y;
-    C.sz[o] = z;
+    if (C.copies) {  // slot-ordered copies for the collision search
+      C.sq[o] = q;
+      C.sx[o] = in.x[p];
+      C.sy[o] = in.y[p];
+      C.sz[o] = in.z[p];
+    }
     const long long Qd = fixed_round(q, kFixDep, &ovf);
     const long long Q32 = fixed_round(q, kFixQcum, &ovf);
     if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;

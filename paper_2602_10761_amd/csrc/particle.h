@@ -32,9 +32,11 @@ struct Fwd {
   double qc;          // charge after particle-particle exchange (= q without 4-way coupling)
 };
 
-// SORTED: positions and charges of slot s and of its cell mates come from the
-// slot-ordered copies C.sx, C.sy, C.sz, C.sq written by the sort (coalesced,
-// no dependent gather); otherwise they are gathered through C.perm from `in`.
+// Position, charge, velocity and diameter of slot s are gathered through
+// C.perm from `in` (nearly coalesced: particles move little between sorts).
+// SORTED (the push: the lanes of a wave hold consecutive slots): the cell
+// mates' positions and charges come from their lanes; otherwise (the reverse
+// step) they are gathered through C.perm as well.
 // One binary collision of the particle (position difference r = s_self -
 // s_mate, |r|^2 = r2, diameter d, velocity v, charge q) with the mate at old
 // slot pj: hit when they overlap and approach; then the velocity and charge
@@ -81,10 +83,7 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   const double* __restrict__ yf = C.yf + E.y_off;
   const double* __restrict__ idy = C.idy + E.y_off;
 
-  const double x = SORTED ? C.sx[s] : in.x[p];
-  const double y = SORTED ? C.sy[s] : in.y[p];
-  const double z = SORTED ? C.sz[s] : in.z[p];
-  const double q = SORTED ? C.sq[s] : in.q[p];
+  const double x = in.x[p], y = in.y[p], z = in.z[p], q = in.q[p];
   const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p];
   const double d = in.d[p];
 
@@ -177,10 +176,11 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
         double oz = __shfl(z, src & 63, 64), oq = __shfl(q, src & 63, 64);
         if (kk < n && t != s) {
           if (!inw) {
-            ox = C.sx[t];
-            oy = C.sy[t];
-            oz = C.sz[t];
-            oq = C.sq[t];
+            const int pt = C.perm[t];
+            ox = in.x[pt];
+            oy = in.y[pt];
+            oz = in.z[pt];
+            oq = in.q[pt];
           }
           coulomb(ox, oy, oz, oq);
         }

@@ -113,6 +113,8 @@ struct Ctx {
   int* skey;                 // [n_tot]   cell of each new slot
   double* sq;                // [n_tot]   charge of each new slot
   double *sx, *sy, *sz;      // [n_tot]   position of each new slot
+  int copies;                // the incremental sort writes sq, sx, sy, sz (for the collision search only;
+                             // the push gathers position and charge through perm)
   // incremental sort: the state is stored in the previous sort's order, so a
   // row pair's new members are the ones of its own slot range that stayed
   // plus the particles that moved in (mover list, far list)
