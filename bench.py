@@ -81,9 +81,9 @@ def design_bytes(phase, n_p, nx, ny, nz):
         # each at most once per cell or per particle
         "push": 148 * n_p + min(24 * n_nodes, 192 * n_p) + min(8 * n_c, 56 * n_p) + min(4 * n_c, 8 * n_p),
         # incremental sort + deposit + x transform: keys and ids of the
-        # members, their charge and position gathered (40 B) and written in slot
-        # order with perm and cell (48 B); cell starts; the half spectrum
-        "deposit_fftx": 96 * n_p + 4 * n_c + spec,
+        # members (8 B), their charge gathered (8 B), perm and cell written in
+        # slot order (8 B); cell starts; the half spectrum
+        "deposit_fftx": 24 * n_p + 4 * n_c + spec,
         "fftz_fwd": 2 * spec,
         # spectrum in and out, Thomas factors (16 B per mode and row)
         "tridiag": 3 * spec,
@@ -284,12 +284,12 @@ def adjoint_ratio(torch, W, R, autotune, seg, log):
             "adjoint_over_forward": ms_bwd / ms_fwd, "wall_ms_record_plus_adjoint": wall_bwd}
 
 
-def plain_run(torch, W, R, autotune, config, args, log):
+def plain_run(torch, W, R, autotune, config, args, log, **overrides):
     """One ensemble of a plain workload: warm-up, an untimed phase pass (an
     event at every phase boundary), then the timed region with HIP events only
     around the dominant kernel on every args.event_every-th step (on the
     library's stream).  Returns the measurement and the workload."""
-    ens = W.make_workload(config)[0]
+    ens = W.make_workload(config, **overrides)[0]
     m = ens.mesh
     log(f"workload config {config}: {ens.n} particles, mesh {m.nx}x{m.ny}x{m.nz}")
     tuned = autotune.ensure_tuned_workload([ens])
@@ -336,7 +336,8 @@ def plain_run(torch, W, R, autotune, config, args, log):
     res = {
         "value": ens.n * args.steps / (total_ms * 1e-3),
         "ms_per_step": ms_step,
-        "config": {"workload": WORKLOAD_NAME[config], "n_particles": ens.n, "mesh": [m.nx, m.ny, m.nz],
+        "config": {"workload": WORKLOAD_NAME[config] + (f", {overrides}" if overrides else ""),
+                   "n_particles": ens.n, "mesh": [m.nx, m.ny, m.nz],
                    "poisson_every": 1},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -374,6 +375,8 @@ def main():
     ap.add_argument("--no-fourway", action="store_true", help="skip the 4-way coupling timing")
     ap.add_argument("--no-second", action="store_true",
                     help="skip the 1e6-particle 128^3 workload measured beside the headline")
+    ap.add_argument("--no-charged", action="store_true",
+                    help="skip the headline workload with wall impacts and charged particles")
     ap.add_argument("--graphs", action="store_true", help="time graph replays instead of eager phase-timed steps")
     ap.add_argument("--event-every", type=int, default=10,
                     help="timed region: HIP events around the dominant kernel on every n-th step")
@@ -424,6 +427,11 @@ def main():
     if not args.no_second and args.config != 2:
         second, _ = plain_run(torch, W, R, autotune, 2, args, log)
         out["config2"] = second
+    if not args.no_charged:
+        # the headline workload starts uncharged and reaches no wall within the
+        # timed steps; the same with wall impacts and charging at work
+        ch, _ = plain_run(torch, W, R, autotune, args.config, args, log, v_jitter=3.0, precharge=0.05)
+        out["charged"] = {k: ch[k] for k in ("value", "ms_per_step", "config", "phase_us", "impacts", "flags")}
     if not args.no_batched:
         out["batched"] = batched_vs_plain(torch, W, R, autotune, args.batched_steps, log)
     if not args.no_adjoint:
