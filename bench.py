@@ -85,8 +85,9 @@ def design_bytes(phase, n_p, nx, ny, nz):
         # slot order (8 B); cell starts; the half spectrum
         "deposit_fftx": 24 * n_p + 4 * n_c + spec,
         "fftz_fwd": 2 * spec,
-        # spectrum in and out, Thomas factors (16 B per mode and row)
-        "tridiag": 3 * spec,
+        # spectrum in and out, Thomas factors (16 B per mode and row, modes
+        # mz <= nz / 2: mz and nz - mz share them)
+        "tridiag": 2 * spec + 16 * ny * (nz // 2 + 1) * nh,
         # inverse transforms: fused per y plane (spectrum in, phi out) when the
         # plane fits one block's LDS, else z (spectrum in and out) then x
         "fftz_inv": spec + 8 * n_c if plane_fused(nx, nz) else 2 * spec,

@@ -143,7 +143,8 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
         src = S->tf_src[o];
     }
     S->tf_src.push_back(src);
-    if (src == e) S->tf_tot += (long long)E.ny * E.nz * nh;
+    // the factors depend on kz^2, the same for modes mz and nz - mz: rows mz <= nz / 2
+    if (src == e) S->tf_tot += (long long)E.ny * (E.nz / 2 + 1) * nh;
     S->up_tot += 3LL * (E.ny + 1) * E.nz * (E.nx + 2);
     S->rows += (long long)E.ny * E.nz;
     S->y_tot += E.ny + 1;
@@ -725,10 +726,11 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
     h->c_off[e + 1] = h->c_off[e] + (long long)T.nx * T.ny * T.nz;
     s_off += (long long)ny * T.nz * E.nhp;
     if (S.tf_src[e] == e) {
-      const int nm = E.nh * T.nz;
+      // modes mz and nz - mz share kz^2 and so their factors: rows mz <= nz / 2
+      const int nm = E.nh * (T.nz / 2 + 1);
       const double* AM = &am[y_off];
       const double* AP = &ap[y_off];
-      for (int mz = 0; mz < T.nz; ++mz)
+      for (int mz = 0; mz <= T.nz / 2; ++mz)
         for (int m = 0; m < E.nh; ++m) {
           const int mode = mz * E.nh + m;
           const double K2 = kz2[kz_off + mz] + kx2[kx_off + m];

@@ -948,7 +948,9 @@ __global__ __launch_bounds__(kBlock) void k_tri(Ctx C, Ens Eone, int one, const 
   const int j0 = g * Re;
   double A[R], Cc[R], ip[R];
   {
-    const double2* __restrict__ tf = C.tfac + E.tf_off + (long long)(act ? mz * nh + m : 0) * ny;  // (1/pivot, c')
+    // (1/pivot, c'); modes mz and nz - mz share their factors (the same kz^2)
+    const int mzs = mz <= (nz >> 1) ? mz : nz - mz;
+    const double2* __restrict__ tf = C.tfac + E.tf_off + (long long)(act ? mzs * nh + m : 0) * ny;
     const double* __restrict__ am = C.am + E.y_off;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -32,7 +32,7 @@ struct Ens {
   long long c_off;   // first cell (global cell index = c_off + (j*nz + k)*nx + i)
   long long s_off;   // first spectrum entry ([ny][nz][nhp] complex)
   long long row_off; // first (j, k) row
-  long long tf_off;  // first tridiagonal factor ([nz * nh][ny], mode-major)
+  long long tf_off;  // first tridiagonal factor ([(nz / 2 + 1) nh][ny], mode-major, mz <= nz / 2)
   int y_off;         // first entry in the per-y tables (ny+1 reserved)
   int ei;            // index of the ensemble (its carrier pointer: Ctx::uptr[ei])
   int kx_off, kz_off;
@@ -145,7 +145,7 @@ struct Ctx {
   unsigned char* chit;       // optional [n_tot] the slot collided this step (cinc valid only there)
   const double *yf, *dy, *idy, *vol, *am, *ap, *beta, *kx2, *kz2;
   const double2* tw;         // twiddles exp(-2 pi i k/n)
-  const double2* tfac;       // Thomas factors per ensemble: [modes][ny] (1 / pivot, c')
+  const double2* tfac;       // Thomas factors per mesh: [modes mz <= nz / 2][ny] (1 / pivot, c')
 };
 
 __device__ __forceinline__ int find_off(const long long* off, int n, long long v) {
