@@ -326,6 +326,46 @@ def test_full_size_one_step(cfg):
     assert_stats_equal(gst, st)
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_incremental_steps(cfg):
+    """The benchmark workloads at full size in the launch configuration the
+    benchmark times (tiles, inverse layout and sort capacity from the
+    committed tuning cache): three steps, so that the last two run the
+    incremental sort; a wall-normal velocity jitter brings several hundred
+    wall impacts (charging: charges that change between deposits);
+    every particle, the potential and the statistics compared with the
+    oracle."""
+    from paper_2602_10761_amd import autotune
+    from paper_2602_10761_amd import runtime as R
+    say("full size incremental config", cfg)
+    ens = W.make_workload(cfg, precharge=0.05, v_jitter=3.0)[0]
+    m = ens.mesh
+    autotune.ensure_tuned_workload([ens])
+    n = 3
+    try:
+        sim = sim_of(ens)
+        sim.step(n)
+        gpu = sim.state_np(0)
+        gst = sim.stats(0)
+        phig = sim.field(0, 0).cpu().numpy()
+        sim.close()
+    finally:
+        R.set_tuning_class(m.nx, m.ny, m.nz)  # back to the built-in choice
+    g = O.Geo.from_mesh(m)
+    st = O.Stats(g.ny)
+    ref = O.state_of(ens)
+    want = {}
+    for k in range(n):
+        ref = O.step(g, ens.U, ref, ens.params, st, want=want if k == n - 1 else None)
+    perr = np.abs(phig - want["phi"].ravel()).max() / np.abs(want["phi"]).max()
+    err = state_errors(gpu, ref, m)
+    say("  impacts", st.impacts, " phi err", perr, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert gst["steps"] == n and st.impacts.sum() > 500
+    assert perr < 1e-11
+    assert max(err.values()) < 1e-11
+    assert_stats_equal(gst, st)
+
+
 # ---------------------------------------------------------------------------
 # determinism, graphs, batching, checkpoint/resume, edge cases
 # ---------------------------------------------------------------------------
