@@ -25,6 +25,7 @@ CACHE = os.environ.get("TRIBO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.
 FZ_COLS = (4, 8, 12, 16)
 # bumped whenever the tiled kernels change shape semantics (older entries are ignored)
 KERNEL_REV = 7
+SORT_REV = 2  # the fused sort's LDS per wavefront (member capacities tuned against it)
 LDS_BYTES = 163840
 
 
@@ -38,7 +39,7 @@ def _key(arch: str, mesh: Tuple[int, int, int]) -> str:
 
 
 def _sort_key(arch: str, mesh: Tuple[int, int, int], n: int) -> str:
-    return f"{arch}/r{KERNEL_REV}/sort/{mesh[0]}x{mesh[1]}x{mesh[2]}/{n}"
+    return f"{arch}/r{KERNEL_REV}/sort{SORT_REV}/{mesh[0]}x{mesh[1]}x{mesh[2]}/{n}"
 
 
 def tri_candidates(ny: int):
@@ -125,7 +126,7 @@ def sort_cap_candidates(ens) -> Sequence[int]:
     def lds(cap):
         lists = max(12 * cap, 16 * nx)
         lists = (lists + 15) // 16 * 16
-        return 16 * nx + 4 * (lists + 32 * nx + 16)
+        return 16 * nx + 4 * (lists + 24 * nx + 16)
 
     for blocks in range(1, 9):
         room = LDS_BYTES // blocks

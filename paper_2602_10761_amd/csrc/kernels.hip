@@ -632,14 +632,14 @@ constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight 
 
 // LDS of one wave: member list {id, old slot} (8 B), member index by cell
 // position (u16), member cell (u16) -- later the first FFT buffer -- then the
-// int64 cell charges (later the second FFT buffer), cell counts, cell
-// starts/cursors
+// int64 cell charges (later the second FFT buffer), and one int per cell:
+// its count, then its start, then (after bucketing) its end
 __host__ __device__ inline size_t sortdep_lists_bytes(int nx_max, int cap) {
   const size_t lists = (size_t)cap * 12, buf = (size_t)nx_max * 16;
   return ((lists > buf ? lists : buf) + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t sortdep_wave_bytes(int nx_max, int cap) {
-  return sortdep_lists_bytes(nx_max, cap) + (size_t)nx_max * 32 + 16;
+  return sortdep_lists_bytes(nx_max, cap) + (size_t)nx_max * 24 + 16;
 }
 
 __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int one, PState in,
@@ -655,8 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   double2* buf0 = reinterpret_cast<double2*>(base);
   long long* Q = reinterpret_cast<long long*>(base + ub);  // 2 nx int64, read into buf0 before buf1 is used
   double2* buf1 = reinterpret_cast<double2*>(Q);
-  int* cnt = reinterpret_cast<int*>(Q + 2 * nmax);
-  int* pre = cnt + 2 * nmax;
+  int* pre = reinterpret_cast<int*>(Q + 2 * nmax);  // per cell: count -> start -> end
   int* nmem = pre + 2 * nmax;
 
   Ens E;
@@ -683,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     r1 = min(max(C.ps[(rA >> 1) + 1], r0), (int)C.n_tot);
     TT = TB + min(C.far_n[0], (int)C.n_tot);
     for (int i = lane; i < n2; i += 64) {
-      cnt[i] = 0;
+      pre[i] = 0;
       Q[i] = 0;
     }
     if (lane == 0) {
@@ -733,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       const unsigned long long mask = __ballot(hit);
       if (hit) {
         const int i = c[u] - (int)c0;
-        atomicAdd(&cnt[i], 1);
+        atomicAdd(&pre[i], 1);
         if (fast) {
           const int m = nlist + __popcll(mask & below);
           if (m < cap) {
@@ -748,12 +747,13 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   if (lane == 0) *nmem = nlist;
   wave_sync();
   if (ok) {
-    // exclusive scan of the pair's cell counts: lane owns cells [lane*mm, lane*mm + mm)
+    // exclusive scan of the pair's cell counts, in place: lane owns cells
+    // [lane*mm, lane*mm + mm)
     const int mm = (n2 + 63) >> 6;
     int v = 0;
     for (int u = 0; u < mm; ++u) {
       const int i = lane * mm + u;
-      if (i < n2) v += cnt[i];
+      if (i < n2) v += pre[i];
     }
     int incl = v;
 #pragma unroll
@@ -765,9 +765,10 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     for (int u = 0; u < mm; ++u) {
       const int i = lane * mm + u;
       if (i < n2) {
+        const int ci = pre[i];
         pre[i] = ex;
         C.start[c0 + i] = r0 + min(ex, M);
-        ex += cnt[i];
+        ex += ci;
       }
     }
     if (rA + 2 == C.n_rows && lane == 0) C.start[c1] = r1;
@@ -782,7 +783,8 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       if (rA + 2 == C.n_rows) C.rs_new[rA + 2] = r1;
     }
   }
-  // members bucketed by cell (unordered within a cell); pre[] becomes the cell ends
+  // members bucketed by cell (unordered within a cell); pre[] becomes the
+  // cell ends, so cell i then spans [pre[i - 1], pre[i]) (from 0 for i = 0)
   if (fast) {
     const int nm = min(*nmem, M);
     for (int m = lane; m < nm; m += 64) {
@@ -834,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       i = rec.z - (int)c0;
     }
     if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
-    const int b = min(pre[i], M), a = max(pre[i] - cnt[i], 0);
+    const int b = min(pre[i], M), a = i ? min(max(pre[i - 1], 0), b) : 0;
     const double q = in.q[p];
     int rk = 0;
     if (b - a > 1) {
@@ -1844,7 +1846,7 @@ int sortdep_cap(const Ctx& C, int nx_max, int want) {
   // least what the FFT buffer it shares leaves free.  Always within 64 KiB
   // per block.
   if (want < 0) return 0;
-  const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 32LL * nx_max - 16 - 15) / 12;
+  const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 24LL * nx_max - 16 - 15) / 12;
   long long cap;
   if (want > 0) {
     cap = want;
