@@ -126,7 +126,7 @@ def sort_cap_candidates(ens) -> Sequence[int]:
     def lds(cap):
         lists = max(12 * cap, 16 * nx)
         lists = (lists + 15) // 16 * 16
-        return 16 * nx + 4 * (lists + 24 * nx + 16)
+        return 16 * nx + 4 * (lists + 24 * nx + 48)
 
     for blocks in range(1, 9):
         room = LDS_BYTES // blocks

@@ -632,14 +632,15 @@ constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight 
 
 // LDS of one wave: member list {id, old slot} (8 B), member index by cell
 // position (u16), member cell (u16) -- later the first FFT buffer -- then the
-// int64 cell charges (later the second FFT buffer), and one int per cell:
-// its count, then its start, then (after bucketing) its end
+// int64 cell charges (later the second FFT buffer), one int per cell (its
+// count, then its start, then after bucketing its end), the member count and
+// the pair's two row accumulators
 __host__ __device__ inline size_t sortdep_lists_bytes(int nx_max, int cap) {
   const size_t lists = (size_t)cap * 12, buf = (size_t)nx_max * 16;
   return ((lists > buf ? lists : buf) + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t sortdep_wave_bytes(int nx_max, int cap) {
-  return sortdep_lists_bytes(nx_max, cap) + (size_t)nx_max * 24 + 16;
+  return sortdep_lists_bytes(nx_max, cap) + (size_t)nx_max * 24 + 48;
 }
 
 __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int one, PState in,
@@ -657,6 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   double2* buf1 = reinterpret_cast<double2*>(Q);
   int* pre = reinterpret_cast<int*>(Q + 2 * nmax);  // per cell: count -> start -> end
   int* nmem = pre + 2 * nmax;
+  longlong2* racc = reinterpret_cast<longlong2*>(nmem + 4);  // 16-byte aligned (nmax is even)
 
   Ens E;
   int lb;
@@ -690,13 +692,22 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       // consumed by the pair scan and here: restart the counts for this step's push
       C.pair_cnt[rA >> 1] = 0;
       C.mv_n[rA >> 1] = 0;
+      // the pair's row accumulators (only this wavefront updates them), read
+      // with the other set-up loads instead of on the way to the transform
+      racc[0] = C.rowacc[rA];
+      racc[1] = C.rowacc[rA + 1];
     }
   }
   const int M = r1 - r0;
   const bool fast = M <= cap;  // wave-uniform
   const unsigned long long below = (1ull << lane) - 1ull;
   int nlist = 0;               // wave-uniform length of the member list
-  wave_sync();
+  // twiddles of the x transform (nx <= kBlock), shared by the block's waves:
+  // the kernel's only block barrier, taken while the waves are still
+  // together (one before the transform made every wave wait for the block's
+  // most populous row pair)
+  if ((int)threadIdx.x < nx) tw[threadIdx.x] = C.tw[E.fx.tw_off + threadIdx.x];
+  __syncthreads();
   // pass 1: cell counts; the fast path also lists the members (positions by
   // ballot: no same-address LDS atomics); the loop is wave-uniform
   // loads are unconditional from a clamped slot (no branches around them)
@@ -814,8 +825,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   wave_sync();
-  // twiddles of the x transform (nx <= kBlock): loaded now, stored after this phase
-  const double2 twv = C.tw[E.fx.tw_off + min((int)threadIdx.x, nx - 1)];
   // rank each member by id inside its cell; write the sorted arrays; deposit
   bool ovf = false;
   long long rq32[2] = {0, 0};
@@ -888,7 +897,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     for (int h = 0; h < 2; ++h) {
       const long long a48 = wave_sum(rq48[h]), a32 = wave_sum(rq32[h]);
       if (lane == 0) {
-        longlong2 acc = C.rowacc[rA + h];
+        longlong2 acc = racc[h];
         acc.x += cntr[h];
         acc.y += a32;
         C.rowacc[rA + h] = acc;
@@ -897,8 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   if (ovf) atomicOr((unsigned long long*)&C.stats[E.st_off + ST_FLAGS], (unsigned long long)FLAG_OVERFLOW);
-  if ((int)threadIdx.x < nx) tw[threadIdx.x] = twv;
-  __syncthreads();
+  wave_sync();
   pair_forward_store(C, E, jkA, buf0, buf1, tw, lane, ok);
 }
 
@@ -1846,7 +1854,7 @@ int sortdep_cap(const Ctx& C, int nx_max, int want) {
   // least what the FFT buffer it shares leaves free.  Always within 64 KiB
   // per block.
   if (want < 0) return 0;
-  const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 24LL * nx_max - 16 - 15) / 12;
+  const long long lim = ((65536 - 16LL * nx_max) / kPairsPerBlock - 24LL * nx_max - 48 - 15) / 12;
   long long cap;
   if (want > 0) {
     cap = want;
