@@ -334,6 +334,11 @@ def plain_run(torch, W, R, autotune, config, args, log, **overrides):
     achieved = ab / (dms * 1e-3) / 1e9
     tr = measured_traffic(dom, config)
     B = algorithmic_step_bytes(ens.n, m.nx, m.ny, m.nz)
+    # the step's HBM bytes as counted (FETCH_SIZE + WRITE_SIZE of every kernel
+    # with design traffic, from the committed summary of this workload)
+    kern = [k for k in per_phase if design_bytes(k, ens.n, m.nx, m.ny, m.nz) > 0]
+    mt = {k: measured_traffic(k, config) for k in kern}
+    mb = None if overrides or any(v is None for v in mt.values()) else sum(mt.values())
     res = {
         "value": ens.n * args.steps / (total_ms * 1e-3),
         "ms_per_step": ms_step,
@@ -350,7 +355,10 @@ def plain_run(torch, W, R, autotune, config, args, log, **overrides):
                                        if dom_ms is not None else "phase pass")},
         "step": {"algorithmic_bytes": B, "algorithmic_GBs": B / (ms_step * 1e-3) / 1e9,
                  "algorithmic_frac": B / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                 "design_bytes": sum(design_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_phase)},
+                 "design_bytes": sum(design_bytes(k, ens.n, m.nx, m.ny, m.nz) for k in per_phase),
+                 "measured_bytes": mb,
+                 "measured_GBs": None if mb is None else mb / (ms_step * 1e-3) / 1e9,
+                 "measured_frac": None if mb is None else mb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "phase_us": {k: 1e3 * v for k, v in per_phase.items()},
         "impacts": [int(v) for v in st["impacts"]],
         "flags": int(st["flags"]),
