@@ -309,23 +309,31 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  *              then an x kernel through global memory; 0 = 2 when it fits and
  *              2 ny does not exceed the GPU's CU count, else 1 when the plane
  *              fits a block, else 4 when a quarter plane does, else 3
+ *   push_order order of the push's blocks over the GPU's XCDs (each with its
+ *              own L2): 1 = consecutive slot ranges per XCD (an XCD's L2
+ *              keeps the carrier and phi rows that neighbouring cells share),
+ *              2 = the hardware's round robin (every XCD on neighbouring
+ *              slots: shared rows come from the memory-side cache, work near
+ *              the walls and in the middle of the channel spread evenly);
+ *              0 = 1
  * Values whose LDS need exceeds a block's LDS are rejected at tf_init.
- * Results do not depend on sort_cap or fz_cols (bitwise); tri_modes and
+ * Results do not depend on sort_cap, fz_cols or push_order (bitwise); tri_modes and
  * inv_plane set the association order of the tridiagonal scans or of the
  * inverse transforms, so they change results at the rounding level only.
  */
 typedef struct {
-  int32_t sort_cap, fz_cols, tri_modes, inv_plane;
+  int32_t sort_cap, fz_cols, tri_modes, inv_plane, push_order;
 } tf_tuning;
 int tf_set_tuning(const tf_tuning* t);
 
 /* Tile shapes for the ensembles of one mesh-size class (nx, ny, nz); they take
  * precedence over tf_set_tuning for those ensembles (t == NULL removes the
  * entry).  Ensembles of different classes in one handle keep their own tiles
- * within the same launches.  The sort's member capacity is one per handle:
- * the class's sort_cap (>= 0 here, 0 = no choice) applies when every ensemble
- * of the handle has that mesh and tf_set_tuning set none; a handle with
- * several mesh classes takes the built-in rule over all its row pairs. */
+ * within the same launches.  The sort's member capacity and the push's block
+ * order are one per handle: the class's sort_cap (>= 0 here, 0 = no choice)
+ * and push_order apply when every ensemble of the handle has that mesh and
+ * tf_set_tuning set none; a handle with several mesh classes takes the
+ * built-in rules. */
 int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t);
 
 void tf_destroy(tf_handle* h);

@@ -64,12 +64,13 @@ def inverse_layouts(nx: int, nz: int):
     return out
 
 
-def _time_phases(ens, steps: int, sort_cap: int = 0, fz: int = 0, tm: int = 0, inv: int = 0) -> Dict[str, float]:
-    R.set_tuning(sort_cap, fz, tm, inv)
+def _time_phases(ens, steps: int, sort_cap: int = 0, fz: int = 0, tm: int = 0, inv: int = 0,
+                 push_order: int = 0) -> Dict[str, float]:
+    R.set_tuning(sort_cap, fz, tm, inv, push_order)
     try:
         sim = R.TriboSim([ens])
     finally:
-        R.set_tuning(0, 0, 0, 0)
+        R.set_tuning()
     sim.step(2)
     sim.profile_begin(steps)
     sim.step(steps)
@@ -151,6 +152,17 @@ def tune_sort_cap(ens, steps: int = 10) -> Dict[str, float]:
     return {"sort_cap": best, "deposit_us": t_best}
 
 
+def tune_push_order(ens, steps: int = 10) -> Dict[str, float]:
+    """Faster block order of the push for this ensemble: consecutive slot
+    ranges per XCD (1) or the hardware's round robin (2)."""
+    best, t_best = 1, float("inf")
+    for order in (1, 2):
+        t = _time_phases(ens, steps, push_order=order)["push"]
+        if t < t_best:
+            best, t_best = order, t
+    return {"push_order": best, "push_us": t_best}
+
+
 def load_cache(path: str = CACHE) -> dict:
     if os.path.exists(path):
         with open(path) as f:
@@ -167,7 +179,8 @@ def _save(cache: dict, path: Optional[str]):
 
 
 def ensure_tuned(meshes: Iterable[Tuple[int, int, int]], path: Optional[str] = CACHE, retune: bool = False,
-                 steps: int = 8, sort_caps: Optional[Dict[Tuple[int, int, int], int]] = None) -> dict:
+                 steps: int = 8, sort_caps: Optional[Dict[Tuple[int, int, int], int]] = None,
+                 push_orders: Optional[Dict[Tuple[int, int, int], int]] = None) -> dict:
     """Tune the meshes missing from the cache, register all of them, return the entries."""
     arch = _arch()
     cache = load_cache(path) if path else {}
@@ -180,31 +193,37 @@ def ensure_tuned(meshes: Iterable[Tuple[int, int, int]], path: Optional[str] = C
             changed = True
         ent = cache[k]
         cap = (sort_caps or {}).get(mesh, 0)
+        order = (push_orders or {}).get(mesh, 0)
         R.set_tuning_class(*mesh, fz_cols=int(ent["fz_cols"]), tri_modes=int(ent["tri_modes"]),
-                           inv_plane=int(ent.get("inv_plane", 0)), sort_cap=int(cap))
-        out[k] = dict(ent, sort_cap=cap)
+                           inv_plane=int(ent.get("inv_plane", 0)), sort_cap=int(cap), push_order=int(order))
+        out[k] = dict(ent, sort_cap=cap, push_order=order)
     if changed:
         _save(cache, path)
     return out
 
 
 def ensure_tuned_workload(ensembles, path: Optional[str] = CACHE, retune: bool = False) -> dict:
-    """Tile shapes of every mesh class of a workload and the fused sort's member
-    capacity tuned on the largest ensemble of each class."""
+    """Tile shapes of every mesh class of a workload, the fused sort's member
+    capacity and the push's block order tuned on the largest ensemble of each
+    class."""
     arch = _arch()
     ensure_tuned(meshes_of(ensembles), path, retune)
     cache = load_cache(path) if path else {}
-    caps, changed = {}, False
+    caps, orders, changed = {}, {}, False
     for mesh in sorted(set(meshes_of(ensembles))):
         big = max((E for E in ensembles if (E.mesh.nx, E.mesh.ny, E.mesh.nz) == mesh), key=lambda E: E.n)
         k = _sort_key(arch, mesh, big.n)
         if retune or k not in cache:
             cache[k] = tune_sort_cap(big)
             changed = True
+        if "push_order" not in cache[k]:
+            cache[k].update(tune_push_order(big))
+            changed = True
         caps[mesh] = int(cache[k]["sort_cap"])
+        orders[mesh] = int(cache[k]["push_order"])
     if changed:
         _save(cache, path)
-    return ensure_tuned(meshes_of(ensembles), path, False, sort_caps=caps)
+    return ensure_tuned(meshes_of(ensembles), path, False, sort_caps=caps, push_orders=orders)
 
 
 def meshes_of(ensembles) -> list:

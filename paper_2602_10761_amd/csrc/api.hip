@@ -20,7 +20,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local const char* g_err_lit = nullptr;  // set by fail_lit (no allocation), cleared by fail
-tf_tuning g_tune = {0, 0, 0, 0};
+tf_tuning g_tune = {0, 0, 0, 0, 0};
 std::map<std::tuple<int, int, int>, tf_tuning> g_class_tune;  // per (nx, ny, nz)
 
 int fail(int code, const std::string& msg) {
@@ -75,6 +75,7 @@ struct Sizes {
   int y_tot = 0, kx_tot = 0, kz_tot = 0, tw_tot = 0, st_tot = 0;
   int nx_max = 0, nz_max = 0, ny_max = 0, wz = 8, tri_rows = 1;
   int sort_cap = 0;             // member capacity of the fused sort for this handle
+  int push_order = 0;           // the push's block order over the XCDs (tf_tuning.push_order)
   long long tf_tot = 0;         // tridiagonal factors (double2 per mode and y row)
   std::vector<int> tf_src;      // ensemble whose factor table an ensemble uses (the first of its mesh)
   long long up_tot = 0;         // padded carrier copies (doubles)
@@ -173,6 +174,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
   // else the one set for the mesh class when every ensemble has that mesh
   // (a batch of several classes takes the built-in rule over the whole batch)
   S->sort_cap = g_tune.sort_cap;
+  S->push_order = g_tune.push_order;
   bool one_class = true;
   for (int e = 1; e < n_ens; ++e)
     one_class = one_class && ens[e].nx == ens[0].nx && ens[e].ny == ens[0].ny && ens[e].nz == ens[0].nz;
@@ -185,6 +187,7 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
       if (it->second.tri_modes > 0) t.tri_modes = it->second.tri_modes;
       if (it->second.inv_plane > 0) t.inv_plane = it->second.inv_plane;
       if (g_tune.sort_cap == 0 && one_class && it->second.sort_cap > 0) S->sort_cap = it->second.sort_cap;
+      if (g_tune.push_order == 0 && one_class && it->second.push_order > 0) S->push_order = it->second.push_order;
     }
     want_plane[e] = t.inv_plane;
     const int wz = t.fz_cols > 0 ? t.fz_cols : 2;
@@ -550,11 +553,11 @@ const char* tf_last_error(void) { return g_err_lit ? g_err_lit : g_err.c_str(); 
 
 int tf_set_tuning(const tf_tuning* t) {
   if (!t) {
-    g_tune = tf_tuning{0, 0, 0, 0};
+    g_tune = tf_tuning{0, 0, 0, 0, 0};
     return TF_OK;
   }
   if (t->sort_cap < -1 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4)
+      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4 || t->push_order < 0 || t->push_order > 2)
     return fail(TF_EINVAL, "tuning value out of range");
   g_tune = *t;
   return TF_OK;
@@ -568,7 +571,7 @@ int tf_set_tuning_class(int32_t nx, int32_t ny, int32_t nz, const tf_tuning* t) 
     return TF_OK;
   }
   if (t->sort_cap < 0 || t->sort_cap > 4096 || t->fz_cols < 0 || t->fz_cols > 64 || t->tri_modes < 0 ||
-      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4)
+      t->tri_modes > 32 || t->inv_plane < 0 || t->inv_plane > 4 || t->push_order < 0 || t->push_order > 2)
     return fail(TF_EINVAL, "tuning value out of range");
   g_class_tune[key] = *t;
   return TF_OK;
@@ -819,6 +822,7 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init, voi
   h->G.ny_max = S.ny_max;
   h->G.tri_rows = S.tri_rows;
   h->G.sort_cap = S.sort_cap;
+  h->G.push_order = S.push_order;
   h->G.fp_blk = h->S.fp_blk.data();
   h->G.fz_blk = h->S.fz_blk.data();
   h->G.tri_blk = h->S.tri_blk.data();

@@ -1730,13 +1730,16 @@ __device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
 
 // four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat
 // the few spilled registers
-template <bool PP>
+// RR: blocks in the hardware's round robin over the XCDs, else consecutive
+// slot ranges per XCD
+template <bool PP, bool RR>
 __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   // the new row ranges become the stored order's (read by the next sort)
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
     C.rs_old[r] = C.rs_new[r];
-  const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+  const long long blk = RR ? (long long)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int s = (int)(blk * kBlock + threadIdx.x);
   const bool act = s < C.n_tot;
   const int c = act ? C.skey[s] : 0x7fffffff;
   // the slots of the lane's cell from the wave's keys (every lane takes part)
@@ -1969,10 +1972,14 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
   const int nb = std::max(1, (int)((C.n_tot + kBlock - 1) / kBlock));
   const int one = (C.n_ens == 1) ? 1 : 0;
   // the collision code only when an ensemble has 4-way coupling on
-  if (G.pp_any)
-    k_push<true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
-  else
-    k_push<false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  const bool rr = G.push_order == 2;
+  if (G.pp_any) {
+    if (rr) k_push<true, true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+    else k_push<true, false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  } else {
+    if (rr) k_push<false, true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+    else k_push<false, false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+  }
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct LaunchGeo {
   int ny_max;
   int tri_rows;    // rows per lane of the tridiagonal scans (largest over the ensembles)
   int sort_cap;    // members per row pair in LDS for the fused sort (0 auto, -1 none)
+  int push_order;  // the push's blocks: 0, 1 consecutive slot ranges per XCD, 2 the hardware's round robin
   int pp_any;      // some ensemble has 4-way coupling on
   int plane_any, half_any, split_any;  // some ensembles with inverse transforms per plane /
                                        // per half plane / by the z and x kernels

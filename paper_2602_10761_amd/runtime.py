@@ -49,7 +49,8 @@ class TfParticles(Structure):
 
 
 class TfTuning(Structure):
-    _fields_ = [("sort_cap", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("inv_plane", c_int32)]
+    _fields_ = [("sort_cap", c_int32), ("fz_cols", c_int32), ("tri_modes", c_int32), ("inv_plane", c_int32),
+                ("push_order", c_int32)]
 
 
 class TfStatsOut(Structure):
@@ -103,16 +104,16 @@ class TriboError(RuntimeError):
     pass
 
 
-def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0):
+def set_tuning(sort_cap: int = 0, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0, push_order: int = 0):
     """Tile shapes for every later TriboSim of this process (0 = built-in choice)."""
-    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane)
+    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane, push_order)
     _check(lib().tf_set_tuning(ctypes.byref(t)))
 
 
 def set_tuning_class(nx: int, ny: int, nz: int, fz_cols: int = 0, tri_modes: int = 0, inv_plane: int = 0,
-                     sort_cap: int = 0):
+                     sort_cap: int = 0, push_order: int = 0):
     """Tile shapes for ensembles of mesh size (nx, ny, nz) in later TriboSims."""
-    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane)
+    t = TfTuning(sort_cap, fz_cols, tri_modes, inv_plane, push_order)
     _check(lib().tf_set_tuning_class(nx, ny, nz, ctypes.byref(t)))
 
 

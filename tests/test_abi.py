@@ -158,3 +158,17 @@ def test_autotune_candidates():
         caps = A.sort_cap_candidates(ens)
         assert min(caps) <= max(mean, 64) < max(caps) <= max(2.5 * mean + 64, 128)
     assert all(c % 8 == 0 for c in caps)
+
+
+def test_tuning_ranges():
+    # host-side validation of tf_tuning (no device work)
+    L = R.lib()
+    try:
+        assert L.tf_set_tuning(ctypes.byref(R.TfTuning(0, 0, 0, 0, 2))) == 0
+        assert L.tf_set_tuning(ctypes.byref(R.TfTuning(0, 0, 0, 0, 3))) != 0
+        assert L.tf_set_tuning(ctypes.byref(R.TfTuning(0, 0, 0, 5, 0))) != 0
+        assert L.tf_set_tuning_class(8, 8, 8, ctypes.byref(R.TfTuning(0, 0, 0, 0, -1))) != 0
+        assert L.tf_set_tuning_class(8, 8, 8, ctypes.byref(R.TfTuning(0, 0, 0, 0, 1))) == 0
+        assert L.tf_set_tuning_class(8, 8, 8, None) == 0
+    finally:
+        assert L.tf_set_tuning(None) == 0

@@ -243,6 +243,29 @@ def test_sort_capacity_paths():
             np.testing.assert_array_equal(runs[cap][0][k], runs[0][0][k])
 
 
+def test_push_orders_bitwise():
+    """The push's two block orders over the XCDs (consecutive slot ranges per
+    XCD, the hardware's round robin) give bitwise the same steps."""
+    from paper_2602_10761_amd import runtime as R
+    say("push orders")
+    ens = ens_small(nx=32, ny=40, nz=32, n=30000, v_jitter=3.0, precharge=0.2, re_tau=40.0, c_el=5.0)
+    runs = {}
+    try:
+        for order in (1, 2):
+            R.set_tuning(push_order=order)
+            sim = sim_of(ens)
+            sim.step(6)
+            runs[order] = (sim.state_np(0), sim.stats(0))
+            sim.close()
+    finally:
+        R.set_tuning()
+    for k in KEYS:
+        np.testing.assert_array_equal(runs[1][0][k], runs[2][0][k])
+    for k in ("impacts", "wallq", "crel_y", "qcum_y", "qnow_y", "unhist"):
+        np.testing.assert_array_equal(runs[1][1][k], runs[2][1][k])
+    assert runs[1][1]["impacts"].sum() > 0
+
+
 @pytest.mark.parametrize("graphs", [False, True])
 def test_carrier_replacement(graphs):
     """tf_set_carrier: steps after a new carrier field follow the oracle with
