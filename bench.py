@@ -15,6 +15,7 @@ and the CPU oracle baseline.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -102,10 +103,16 @@ def traffic_file(config):
 
 
 def source_hash():
+    """Hash of the kernel sources' code (comments and blank lines left out, so
+    that a comment edit keeps a measurement valid)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
