@@ -315,7 +315,7 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
  *              2 = the hardware's round robin (every XCD on neighbouring
  *              slots: shared rows come from the memory-side cache, work near
  *              the walls and in the middle of the channel spread evenly);
- *              0 = 1
+ *              0 = 1 for a handle of one mesh class, 2 for several
  * Values whose LDS need exceeds a block's LDS are rejected at tf_init.
  * Results do not depend on sort_cap, fz_cols or push_order (bitwise); tri_modes and
  * inv_plane set the association order of the tridiagonal scans or of the

@@ -204,6 +204,9 @@ int check_config(const tf_ensemble* ens, int n_ens, Sizes* S) {
     S->wz = std::max(S->wz, wz);
     S->tri_rows = std::max(S->tri_rows, rows);
   }
+  // push block order: a handle of several mesh classes (small ensembles
+  // side by side) takes the round robin
+  if (S->push_order == 0 && !one_class) S->push_order = 2;
   const size_t lds_fx = (size_t)9 * S->nx_max * 16;  // twiddles + 4 waves x 2 line buffers
   const size_t lds_fz = (size_t)(S->wz * S->nz_max + S->nz_max) * 16;
   const size_t lds_tri = ((size_t)kBlock * (S->tri_rows | 1) + kBlock) * 16;
