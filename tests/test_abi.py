@@ -172,3 +172,17 @@ def test_tuning_ranges():
         assert L.tf_set_tuning_class(8, 8, 8, None) == 0
     finally:
         assert L.tf_set_tuning(None) == 0
+
+
+def test_bench_source_hash_ignores_comments(tmp_path, monkeypatch):
+    # a measurement stays valid across comment edits, not across code edits
+    import bench
+    src = tmp_path / "k.hip"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.hip"])
+    src.write_text("int f(int a) { return a + 1; }  // one\n/* block\n comment */\n")
+    h0 = bench.source_hash()
+    src.write_text("// new header\nint f(int a) { return a + 1; }  // two\n\n")
+    assert bench.source_hash() == h0
+    src.write_text("int f(int a) { return a + 2; }\n")
+    assert bench.source_hash() != h0
