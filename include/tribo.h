@@ -293,9 +293,10 @@ int tf_profile_end(tf_handle* h, double* phase_ms /* [TF_NPHASE] */, int32_t* n_
 /*
  * Tile shapes of the sort and Poisson kernels, used by every later tf_init /
  * tf_workspace_size of the calling process (0 = built-in choice):
- *   sort_cap   members per row pair held in LDS by the fused sort (pairs with
- *              more take a second pass through global memory); 0 = twice
- *              the mean pair rounded up to 64, -1 = none (always two passes),
+ *   sort_cap   members held in LDS by the fused sort's list (a row pair with
+ *              more is listed one row at a time when each row fits, else it
+ *              takes a second pass through global memory); 0 = twice the
+ *              mean pair rounded up to 64, -1 = none (always two passes),
  *              else 1..4096 (clamped to what fits 64 KiB of LDS per block)
  *   fz_cols    spectral columns per block of the z transforms (1..64, and
  *              fz_cols nz <= 2048)

@@ -25,7 +25,7 @@ CACHE = os.environ.get("TRIBO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.
 FZ_COLS = (4, 8, 12, 16)
 # bumped whenever the tiled kernels change shape semantics (older entries are ignored)
 KERNEL_REV = 7
-SORT_REV = 2  # the fused sort's LDS per wavefront (member capacities tuned against it)
+SORT_REV = 3  # the fused sort's list paths (member capacities tuned against them)
 LDS_BYTES = 163840
 
 

@@ -633,7 +633,7 @@ constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight 
 // LDS of one wave: member list {id, old slot} (8 B), member index by cell
 // position (u16), member cell (u16) -- later the first FFT buffer -- then the
 // int64 cell charges (later the second FFT buffer), one int per cell (its
-// count, then its start, then after bucketing its end), the member count and
+// count, then its start, then after bucketing its end), 16 free bytes and
 // the pair's two row accumulators
 __host__ __device__ inline size_t sortdep_lists_bytes(int nx_max, int cap) {
   const size_t lists = (size_t)cap * 12, buf = (size_t)nx_max * 16;
@@ -657,8 +657,8 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   long long* Q = reinterpret_cast<long long*>(base + ub);  // 2 nx int64, read into buf0 before buf1 is used
   double2* buf1 = reinterpret_cast<double2*>(Q);
   int* pre = reinterpret_cast<int*>(Q + 2 * nmax);  // per cell: count -> start -> end
-  int* nmem = pre + 2 * nmax;
-  longlong2* racc = reinterpret_cast<longlong2*>(nmem + 4);  // 16-byte aligned (nmax is even)
+  // (16 bytes free, then the row accumulators, 16-byte aligned: nmax is even)
+  longlong2* racc = reinterpret_cast<longlong2*>(pre + 2 * nmax + 4);
 
   Ens E;
   int lb;
@@ -688,7 +688,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       Q[i] = 0;
     }
     if (lane == 0) {
-      *nmem = 0;
       // consumed by the pair scan and here: restart the counts for this step's push
       C.pair_cnt[rA >> 1] = 0;
       C.mv_n[rA >> 1] = 0;
@@ -699,63 +698,69 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   const int M = r1 - r0;
-  const bool fast = M <= cap;  // wave-uniform
+  const bool fast = M <= cap;  // wave-uniform: the whole pair fits the list
   const unsigned long long below = (1ull << lane) - 1ull;
-  int nlist = 0;               // wave-uniform length of the member list
   // twiddles of the x transform (nx <= kBlock), shared by the block's waves:
   // the kernel's only block barrier, taken while the waves are still
   // together (one before the transform made every wave wait for the block's
   // most populous row pair)
   if ((int)threadIdx.x < nx) tw[threadIdx.x] = C.tw[E.fx.tw_off + threadIdx.x];
   __syncthreads();
-  // pass 1: cell counts; the fast path also lists the members (positions by
-  // ballot: no same-address LDS atomics); the loop is wave-uniform
-  // loads are unconditional from a clamped slot (no branches around them)
+  // candidate pass over the pair's own range, its mover list and the far
+  // list: with count (a compile-time tag), the cell counts; members of the cells [lo, hi) listed
+  // in LDS (positions by ballot: no same-address LDS atomics), at most cap;
+  // returns how many were listed (wave-uniform; the loop is wave-uniform).
+  // Loads are unconditional from a clamped slot (no branches around them)
   const int last = (int)C.n_tot - 1;
-  for (int tb = 0; tb < TT; tb += 64 * kCand) {
-    const int t0 = tb + lane;
-    int sl[kCand], c[kCand], idv[kCand];
-#pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      const int t = t0 + 64 * u;
-      sl[u] = t < T ? a0 + t : -1;
-    }
-    if (tb + 64 * kCand > T && TT > T) {  // the batch reaches the mover or far list
+  auto cand_pass = [&](auto count_tag, int lo, int hi) -> int {
+    constexpr bool count = decltype(count_tag)::value;
+    int nl = 0;
+    for (int tb = 0; tb < TT; tb += 64 * kCand) {
+      const int t0 = tb + lane;
+      int sl[kCand], c[kCand], idv[kCand];
 #pragma unroll
       for (int u = 0; u < kCand; ++u) {
         const int t = t0 + 64 * u;
-        if (t >= T && t < TB) sl[u] = mvp[t - T];
-        else if (t >= TB && t < TT) sl[u] = C.far[t - TB];
+        sl[u] = t < T ? a0 + t : -1;
       }
-    }
+      if (tb + 64 * kCand > T && TT > T) {  // the batch reaches the mover or far list
 #pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      const int kv = in.key[min(max(sl[u], 0), last)];
-      c[u] = sl[u] >= 0 ? kv : -1;
-    }
-    if (fast) {
+        for (int u = 0; u < kCand; ++u) {
+          const int t = t0 + 64 * u;
+          if (t >= T && t < TB) sl[u] = mvp[t - T];
+          else if (t >= TB && t < TT) sl[u] = C.far[t - TB];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCand; ++u) {
+        const int kv = in.key[min(max(sl[u], 0), last)];
+        c[u] = sl[u] >= 0 ? kv : -1;
+      }
 #pragma unroll
       for (int u = 0; u < kCand; ++u) idv[u] = in.id[min(max(sl[u], 0), last)];
-    }
 #pragma unroll
-    for (int u = 0; u < kCand; ++u) {
-      const bool hit = c[u] >= c0 && c[u] < c1;
-      const unsigned long long mask = __ballot(hit);
-      if (hit) {
+      for (int u = 0; u < kCand; ++u) {
+        const bool hit = c[u] >= c0 && c[u] < c1;
         const int i = c[u] - (int)c0;
-        atomicAdd(&pre[i], 1);
-        if (fast) {
-          const int m = nlist + __popcll(mask & below);
+        if (count && hit) atomicAdd(&pre[i], 1);
+        const bool li = hit && i >= lo && i < hi;
+        const unsigned long long mask = __ballot(li);
+        if (li) {
+          const int m = nl + __popcll(mask & below);
           if (m < cap) {
             A[m] = make_int2(idv[u], sl[u]);
             Ai[m] = (unsigned short)i;
           }
         }
+        nl += __popcll(mask);
       }
-      nlist += __popcll(mask);
     }
-  }
-  if (lane == 0) *nmem = nlist;
+    return nl;
+  };
+  // pass 1: the counts, and the members listed: all of them when the pair
+  // fits the list, else those of its first row (the pair may fit in two
+  // rounds, one row each)
+  const int nl1 = cand_pass(std::true_type{}, 0, fast ? n2 : nx);
   wave_sync();
   if (ok) {
     // exclusive scan of the pair's cell counts, in place: lane owns cells
@@ -794,16 +799,64 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
       if (rA + 2 == C.n_rows) C.rs_new[rA + 2] = r1;
     }
   }
-  // members bucketed by cell (unordered within a cell); pre[] becomes the
-  // cell ends, so cell i then spans [pre[i - 1], pre[i]) (from 0 for i = 0)
-  if (fast) {
-    const int nm = min(*nmem, M);
-    for (int m = lane; m < nm; m += 64) {
-      const int pos = atomicAdd(&pre[Ai[m]], 1);
-      if (pos < M) Bm[pos] = (unsigned short)m;
+  const int MA = rm - r0;  // members of the first row
+  const bool rows2 = !fast && MA <= cap && M - MA <= cap;  // wave-uniform
+  bool ovf = false;
+  long long rq32[2] = {0, 0};
+  // a member (old slot p, charge q, cell i, rank rk by id among its cell's
+  // members, which start at position a): its slot and its deposit
+  auto place = [&](double q, int p, int i, int a, int rk) {
+    const int o = r0 + a + rk;
+    C.perm[o] = p;
+    C.skey[o] = (int)c0 + i;
+    if (C.copies) {  // slot-ordered copies for the collision search
+      C.sq[o] = q;
+      C.sx[o] = in.x[p];
+      C.sy[o] = in.y[p];
+      C.sz[o] = in.z[p];
+    }
+    const long long Qd = fixed_round(q, kFixDep, &ovf);
+    const long long Q32 = fixed_round(q, kFixQcum, &ovf);
+    if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&Q[i]), (unsigned long long)Qd);
+  };
+  if (fast || rows2) {
+    // members listed in LDS, one round per listed range of positions
+    // [base, lim) (the pair, or its first row and then its second): bucketed
+    // by cell (pre[] becomes the cell ends, so cell i spans [pre[i - 1],
+    // pre[i]), from 0 for i = 0), ranked by id, placed
+    int nm = min(nl1, cap);
+    for (int rd = 0; rd < (rows2 ? 2 : 1); ++rd) {  // wave-uniform
+      if (rd == 1) {
+        // the second row: its members listed by a candidate pass of their own
+        nm = min(cand_pass(std::false_type{}, nx, n2), cap);
+        wave_sync();
+      }
+      const int base = rd ? MA : 0, lim = fast ? M : (rd ? M : MA);
+      for (int m = lane; m < nm; m += 64) {
+        const int pos = atomicAdd(&pre[Ai[m]], 1);
+        if (pos >= base && pos < lim) Bm[pos - base] = (unsigned short)m;
+      }
+      wave_sync();
+      for (int t = base + lane; t < lim; t += 64) {
+        const int m = Bm[t - base];
+        if (m >= nm) continue;  // members inconsistent with the row counts: never by construction
+        const int2 e = A[m];
+        const int id = e.x, p = e.y, i = Ai[m];
+        if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
+        const int b = min(pre[i], lim), a = i ? min(max(pre[i - 1], base), b) : base;
+        const double q = in.q[p];  // in flight during the ranking
+        int rk = 0;
+        for (int u = a; u < b; ++u) {
+          const int mu = Bm[u - base];
+          rk += (mu < nm && A[mu].x < id) ? 1 : 0;
+        }
+        place(q, p, i, a, rk);
+      }
+      wave_sync();
     }
   } else {
-    // more members than the LDS list holds: a second candidate pass through C.tmp
+    // more members than the LDS lists hold: a second candidate pass through C.tmp
     for (int t0 = lane; t0 < TT; t0 += 64 * kCand) {
       int sl[kCand], c[kCand], idv[kCand];
 #pragma unroll
@@ -823,60 +876,23 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
         }
       }
     }
-  }
-  wave_sync();
-  // rank each member by id inside its cell; write the sorted arrays; deposit
-  bool ovf = false;
-  long long rq32[2] = {0, 0};
-  const int nmv = fast ? min(*nmem, M) : M;
-  for (int t = lane; t < M; t += 64) {
-    int id, p, i;
-    if (fast) {
-      const int m = Bm[t];
-      if (m >= nmv) continue;  // members inconsistent with the row counts: never by construction
-      const int2 e = A[m];
-      id = e.x;
-      p = e.y;
-      i = Ai[m];
-    } else {
+    wave_sync();
+    for (int t = lane; t < M; t += 64) {
       const int4 rec = C.tmp[r0 + t];
-      id = rec.x;
-      p = rec.y;
-      i = rec.z - (int)c0;
-    }
-    if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
-    const int b = min(pre[i], M), a = i ? min(max(pre[i - 1], 0), b) : 0;
-    const double q = in.q[p];
-    int rk = 0;
-    if (b - a > 1) {
-      if (fast) {
-        for (int u = a; u < b; ++u) {
-          const int mu = Bm[u];
-          rk += (mu < nmv && A[mu].x < id) ? 1 : 0;
-        }
-      } else {
-        for (int u = a; u < b; u += 4) {
-          int idu[4];
+      const int id = rec.x, p = rec.y, i = rec.z - (int)c0;
+      if (p < 0 || p >= C.n_tot || i < 0 || i >= n2) continue;
+      const int b = min(pre[i], M), a = i ? min(max(pre[i - 1], 0), b) : 0;
+      const double q = in.q[p];
+      int rk = 0;
+      for (int u = a; u < b; u += 4) {
+        int idu[4];
 #pragma unroll
-          for (int vv = 0; vv < 4; ++vv) idu[vv] = (u + vv < b) ? C.tmp[r0 + u + vv].x : 0x7fffffff;
+        for (int vv = 0; vv < 4; ++vv) idu[vv] = (u + vv < b) ? C.tmp[r0 + u + vv].x : 0x7fffffff;
 #pragma unroll
-          for (int vv = 0; vv < 4; ++vv) rk += (idu[vv] < id) ? 1 : 0;
-        }
+        for (int vv = 0; vv < 4; ++vv) rk += (idu[vv] < id) ? 1 : 0;
       }
+      place(q, p, i, a, rk);
     }
-    const int o = r0 + a + rk;
-    C.perm[o] = p;
-    C.skey[o] = (int)c0 + i;
-    if (C.copies) {  // slot-ordered copies for the collision search
-      C.sq[o] = q;
-      C.sx[o] = in.x[p];
-      C.sy[o] = in.y[p];
-      C.sz[o] = in.z[p];
-    }
-    const long long Qd = fixed_round(q, kFixDep, &ovf);
-    const long long Q32 = fixed_round(q, kFixQcum, &ovf);
-    if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;
-    atomicAdd(reinterpret_cast<unsigned long long*>(&Q[i]), (unsigned long long)Qd);
   }
   wave_sync();  // member lists read: the FFT buffers may overwrite them
   const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V

@@ -216,9 +216,10 @@ def test_many_row_pairs_multi_step(ny):
 
 
 def test_sort_capacity_paths():
-    """The fused sort's two paths (member list in LDS, or a second candidate
-    pass through global memory for pairs above the list capacity): bitwise the
-    same results for every capacity, and the oracle's."""
+    """The fused sort's paths (member list in LDS; one list round per row when
+    the pair exceeds the list but each of its rows fits; a second candidate
+    pass through global memory otherwise): bitwise the same results for every
+    capacity, and the oracle's."""
     from paper_2602_10761_amd import runtime as R
     say("sort capacity paths")
     ens = ens_small(nx=16, ny=24, nz=16, n=12000, v_jitter=3.0, precharge=0.2, re_tau=40.0, c_el=5.0)
