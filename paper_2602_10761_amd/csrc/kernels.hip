@@ -626,7 +626,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_fftx(Ctx C, Ens Eone, int one, 
 // state is stored in the previous sort's order, so the pair's members are
 // the slots of the pair's own range in that order that stayed, plus the
 // pair's mover list and the far list, both written by the push.  The push
-// counted the members of every row pair (pair_cnt); their scan is ps.
+// counted the members of every row pair (pair_cnt); their scan is ps.  The
+// members are listed in LDS (at most cap of them), bucketed by cell, ranked
+// by id and placed; a pair with more members is listed one row at a time
+// when each row fits, else it takes a second candidate pass through global
+// memory (C.tmp).  All paths give the same slots.
 // ---------------------------------------------------------------------------
 constexpr int kCand = 8;  // candidates per lane per batch (key loads in flight together)
 
