@@ -529,6 +529,40 @@ def test_pp_collisions_parity(steps):
     assert abs(gpu["q"].sum() - ref["q"].sum()) < 1e-12
 
 
+def test_full_size_next_rows():
+    """The 1e6-particle 128^3 workload with the next rows on together: 4-way
+    coupling, the stochastic wall-charging model and the 2-way coupling
+    source, two steps against the oracle (state, collision pairs, impacts and
+    histograms exact, wall charge to the rounding of its sums, source)."""
+    say("full size next rows")
+    ens = W.make_workload(2, precharge=0.05, v_jitter=3.0, pp=1, k_pp=1.0, charging=1, ssm=SSM_PARAMS)[0]
+    n = 2
+    sim = sim_of(ens, source=True)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    fsg = sim.field(0, 2).cpu().numpy().reshape(3, -1)
+    sim.close()
+    g = O.Geo.from_mesh(ens.mesh)
+    st = O.Stats(g.ny)
+    ref = O.state_of(ens)
+    want = {}
+    for k in range(n):
+        ref = O.step(g, ens.U, ref, ens.params, st, want=want if k == n - 1 else None)
+    err = state_errors(gpu, ref, ens.mesh)
+    fserr = np.abs(fsg - want["fs"]).max() / np.abs(want["fs"]).max()
+    say("  pairs", gst["pp_pairs"], st.pp_pairs, " impacts", st.impacts, " source err", fserr,
+        " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert st.pp_pairs > 100 and st.impacts.sum() > 100
+    assert gst["pp_pairs"] == st.pp_pairs
+    np.testing.assert_array_equal(gst["impacts"], st.impacts)
+    np.testing.assert_array_equal(gst["unhist"], st.unhist)
+    np.testing.assert_array_equal(gst["crel_y"], st.crel_y)
+    assert np.all(np.abs(gst["wallq"] - st.wallq) <= st.impacts)
+    assert max(err.values()) < 1e-11
+    assert np.all((fsg == 0.0) == (want["fs"] == 0.0)) and fserr < 1e-11
+
+
 def test_pp_record_refused():
     from paper_2602_10761_amd.runtime import TriboError
     sim = sim_of(pp_ensemble(n=100), traj_steps=2)
