@@ -1755,8 +1755,8 @@ __device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
 // the few spilled registers
 // RR: blocks in the hardware's round robin over the XCDs, else consecutive
 // slot ranges per XCD
-template <bool PP, bool RR>
-__global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PState in, PState out,
+template <bool PP, bool RR, bool ONE>
+__global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   // the new row ranges become the stored order's (read by the next sort)
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
@@ -1773,7 +1773,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, int one, PS
     if (perm_rec) perm_rec[s] = p;
     if (ra < 0) ra = C.start[c];
     if (rb < 0) rb = C.start[c + 1];
-    if (one) {
+    if constexpr (ONE) {
       push_one<PP>(C, Eone, in, out, s, p, c, ra, rb, wall_rec);
     } else {
       const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
@@ -1996,13 +1996,15 @@ hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const
   const int one = (C.n_ens == 1) ? 1 : 0;
   // the collision code only when an ensemble has 4-way coupling on
   const bool rr = G.push_order == 2;
+#define PUSH_LAUNCH(pp, r, o) k_push<pp, r, o><<<nb, kBlock, 0, st>>>(C, G.eh[0], in, out, perm_rec, wall_rec)
   if (G.pp_any) {
-    if (rr) k_push<true, true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
-    else k_push<true, false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+    if (rr) { if (one) PUSH_LAUNCH(true, true, true); else PUSH_LAUNCH(true, true, false); }
+    else { if (one) PUSH_LAUNCH(true, false, true); else PUSH_LAUNCH(true, false, false); }
   } else {
-    if (rr) k_push<false, true><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
-    else k_push<false, false><<<nb, kBlock, 0, st>>>(C, G.eh[0], one, in, out, perm_rec, wall_rec);
+    if (rr) { if (one) PUSH_LAUNCH(false, true, true); else PUSH_LAUNCH(false, true, false); }
+    else { if (one) PUSH_LAUNCH(false, false, true); else PUSH_LAUNCH(false, false, false); }
   }
+#undef PUSH_LAUNCH
   return hipGetLastError();
 }
 
