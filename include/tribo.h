@@ -108,7 +108,8 @@ typedef struct tf_handle tf_handle;
  *               layout [3][ny+1][nz][nx] (component, y face, z, x), node
  *               (i, j, k) at (i dx, y_faces[j], k dz); borrowed (read by
  *               every step) until tf_set_carrier replaces it
- *   n_particles 1..2^30
+ *   n_particles 0..2^30 (an empty ensemble still solves the field of zero
+ *               charge and counts its steps)
  *   pp, k_pp    4-way coupling (pp = 1; 0 = off): binary hard-sphere
  *               collisions between particles sharing a grid cell (Sec. 2.2),
  *               resolved together on the state at the start of each step

@@ -1,0 +1,196 @@
+"""Degenerate inputs through the C ABI, against the oracle.
+
+* an ensemble without particles: alone (the step then reduces to the field of
+  zero charge and the step counter) and inside a batch with an ensemble of
+  one particle and two ordinary ones, each of which stays bitwise equal to its
+  own plain run;
+* one grid cell holding hundreds of particles: its Coulomb sums and its
+  collisions run over a slot run that spans several wavefronts, and its row
+  pair exceeds the sort's member list at small capacities;
+* the wall-normal mesh at its largest size, 1024 cells: the Poisson solve and
+  a particle step.
+
+Bars as for the other parity tests: deposit, impacts and integer statistics
+exact, particle state within 1e-12 after one step and 1e-10 after several.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import KEYS, oracle_run, state_errors
+from paper_2602_10761_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sim_of(ens_list, **kw):
+    from paper_2602_10761_amd.runtime import TriboSim
+    return TriboSim(ens_list if isinstance(ens_list, list) else [ens_list], **kw)
+
+
+def ens_small(nx=16, ny=16, nz=16, n=3000, seed=0, **kw):
+    spec = W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=n, **kw)
+    return W.make_ensemble(spec, 1, seed)
+
+
+def stats_equal(gs, st):
+    assert gs["steps"] == st.steps and gs["flags"] == st.flags
+    for k, ref in (("impacts", st.impacts), ("wallq", st.wallq), ("unhist", st.unhist), ("crel_y", st.crel_y),
+                   ("qcum_y", st.qcum_y), ("qnow_y", st.qnow_y)):
+        np.testing.assert_array_equal(gs[k], ref, err_msg=k)
+
+
+def crowd(ens, n_in, cell, side, seed=7):
+    """Move the first n_in particles into a cube of edge `side` centred in
+    grid cell (i, j, k)."""
+    m = ens.mesh
+    i, j, k = cell
+    dx, dz, dy = m.lx / m.nx, m.lz / m.nz, m.yf[j + 1] - m.yf[j]
+    assert side < min(dx, dy, dz)
+    u = (np.random.default_rng(seed).uniform(size=(3, n_in)) - 0.5) * side
+    ens.x[:n_in] = (i + 0.5) * dx + u[0]
+    ens.y[:n_in] = 0.5 * (m.yf[j] + m.yf[j + 1]) + u[1]
+    ens.z[:n_in] = (k + 0.5) * dz + u[2]
+    return ens
+
+
+def test_empty_ensemble_alone():
+    ens = ens_small(n=0)
+    say("empty ensemble alone")
+    sim = sim_of(ens, keep_deposit=True)
+    sim.step(3)
+    gst = sim.stats(0)
+    gpu = sim.state_np(0)
+    phi = sim.field(0, 0).cpu().numpy()
+    Q = sim.field(0, 1).cpu().numpy()
+    sim.close()
+    _, st = oracle_run(ens, 3)
+    stats_equal(gst, st)
+    assert gst["steps"] == 3 and gst["q_sum"] == 0.0
+    assert all(gpu[k].size == 0 for k in KEYS)
+    assert not Q.any() and not phi.any()
+
+
+def test_empty_and_single_in_batch():
+    """Four ensembles of different meshes in one handle, one of them empty
+    and one a single particle: each against the oracle over 5 steps, and the
+    populated ones bitwise equal to their own plain runs."""
+    batch = [ens_small(nx=16, ny=24, nz=16, n=3000, v_jitter=3.0, precharge=0.2, c_el=5.0, re_tau=40.0),
+             ens_small(nx=8, ny=8, nz=12, n=0),
+             ens_small(nx=12, ny=10, nz=8, n=1, v_jitter=3.0, precharge=0.3),
+             ens_small(nx=24, ny=16, nz=20, n=2500, v_jitter=2.0, precharge=0.1, seed=3)]
+    n = 5
+    say("empty and single in a batch")
+    sim = sim_of(batch, keep_deposit=True)
+    sim.step(n)
+    got = [(sim.state_np(e), sim.stats(e)) for e in range(len(batch))]
+    phi_empty = sim.field(1, 0).cpu().numpy()
+    sim.close()
+    assert not phi_empty.any()
+    for e, ens in enumerate(batch):
+        ref, st = oracle_run(ens, n)
+        stats_equal(got[e][1], st)
+        if ens.n:
+            err = state_errors(got[e][0], ref, ens.mesh)
+            say("  ensemble", e, "state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+            assert max(err.values()) < 1e-10
+            plain = sim_of(ens)
+            plain.step(n)
+            mine = plain.state_np(0)
+            plain.close()
+            for k in KEYS:
+                np.testing.assert_array_equal(got[e][0][k], mine[k], err_msg=f"ensemble {e} {k}")
+
+
+@pytest.mark.parametrize("pp", [0, 1])
+def test_crowded_cell(pp):
+    """400 of 3000 particles in a cube of edge 8 inside one cell: one step
+    at 1e-12 and four at 1e-10, collision pairs exact; the same steps with
+    the sort's member list too small for the row pair (capacity 8) and with
+    no list at all are bitwise equal."""
+    from paper_2602_10761_amd import runtime as R
+    say("crowded cell, pp", pp)
+    mk = lambda: crowd(ens_small(v_jitter=2.0, precharge=0.05, c_el=1.0, pp=pp, k_pp=2.0), 400, (5, 8, 9), 8.0)
+    ens = mk()
+    g = O.Geo.from_mesh(ens.mesh)
+    i, j, k = O.locate(g, ens.x[:400], ens.y[:400], ens.z[:400])
+    assert np.all(O.cell_index(g, i, j, k) == O.cell_index(g, 5, 8, 9))
+    runs = {}
+    try:
+        for cap in (0, 8, -1):
+            R.set_tuning(sort_cap=cap)
+            sim = sim_of(mk())
+            sim.step(1)
+            one = (sim.state_np(0), sim.stats(0))
+            sim.step(3)
+            runs[cap] = (one, (sim.state_np(0), sim.stats(0)))
+            sim.close()
+    finally:
+        R.set_tuning()
+    for steps, idx in ((1, 0), (4, 1)):
+        ref, st = oracle_run(ens, steps)
+        gpu, gst = runs[0][idx]
+        err = state_errors(gpu, ref, ens.mesh)
+        say("  steps", steps, "pairs", gst["pp_pairs"], st.pp_pairs, "state err",
+            {k: float(f"{v:.2e}") for k, v in err.items()})
+        assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+        stats_equal(gst, st)
+        assert gst["pp_pairs"] == st.pp_pairs
+        if pp:
+            assert st.pp_pairs > 10 * steps
+        for cap in (8, -1):
+            for k in KEYS:
+                np.testing.assert_array_equal(runs[cap][idx][0][k], gpu[k], err_msg=f"cap {cap} {k}")
+
+
+@pytest.mark.parametrize("shape", [(8, 1024, 8), (12, 1000, 16)])
+def test_poisson_tallest_channel(shape):
+    nx, ny, nz = shape
+    say("poisson", shape)
+    ens = W.make_ensemble(W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=10, stretch=2.0, n_modes=4))
+    g = O.Geo.from_mesh(ens.mesh)
+    rng = np.random.default_rng(nx * 7 + ny)
+    Q = np.zeros(g.ncell, dtype=np.int64)
+    idx = rng.integers(0, g.ncell, max(4, g.ncell // 50))
+    Q[idx] = rng.integers(-(1 << 50), 1 << 50, idx.size)
+    sim = sim_of(ens)
+    phi = sim.poisson(0, Q).cpu().numpy().reshape(ny, nz, nx)
+    sim.close()
+    ref = O.poisson(g, Q)
+    err = np.abs(phi - ref).max() / np.abs(ref).max()
+    say("  rel err", err)
+    assert err < TOL
+
+
+def test_step_tallest_channel():
+    """A 8 x 1024 x 8 channel (1024 wall-normal cells, 4096 row pairs) with
+    20000 charged particles: one step against the oracle, the deposit exact."""
+    say("step, 1024 wall-normal cells")
+    ens = ens_small(nx=8, ny=1024, nz=8, n=20000, v_jitter=3.0, precharge=0.3, c_el=5.0)
+    sim = sim_of(ens, keep_deposit=True)
+    sim.step(1)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    Qg = sim.field(0, 1).cpu().numpy()
+    phig = sim.field(0, 0).cpu().numpy()
+    sim.close()
+    g = O.Geo.from_mesh(ens.mesh)
+    st = O.Stats(g.ny)
+    want = {}
+    ref = O.step(g, ens.U, O.state_of(ens), ens.params, st, want=want)
+    np.testing.assert_array_equal(Qg, want["Q"])
+    perr = np.abs(phig - want["phi"].ravel()).max() / np.abs(want["phi"]).max()
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  phi err", perr, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert perr < TOL
+    assert max(err.values()) < TOL
+    stats_equal(gst, st)
