@@ -187,7 +187,9 @@ int tf_init(const tf_ensemble* ens, int32_t n_ens, const tf_particles* init,
 
 /* Advance every ensemble by n_steps >= 0 steps.  With TF_STEP_RECORD the
  * steps are appended to the recorded trajectory (at most traj_steps since the
- * last tf_adjoint_step or tf_set_state). */
+ * last tf_adjoint_step or tf_set_state); a handle without any particles
+ * records nothing (its derivatives are zero), so tf_adjoint_step then
+ * returns TF_ESTATE. */
 int tf_step(tf_handle* h, int32_t n_steps, uint32_t flags);
 
 /* Copy the statistics of ensemble `ens` to the host (synchronises). */

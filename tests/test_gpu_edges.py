@@ -2,8 +2,9 @@
 
 * an ensemble without particles: alone (the step then reduces to the field of
   zero charge and the step counter) and inside a batch with an ensemble of
-  one particle and two ordinary ones, each of which stays bitwise equal to its
-  own plain run;
+  one particle and two ordinary ones (eager and by graph replays), each of
+  which stays bitwise equal to its own plain run, and in reverse mode, where
+  its derivatives are zero;
 * one grid cell holding hundreds of particles: its Coulomb sums and its
   collisions run over a slot run that spans several wavefronts, and its row
   pair exceeds the sort's member list at small capacities;
@@ -80,17 +81,19 @@ def test_empty_ensemble_alone():
     assert not Q.any() and not phi.any()
 
 
-def test_empty_and_single_in_batch():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_empty_and_single_in_batch(graphs):
     """Four ensembles of different meshes in one handle, one of them empty
-    and one a single particle: each against the oracle over 5 steps, and the
-    populated ones bitwise equal to their own plain runs."""
+    and one a single particle, stepped eagerly or by graph replays: each
+    against the oracle over 5 steps, and the populated ones bitwise equal to
+    their own plain (eager) runs."""
     batch = [ens_small(nx=16, ny=24, nz=16, n=3000, v_jitter=3.0, precharge=0.2, c_el=5.0, re_tau=40.0),
              ens_small(nx=8, ny=8, nz=12, n=0),
              ens_small(nx=12, ny=10, nz=8, n=1, v_jitter=3.0, precharge=0.3),
              ens_small(nx=24, ny=16, nz=20, n=2500, v_jitter=2.0, precharge=0.1, seed=3)]
     n = 5
-    say("empty and single in a batch")
-    sim = sim_of(batch, keep_deposit=True)
+    say("empty and single in a batch, graphs", graphs)
+    sim = sim_of(batch, keep_deposit=True, graphs=graphs)
     sim.step(n)
     got = [(sim.state_np(e), sim.stats(e)) for e in range(len(batch))]
     phi_empty = sim.field(1, 0).cpu().numpy()
@@ -194,3 +197,46 @@ def test_step_tallest_channel():
     assert perr < TOL
     assert max(err.values()) < TOL
     stats_equal(gst, st)
+
+
+def test_adjoint_with_empty_ensemble():
+    """Reverse mode over a batch holding an empty ensemble: the empty one's
+    derivatives are zero and the others' equal those of their own handles,
+    for both objectives (mean charge, wall charge flux)."""
+    import torch
+
+    from paper_2602_10761_amd.runtime import TriboSim
+
+    def charged(seed, n, nx=8, ny=12, nz=8):
+        spec = W.CONFIGS[1].replace(nx=nx, ny=ny, nz=nz, n_particles=n, v_jitter=4.0, re_tau=10.0,
+                                    density_ratio=200.0, precharge=0.3, c_el=40.0)
+        ens = W.make_ensemble(spec, 1, seed)
+        ens.params["k_c"] = 0.05
+        return ens
+
+    def grads(ens_list, n_steps, which):
+        sim = TriboSim(ens_list, traj_steps=n_steps)
+        sim.step(n_steps, record=True)
+        lam, ww = [], np.zeros((sim.n_ens, 2))
+        for e, E in enumerate(ens_list):
+            L = {k: torch.zeros(E.n, dtype=torch.float64, device=sim.dev) for k in KEYS}
+            if which == 0 and E.n:
+                L["q"].fill_(1.0 / E.n)
+            if which == 1:
+                ww[e, :] = 1.0 / (n_steps * E.params["dt"])
+            lam.append(L)
+        dth = sim.adjoint(lam, ww)
+        sim.close()
+        return dth
+
+    say("adjoint with an empty ensemble")
+    batch = [charged(1, 500), charged(0, 0, nx=12, ny=10, nz=8), charged(2, 400)]
+    n_steps = 12
+    for which in (0, 1):
+        both = grads(batch, n_steps, which)
+        say("  J", which + 1, both.tolist())
+        assert not both[1].any()
+        for e in (0, 2):
+            one = grads([batch[e]], n_steps, which)[0]
+            assert np.abs(one).max() > 0
+            np.testing.assert_allclose(both[e], one, rtol=1e-13, atol=1e-300)
