@@ -9,7 +9,9 @@
   collisions run over a slot run that spans several wavefronts, and its row
   pair exceeds the sort's member list at small capacities;
 * the wall-normal mesh at its largest size, 1024 cells: the Poisson solve and
-  a particle step.
+  a particle step;
+* particles at rest exactly on cell faces and at the ends of the periodic
+  directions, binned the same way on both sides at every step.
 
 Bars as for the other parity tests: deposit, impacts and integer statistics
 exact, particle state within 1e-12 after one step and 1e-10 after several.
@@ -240,3 +242,56 @@ def test_adjoint_with_empty_ensemble():
             one = grads([batch[e]], n_steps, which)[0]
             assert np.abs(one).max() > 0
             np.testing.assert_allclose(both[e], one, rtol=1e-13, atol=1e-300)
+
+
+def test_particles_on_cell_faces():
+    """Charged particles at rest exactly on cell faces (x = i dx, z = k dz,
+    y on the stretched faces, x or z = 0, and the last double below the
+    periodic length) in a carrier at rest, without electric forces, among
+    moving particles: they stay where they are, and both sides put them in
+    the same cells at every step (the deposit bit-exact, histograms, the
+    others' state as the oracle)."""
+    say("particles on cell faces")
+    ens = ens_small(n=3000, v_jitter=2.0, precharge=0.2, c_el=0.0)
+    ens.U[...] = 0.0
+    m = ens.mesh
+    nf = 600
+    rng = np.random.default_rng(11)
+    dx, dz = m.lx / m.nx, m.lz / m.nz
+    i = rng.integers(0, m.nx, nf)
+    k = rng.integers(0, m.nz, nf)
+    j = rng.integers(1, m.ny - 1, nf)
+    ux, uy, uz = rng.uniform(size=(3, nf))
+    x = (i + ux) * dx
+    y = m.yf[j] + uy * (m.yf[j + 1] - m.yf[j])
+    z = (k + uz) * dz
+    third = nf // 3
+    x[:third] = i[:third] * dx
+    z[third:2 * third] = k[third:2 * third] * dz
+    y[2 * third:] = m.yf[j[2 * third:]]
+    x[:8] = (0.0, np.nextafter(m.lx, 0.0)) * 4
+    z[third:third + 8] = (0.0, np.nextafter(m.lz, 0.0)) * 4
+    ens.x[:nf], ens.y[:nf], ens.z[:nf] = x, y, z
+    for a in (ens.vx, ens.vy, ens.vz):
+        a[:nf] = 0.0
+    n = 3
+    sim = sim_of(ens, keep_deposit=True)
+    sim.step(n)
+    gpu = sim.state_np(0)
+    gst = sim.stats(0)
+    Qg = sim.field(0, 1).cpu().numpy()
+    sim.close()
+    g = O.Geo.from_mesh(ens.mesh)
+    st = O.Stats(g.ny)
+    ref = O.state_of(ens)
+    want = {}
+    for s in range(n):
+        ref = O.step(g, ens.U, ref, ens.params, st, want=want if s == n - 1 else None)
+    for key, v in (("x", x), ("y", y), ("z", z)):
+        np.testing.assert_array_equal(ref[key][:nf], v)
+        np.testing.assert_array_equal(gpu[key][:nf], v)
+    np.testing.assert_array_equal(Qg, want["Q"])
+    err = state_errors(gpu, ref, ens.mesh)
+    say("  state err", {kk: float(f"{v:.2e}") for kk, v in err.items()})
+    assert max(err.values()) < 1e-10
+    stats_equal(gst, st)
