@@ -1751,12 +1751,13 @@ __device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
   *rb = el == 64 ? -1 : s0 + el;
 }
 
-// four waves per SIMD (at most 128 VGPRs): more memory chains in flight beat
-// the few spilled registers
+// ONE (a handle of one ensemble, its descriptor by value): four waves per
+// SIMD (at most 128 VGPRs, none spilled); the batched form, which needs more
+// registers, three waves per SIMD rather than spilling to memory
 // RR: blocks in the hardware's round robin over the XCDs, else consecutive
 // slot ranges per XCD
 template <bool PP, bool RR, bool ONE>
-__global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, PState in, PState out,
+__global__ __launch_bounds__(kBlock, ONE ? 4 : 3) void k_push(Ctx C, Ens Eone, PState in, PState out,
                                                  int* __restrict__ perm_rec, signed char* __restrict__ wall_rec) {
   // the new row ranges become the stored order's (read by the next sort)
   for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r <= C.n_rows; r += (long long)gridDim.x * kBlock)
@@ -1776,7 +1777,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_push(Ctx C, Ens Eone, PState in, 
     if constexpr (ONE) {
       push_one<PP>(C, Eone, in, out, s, p, c, ra, rb, wall_rec);
     } else {
-      const int e_lane = find_off(C.c_off, C.n_ens + 1, c);
+      // the ensemble of the wave's first slot (one uniform search: an
+      // ensemble's particles fill a contiguous slot range); lanes past its end
+      // (a wave across an ensemble boundary) search their own
+      const int e0 = find_off(C.p_off, C.n_ens + 1, (long long)__builtin_amdgcn_readfirstlane(s));
+      const int e_lane = s < C.p_off[e0 + 1] ? e0 : find_off(C.p_off, C.n_ens + 1, (long long)s);
       // waterfall over the ensembles present in this wave (usually one)
       bool done = false;
       while (!done) {
@@ -2048,7 +2053,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(Ctx C, PState in) {
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
   if (s >= C.n_tot) return;
   const int c = C.skey[s];
-  const int e = find_off(C.c_off, C.n_ens + 1, c);
+  // the ensemble of the wave's first slot (uniform search), else the lane's own
+  const int e0 = find_off(C.p_off, C.n_ens + 1, (long long)__builtin_amdgcn_readfirstlane(s));
+  const int e = s < C.p_off[e0 + 1] ? e0 : find_off(C.p_off, C.n_ens + 1, (long long)s);
   const Ens& E = C.ens[e];
   double inc[4] = {0.0, 0.0, 0.0, 0.0};
   int hit = 0;
