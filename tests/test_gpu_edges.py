@@ -11,7 +11,8 @@
 * the wall-normal mesh at its largest size, 1024 cells: the Poisson solve and
   a particle step;
 * particles at rest exactly on cell faces and at the ends of the periodic
-  directions, binned the same way on both sides at every step.
+  directions, binned the same way on both sides at every step;
+* particle Reynolds numbers above 1000 (the constant drag coefficient).
 
 Bars as for the other parity tests: deposit, impacts and integer statistics
 exact, particle state within 1e-12 after one step and 1e-10 after several.
@@ -295,3 +296,25 @@ def test_particles_on_cell_faces():
     say("  state err", {kk: float(f"{v:.2e}") for kk, v in err.items()})
     assert max(err.values()) < 1e-10
     stats_equal(gst, st)
+
+
+def test_fast_particles_newton_drag():
+    """Particles 3000 wall units per unit time faster than the carrier in x:
+    particle Reynolds numbers above 1000 (the constant drag coefficient
+    branch) and several cells crossed per step; one step at 1e-12 and three
+    at 1e-10 against the oracle."""
+    say("fast particles, Re_p > 1000")
+    ens = ens_small(nx=32, ny=32, nz=32, n=4000, v_jitter=2.0, precharge=0.1, c_el=5.0)
+    ens.vx[:] += 3000.0
+    assert np.all(2900.0 * ens.d > 1000.0)  # |v - u| d, carrier speeds below 100
+    for steps in (1, 3):
+        sim = sim_of(ens)
+        sim.step(steps)
+        gpu = sim.state_np(0)
+        gst = sim.stats(0)
+        sim.close()
+        ref, st = oracle_run(ens, steps)
+        err = state_errors(gpu, ref, ens.mesh)
+        say("  steps", steps, "state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+        assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+        stats_equal(gst, st)

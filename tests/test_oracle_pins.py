@@ -86,6 +86,28 @@ def test_stokes_settling(rr, gacc, d):
     assert np.all(s["vy"] == 0.0) and np.all(s["vz"] == 0.0)
 
 
+def test_newton_regime_settling():
+    # Re_p > 1000: C_D = 0.424, so phi_D = 0.424 Re_p / 24 and the terminal
+    # velocity of the semi-implicit step, v phi_D(v d) / tau_p = (1 - 1/rr) g,
+    # has the closed form v_t = sqrt(24 tau_p (1 - 1/rr) g / (0.424 d))
+    g = small_geo()
+    U = np.zeros((3, g.ny + 1, g.nz, g.nx))
+    rr, d, gacc = 2.0, 1.0, 1.0e6
+    taup = rr * d * d / 18.0
+    vt = math.sqrt(24.0 * taup * (1.0 - 1.0 / rr) * gacc / (0.424 * d))
+    assert vt * d > 1500.0
+    s = zero_state(2)
+    s["d"][:] = d
+    s["x"][:] = [1.0, 5.0]
+    s["y"][:] = g.ly / 2
+    s["z"][:] = [0.5, 1.5]
+    prm = dict(BASE, density_ratio=rr, g=(gacc, 0.0, 0.0), dt=0.02 * taup)
+    for _ in range(2000):
+        s = O.step(g, U, s, prm)
+    np.testing.assert_allclose(s["vx"], vt, rtol=1e-12)
+    assert np.all(s["vy"] == 0.0) and np.all(s["vz"] == 0.0)
+
+
 def test_drag_relaxes_toward_carrier():
     # uniform carrier flow, particle at rest: velocity approaches u monotonically
     g = small_geo()
