@@ -484,6 +484,40 @@ def test_lone_charge_pulled_to_grounded_wall(j0, q):
 # --------------------------------------------------------------------------
 # Whole-step invariants on a synthetic channel
 # --------------------------------------------------------------------------
+def test_profile_statistics_by_hand():
+    # Sec. 4.1 profiles over the wall-normal grid rows: particles at rest in
+    # still fluid without forces keep their rows and charges, so after n
+    # steps the time-summed count and charge (2^-32 units) of a row are n
+    # times its population and charge, and the latest charge (2^-48 units)
+    # is the row's charge once; dyadic charges make every sum exact
+    g = small_geo(ny=6)
+    U = np.zeros((3, g.ny + 1, g.nz, g.nx))
+    rows = [0, 2, 2, 3, 3, 3, 5]
+    qs = [0.5, -0.25, 0.125, 1.0, -0.75, 0.0625, -1.5]
+    s = zero_state(len(rows))
+    s["d"][:] = 0.2
+    for p, (j, q) in enumerate(zip(rows, qs)):
+        s["x"][p] = (p + 0.5) * g.lx / (len(rows) + 1)
+        s["y"][p] = 0.5 * (g.yf[j] + g.yf[j + 1])
+        s["z"][p] = 0.3 * g.lz
+        s["q"][p] = q
+    n = 7
+    st = O.Stats(g.ny)
+    for _ in range(n):
+        s = O.step(g, U, s, dict(BASE, k_c=0.0), st)
+    want_c = [0] * g.ny
+    want_q32 = [0] * g.ny
+    want_q48 = [0] * g.ny
+    for j, q in zip(rows, qs):
+        want_c[j] += n
+        want_q32[j] += n * int(q * 2 ** 32)
+        want_q48[j] += int(q * 2 ** 48)
+    assert st.crel_y.tolist() == want_c
+    assert st.qcum_y.tolist() == want_q32
+    assert st.qnow_y.tolist() == want_q48
+    assert st.steps == n and st.flags == 0
+
+
 def test_channel_invariants():
     ens = W.make_ensemble(W.CONFIGS[1].replace(n_particles=3000, precharge=0.01, v_jitter=3.0,
                                                density_ratio=100.0))
