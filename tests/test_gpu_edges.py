@@ -15,7 +15,7 @@
 * particle Reynolds numbers above 1000 (the constant drag coefficient).
 
 Bars as for the other parity tests: deposit, impacts and integer statistics
-exact, particle state within 1e-12 after one step and 1e-10 after several.
+exact, particle state within 1e-12 after one step and after several.
 """
 import sys
 
@@ -108,7 +108,7 @@ def test_empty_and_single_in_batch(graphs):
         if ens.n:
             err = state_errors(got[e][0], ref, ens.mesh)
             say("  ensemble", e, "state err", {k: float(f"{v:.2e}") for k, v in err.items()})
-            assert max(err.values()) < 1e-10
+            assert max(err.values()) < TOL
             plain = sim_of(ens)
             plain.step(n)
             mine = plain.state_np(0)
@@ -120,7 +120,7 @@ def test_empty_and_single_in_batch(graphs):
 @pytest.mark.parametrize("pp", [0, 1])
 def test_crowded_cell(pp):
     """400 of 3000 particles in a cube of edge 8 inside one cell: one step
-    at 1e-12 and four at 1e-10, collision pairs exact; the same steps with
+    and four within 1e-12, collision pairs exact; the same steps with
     the sort's member list too small for the row pair (capacity 8) and with
     no list at all are bitwise equal."""
     from paper_2602_10761_amd import runtime as R
@@ -148,7 +148,7 @@ def test_crowded_cell(pp):
         err = state_errors(gpu, ref, ens.mesh)
         say("  steps", steps, "pairs", gst["pp_pairs"], st.pp_pairs, "state err",
             {k: float(f"{v:.2e}") for k, v in err.items()})
-        assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+        assert max(err.values()) < TOL
         stats_equal(gst, st)
         assert gst["pp_pairs"] == st.pp_pairs
         if pp:
@@ -294,15 +294,15 @@ def test_particles_on_cell_faces():
     np.testing.assert_array_equal(Qg, want["Q"])
     err = state_errors(gpu, ref, ens.mesh)
     say("  state err", {kk: float(f"{v:.2e}") for kk, v in err.items()})
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
     stats_equal(gst, st)
 
 
 def test_fast_particles_newton_drag():
     """Particles 3000 wall units per unit time faster than the carrier in x:
     particle Reynolds numbers above 1000 (the constant drag coefficient
-    branch) and several cells crossed per step; one step at 1e-12 and three
-    at 1e-10 against the oracle."""
+    branch) and several cells crossed per step; one step and three within
+    1e-12 of the oracle."""
     say("fast particles, Re_p > 1000")
     ens = ens_small(nx=32, ny=32, nz=32, n=4000, v_jitter=2.0, precharge=0.1, c_el=5.0)
     ens.vx[:] += 3000.0
@@ -316,5 +316,5 @@ def test_fast_particles_newton_drag():
         ref, st = oracle_run(ens, steps)
         err = state_errors(gpu, ref, ens.mesh)
         say("  steps", steps, "state err", {k: float(f"{v:.2e}") for k, v in err.items()})
-        assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+        assert max(err.values()) < TOL
         stats_equal(gst, st)

@@ -1,8 +1,11 @@
 """GPU parity of the HIP particle step against the CPU oracle (through the C ABI).
 
 Bars: deposit, impact counts and all integer statistics bit-exact; particle
-state within 1e-12 normwise relative per step from the same input state;
-potential within 1e-12 relative to its maximum.
+state within 1e-12 normwise relative, after one step from the same input
+state and after several (rounding differences grow through the charge
+updates of wall impacts, collisions and the Coulomb sums; every case here
+measured below 1e-13, e.g. 7e-14 after 40 steps with 110 impacts); potential
+within 1e-12 relative to its maximum.
 """
 import sys
 
@@ -167,7 +170,7 @@ def test_multi_step_parity():
     say("  impacts", st.impacts, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
     assert st.impacts.sum() > 50
     assert_stats_equal(gst, st)
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
     sim.close()
 
 
@@ -212,7 +215,7 @@ def test_many_row_pairs_multi_step(ny):
     err = state_errors(gpu, ref, ens.mesh)
     say("  impacts", st.impacts, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
     assert_stats_equal(gst, st)
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
 
 
 def test_sort_capacity_paths():
@@ -237,7 +240,7 @@ def test_sort_capacity_paths():
     ref, st = oracle_run(ens, n)
     err = state_errors(runs[0][0], ref, ens.mesh)
     say("  state err", {k: float(f"{v:.2e}") for k, v in err.items()})
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
     assert_stats_equal(runs[0][1], st)
     for cap in (-1, 8, 64):
         for k in KEYS:
@@ -288,7 +291,7 @@ def test_carrier_replacement(graphs):
         s = O.step(g, U2, s, ens.params, None)
     err = state_errors(gpu, s, ens.mesh)
     say("  state err", {k: float(f"{v:.2e}") for k, v in err.items()})
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
 
 
 def test_far_movers_multi_step():
@@ -324,7 +327,7 @@ def test_far_movers_multi_step():
     for k, ref in (("wallq", st.wallq), ("qcum_y", st.qcum_y), ("qnow_y", st.qnow_y)):
         d = np.abs(np.asarray(gst[k], dtype=np.float64) - np.asarray(ref, dtype=np.float64))
         assert d.max() <= 4 * n, (k, d.max())
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
 
 
 @pytest.mark.parametrize("cfg", [2, 3])
@@ -385,8 +388,8 @@ def test_full_size_incremental_steps(cfg):
     err = state_errors(gpu, ref, m)
     say("  impacts", st.impacts, " phi err", perr, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
     assert gst["steps"] == n and st.impacts.sum() > 500
-    assert perr < 1e-11
-    assert max(err.values()) < 1e-11
+    assert perr < TOL
+    assert max(err.values()) < TOL
     assert_stats_equal(gst, st)
 
 
@@ -523,7 +526,7 @@ def test_pp_collisions_parity(steps):
     say("  pairs", gst["pp_pairs"], st.pp_pairs, " state err", {k: float(f"{v:.2e}") for k, v in err.items()})
     assert st.pp_pairs > 10 * steps
     assert gst["pp_pairs"] == st.pp_pairs
-    assert max(err.values()) < (TOL if steps == 1 else 1e-10)
+    assert max(err.values()) < TOL
     np.testing.assert_array_equal(gst["impacts"], st.impacts)
     np.testing.assert_array_equal(gst["crel_y"], st.crel_y)
     assert abs(gpu["q"].sum() - ref["q"].sum()) < 1e-12
@@ -559,8 +562,8 @@ def test_full_size_next_rows():
     np.testing.assert_array_equal(gst["unhist"], st.unhist)
     np.testing.assert_array_equal(gst["crel_y"], st.crel_y)
     assert np.all(np.abs(gst["wallq"] - st.wallq) <= st.impacts)
-    assert max(err.values()) < 1e-11
-    assert np.all((fsg == 0.0) == (want["fs"] == 0.0)) and fserr < 1e-11
+    assert max(err.values()) < TOL
+    assert np.all((fsg == 0.0) == (want["fs"] == 0.0)) and fserr < TOL
 
 
 def test_pp_record_refused():
@@ -600,7 +603,7 @@ def test_ssm_parity():
     assert st.impacts.sum() > 40
     np.testing.assert_array_equal(gst["impacts"], st.impacts)
     np.testing.assert_array_equal(gst["unhist"], st.unhist)
-    assert max(err.values()) < 1e-10
+    assert max(err.values()) < TOL
     # wall charge: sums of rne(-dq 2^40) (an impact may round the other way)
     assert np.all(np.abs(gst["wallq"] - st.wallq) <= st.impacts)
     assert np.std(gpu["q"][gpu["q"] != 0]) > 0  # random, not one value
@@ -642,4 +645,5 @@ def test_carrier_every_step_with_graphs():
     gpu = sim.state_np(0)
     sim.close()
     err = state_errors(gpu, s, ens.mesh)
-    assert max(err.values()) < 1e-10
+    say("  carrier every step, state err", {k: float(f"{v:.2e}") for k, v in err.items()})
+    assert max(err.values()) < TOL
