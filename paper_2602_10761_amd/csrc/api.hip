@@ -429,9 +429,6 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
   C.perm = cv.take<int>(S.n_tot);
   C.skey = cv.take<int>(S.n_tot);
   C.sq = cv.take<double>(S.n_tot);
-  C.sx = cv.take<double>(S.n_tot);
-  C.sy = cv.take<double>(S.n_tot);
-  C.sz = cv.take<double>(S.n_tot);
   const long long nbs = (S.c_tot + 4 * kBlock - 1) / (4 * kBlock);
   C.scan_part = cv.take<int>(nbs + 1);
   C.spec = cv.take<double2>(S.s_tot);
@@ -460,7 +457,6 @@ size_t layout(const Sizes& S, int n_ens, int traj_steps, uint32_t flags, void* b
     C.n_ens = n_ens;
     C.n_tot = S.n_tot;
     C.c_tot = S.c_tot;
-    C.copies = S.pp_any ? 1 : 0;
     h->C = C;
     h->A = A;
     h->B = B;
@@ -513,7 +509,7 @@ hipError_t enqueue_step(tf_handle* h, const PState& in, const PState& out, const
   if (rec && (e = launch_record(rec->skey, h->C.skey, h->C.n_tot, rec->start, h->C.start, rec->phi, h->C.phi,
                                 h->C.c_tot, h->stream)) != hipSuccess)
     return e;
-  if (h->C.cinc && (e = launch_collide(h->C, in, h->stream)) != hipSuccess) return e;
+  if (h->C.cinc && (e = launch_collide(h->C, h->G.eh[0], in, h->stream)) != hipSuccess) return e;
   if ((e = launch_push(h->C, h->G, in, out, rec ? rec->perm : nullptr, rec ? rec->wall : nullptr, h->stream)) !=
       hipSuccess)
     return e;

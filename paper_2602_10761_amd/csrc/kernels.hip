@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_place(Ctx C, const int* __restrict__
 
 // order each run by id: the slot of a particle is its run start plus the
 // number of run members with a smaller id.  Writes perm, skey and the
-// slot-ordered copies of charge and position.
+// slot-ordered copy of the charge (read by the deposit that follows).
 __global__ __launch_bounds__(kBlock) void k_rank(Ctx C, PState in) {
   const long long s0 = (long long)blockIdx.x * (kBlock * kIlp) + threadIdx.x;
   int4 rec[kIlp];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(Ctx C, PState in) {
   }
   bool ok[kIlp];
   int a[kIlp], b[kIlp];
-  double q[kIlp], x[kIlp], y[kIlp], z[kIlp];
+  double q[kIlp];
 #pragma unroll
   for (int r = 0; r < kIlp; ++r) {
     const int p = rec[r].y, c = rec[r].z;
@@ -234,9 +234,6 @@ __global__ __launch_bounds__(kBlock) void k_rank(Ctx C, PState in) {
       a[r] = C.start[c];
       b[r] = C.start[c + 1];
       q[r] = in.q[p];
-      x[r] = in.x[p];
-      y[r] = in.y[p];
-      z[r] = in.z[p];
     }
   }
 #pragma unroll
@@ -249,9 +246,6 @@ __global__ __launch_bounds__(kBlock) void k_rank(Ctx C, PState in) {
     C.perm[o] = rec[r].y;
     C.skey[o] = rec[r].z;
     C.sq[o] = q[r];
-    C.sx[o] = x[r];
-    C.sy[o] = y[r];
-    C.sz[o] = z[r];
   }
 }
 
@@ -813,12 +807,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     const int o = r0 + a + rk;
     C.perm[o] = p;
     C.skey[o] = (int)c0 + i;
-    if (C.copies) {  // slot-ordered copies for the collision search
-      C.sq[o] = q;
-      C.sx[o] = in.x[p];
-      C.sy[o] = in.y[p];
-      C.sz[o] = in.z[p];
-    }
     const long long Qd = fixed_round(q, kFixDep, &ovf);
     const long long Q32 = fixed_round(q, kFixQcum, &ovf);
     if (i < nx) rq32[0] += Q32; else rq32[1] += Q32;
@@ -2047,37 +2035,132 @@ hipError_t launch_source(const Ctx& C, hipStream_t st) {
   return hipGetLastError();
 }
 
-// 4-way coupling: per slot, the velocity and charge increments of its
-// collisions (zero for ensembles without it), read by the push
-__global__ __launch_bounds__(kBlock) void k_collide(Ctx C, PState in) {
+// 4-way coupling: per slot, the velocity and charge increments of its binary
+// hard-sphere collisions with the other particles of its cell on the state at
+// the start of the step (zero for ensembles without it), summed in ascending
+// id and read by the push; the pairs with a partner of larger id are counted.
+// As in the push's Coulomb sum, a cell's slots are a run of the wave's lanes:
+// the mates' positions and charges come from their lanes (cross-lane reads),
+// those of runs across the wave's ends through perm, the loops running while
+// some lane of the wave has a mate left.  A slot with no mate closer than
+// d_max (>= (d + d_max)/2) reads nothing more; pairs beyond (d + d_max)/2 are
+// skipped before the partner's velocity and diameter are read.  ONE: a handle
+// of one ensemble, its descriptor by value.
+template <bool ONE>
+__global__ __launch_bounds__(kBlock) void k_collide(Ctx C, Ens Eone, PState in) {
   const int s = (int)(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
-  if (s >= C.n_tot) return;
-  const int c = C.skey[s];
-  // the ensemble of the wave's first slot (uniform search), else the lane's own
-  const int e0 = find_off(C.p_off, C.n_ens + 1, (long long)__builtin_amdgcn_readfirstlane(s));
-  const int e = s < C.p_off[e0 + 1] ? e0 : find_off(C.p_off, C.n_ens + 1, (long long)s);
-  const Ens& E = C.ens[e];
-  double inc[4] = {0.0, 0.0, 0.0, 0.0};
-  int hit = 0;
-  if (E.pp) {
-    const int npp = pp_collide(C, E, in, s, C.perm[s], c, inc, &hit);
-    if (npp) atomicAdd((unsigned long long*)&C.stats[E.st_off + ST_PP], (unsigned long long)npp);
+  const bool act = s < C.n_tot;
+  const int c = act ? C.skey[s] : 0x7fffffff;
+  const int p = act ? C.perm[s] : 0;
+  // the slots of the lane's cell from the wave's keys (every lane takes part)
+  int ra, rb;
+  cell_run(s, c, &ra, &rb);
+  int e = 0;
+  bool want = false;
+  double x = 0.0, y = 0.0, z = 0.0, q = 0.0, dmax = 0.0;
+  if (act) {
+    if constexpr (ONE) {
+      want = Eone.pp != 0;
+      if (want) dmax = __longlong_as_double(C.stats[Eone.st_off + ST_DMAX]);
+    } else {
+      // the ensemble of the wave's first slot (uniform search), else the lane's own
+      const int e0 = find_off(C.p_off, C.n_ens + 1, (long long)__builtin_amdgcn_readfirstlane(s));
+      e = s < C.p_off[e0 + 1] ? e0 : find_off(C.p_off, C.n_ens + 1, (long long)s);
+      want = C.ens[e].pp != 0;
+      if (want) dmax = __longlong_as_double(C.stats[C.ens[e].st_off + ST_DMAX]);
+    }
+    if (ra < 0) ra = C.start[c];
+    if (rb < 0) rb = C.start[c + 1];
+    x = in.x[p];
+    y = in.y[p];
+    z = in.z[p];
+    q = in.q[p];
   }
+  const int lane = (int)(threadIdx.x & 63u);
+  const int s0 = s - lane;
+  const int n = want ? rb - ra : 0;
+  // is any mate closer than d_max (>= (d + d_max)/2)?
+  bool near = false;
+  for (int kk = 0; __any(kk < n); ++kk) {
+    const int t = ra + kk, src = t - s0;
+    double ox = __shfl(x, src & 63, 64), oy = __shfl(y, src & 63, 64), oz = __shfl(z, src & 63, 64);
+    if (kk < n && t != s) {
+      if (!(src >= 0 && src < 64)) {
+        const int pt = C.perm[t];
+        ox = in.x[pt];
+        oy = in.y[pt];
+        oz = in.z[pt];
+      }
+      const double rx = x - ox, ry = y - oy, rz = z - oz;
+      const double r2 = (rx * rx + ry * ry) + rz * rz;
+      near |= r2 < dmax * dmax;
+    }
+  }
+  double inc[4] = {0.0, 0.0, 0.0, 0.0};
+  int hit = 0, npp = 0;
+  if (__any(near)) {
+    const int m = near ? n : 0;
+    double vx = 0.0, vy = 0.0, vz = 0.0, d = 0.0, rcut2 = 0.0, kpp = 0.0;
+    if (near) {
+      vx = in.vx[p];
+      vy = in.vy[p];
+      vz = in.vz[p];
+      d = in.d[p];
+      const double rc = 0.5 * (d + dmax);
+      rcut2 = rc * rc;
+      kpp = ONE ? Eone.kpp : C.ens[e].kpp;
+    }
+    for (int kk = 0; __any(kk < m); ++kk) {
+      const int t = ra + kk, src = t - s0;
+      double ox = __shfl(x, src & 63, 64), oy = __shfl(y, src & 63, 64), oz = __shfl(z, src & 63, 64);
+      double oq = __shfl(q, src & 63, 64);
+      const int pv = __shfl(p, src & 63, 64);
+      if (kk < m && t != s) {
+        int pt = pv;
+        if (!(src >= 0 && src < 64)) {
+          pt = C.perm[t];
+          ox = in.x[pt];
+          oy = in.y[pt];
+          oz = in.z[pt];
+          oq = in.q[pt];
+        }
+        const double rx = x - ox, ry = y - oy, rz = z - oz;
+        const double r2 = (rx * rx + ry * ry) + rz * rz;
+        if (r2 < rcut2) {
+          const PPHit h = pp_pair(pt, in, kpp, rx, ry, rz, r2, d, vx, vy, vz, q, oq);
+          if (h.hit) {
+            hit = 1;
+            if (t > s) ++npp;
+            inc[0] += h.dvx;
+            inc[1] += h.dvy;
+            inc[2] += h.dvz;
+            inc[3] += h.dq;
+          }
+        }
+      }
+    }
+  }
+  if (npp)
+    atomicAdd((unsigned long long*)&C.stats[(ONE ? Eone.st_off : C.ens[e].st_off) + ST_PP], (unsigned long long)npp);
+  if (!act) return;
   // the increments only where a collision happened (the push reads the flag)
   C.chit[s] = (unsigned char)hit;
   if (hit) {
-    const long long n = C.n_tot;
+    const long long nt = C.n_tot;
     C.cinc[s] = inc[0];
-    C.cinc[n + s] = inc[1];
-    C.cinc[2 * n + s] = inc[2];
-    C.cinc[3 * n + s] = inc[3];
+    C.cinc[nt + s] = inc[1];
+    C.cinc[2 * nt + s] = inc[2];
+    C.cinc[3 * nt + s] = inc[3];
   }
 }
 
-hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st) {
+hipError_t launch_collide(const Ctx& C, const Ens& Eone, const PState& in, hipStream_t st) {
   if (C.n_tot == 0) return hipSuccess;
   const int nb = (int)((C.n_tot + kBlock - 1) / kBlock);
-  k_collide<<<nb, kBlock, 0, st>>>(C, in);
+  if (C.n_ens == 1)
+    k_collide<true><<<nb, kBlock, 0, st>>>(C, Eone, in);
+  else
+    k_collide<false><<<nb, kBlock, 0, st>>>(C, Eone, in);
   return hipGetLastError();
 }
 

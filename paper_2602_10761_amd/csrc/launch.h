@@ -68,7 +68,7 @@ hipError_t launch_poisson(const Ctx& C, const LaunchGeo& G, int e0, int e1, cons
 hipError_t launch_push(const Ctx& C, const LaunchGeo& G, const PState& in, const PState& out, int* perm_rec,
                        signed char* wall_rec, hipStream_t st);
 // 4-way coupling: per-slot collision increments (before the push)
-hipError_t launch_collide(const Ctx& C, const PState& in, hipStream_t st);
+hipError_t launch_collide(const Ctx& C, const Ens& Eone, const PState& in, hipStream_t st);
 // copies of a recorded step's sorted keys [n], cell starts [nc + 1] and phi [nc]
 hipError_t launch_record(int* skey_d, const int* skey, long long n, int* start_d, const int* start, double* phi_d,
                          const double* phi, long long nc, hipStream_t st);

@@ -193,7 +193,7 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
       }
     }
   }
-  // 4-way coupling: the collision increments of this slot (pp_collide)
+  // 4-way coupling: the collision increments of this slot (k_collide)
   double cvx = 0.0, cvy = 0.0, cvz = 0.0, cq = 0.0;
   if constexpr (PP) {
     if (E.pp && C.chit[s]) {  // increments stored only for the slots with a collision
@@ -236,51 +236,6 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   F.v1[0] = v1x; F.v1[1] = v1y; F.v1[2] = v1z;
   F.x1 = x1; F.y1 = y1; F.z1 = z1;
   F.qc = pp ? q + cq : q;
-}
-
-// 4-way coupling: binary hard-sphere collisions of slot s (cell c, state at
-// the start of the step) with the other particles of its cell, increments
-// summed in ascending id; pairs farther apart than (d + d_max)/2 are skipped
-// before any gather, and a slot with no mate closer than d_max (>= that
-// cutoff) reads nothing of its own state.  Returns the pairs with a partner
-// of larger id (each pair is counted once over the two particles); *hit: some
-// pair collided.
-__device__ __forceinline__ int pp_collide(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
-                                          double inc[4], int* hit) {
-  inc[0] = inc[1] = inc[2] = inc[3] = 0.0;
-  *hit = 0;
-  const double x = C.sx[s], y = C.sy[s], z = C.sz[s], q = C.sq[s];
-  const double dmax = __longlong_as_double(C.stats[E.st_off + ST_DMAX]);
-  const int a = C.start[c], b = C.start[c + 1];
-  bool near = false;
-  for (int t = a; t < b; ++t) {
-    if (t == s) continue;
-    const double rx = x - C.sx[t], ry = y - C.sy[t], rz = z - C.sz[t];
-    const double r2 = (rx * rx + ry * ry) + rz * rz;
-    near |= r2 < dmax * dmax;
-  }
-  if (!near) return 0;
-  const double vx = in.vx[p], vy = in.vy[p], vz = in.vz[p], d = in.d[p];
-  const double rc = 0.5 * (d + dmax);
-  const double rcut2 = rc * rc;
-  int npp = 0;
-  for (int t = a; t < b; ++t) {
-    if (t == s) continue;
-    const double ox = C.sx[t], oy = C.sy[t], oz = C.sz[t];
-    const double rx = x - ox, ry = y - oy, rz = z - oz;
-    const double r2 = (rx * rx + ry * ry) + rz * rz;
-    if (!(r2 < rcut2)) continue;
-    const PPHit h = pp_pair(C.perm[t], in, E.kpp, rx, ry, rz, r2, d, vx, vy, vz, q, C.sq[t]);
-    if (h.hit) {
-      *hit = 1;
-      if (t > s) ++npp;
-      inc[0] += h.dvx;
-      inc[1] += h.dvy;
-      inc[2] += h.dvz;
-      inc[3] += h.dq;
-    }
-  }
-  return npp;
 }
 
 }  // namespace tf

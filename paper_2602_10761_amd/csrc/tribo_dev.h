@@ -111,10 +111,7 @@ struct Ctx {
   int4* tmp;                 // [n_tot]   (id, old slot, cell, 0), unordered within a cell
   int* perm;                 // [n_tot]   new slot -> old slot, ordered by (cell, id)
   int* skey;                 // [n_tot]   cell of each new slot
-  double* sq;                // [n_tot]   charge of each new slot
-  double *sx, *sy, *sz;      // [n_tot]   position of each new slot
-  int copies;                // the incremental sort writes sq, sx, sy, sz (for the collision search only;
-                             // the push gathers position and charge through perm)
+  double* sq;                // [n_tot]   charge of each new slot (after a full sort, for its deposit)
   // incremental sort: the state is stored in the previous sort's order, so a
   // row pair's new members are the ones of its own slot range that stayed
   // plus the particles that moved in (mover list, far list)
