@@ -12,7 +12,9 @@
   a particle step;
 * particles at rest exactly on cell faces and at the ends of the periodic
   directions, binned the same way on both sides at every step;
-* particle Reynolds numbers above 1000 (the constant drag coefficient).
+* particle Reynolds numbers above 1000 (the constant drag coefficient);
+* refused calls on a live handle (bad arguments, wrong state): their codes
+  and messages, and no effect on the steps that follow.
 
 Bars as for the other parity tests: deposit, impacts and integer statistics
 exact, particle state within 1e-12 after one step and after several.
@@ -318,3 +320,66 @@ def test_fast_particles_newton_drag():
         say("  steps", steps, "state err", {k: float(f"{v:.2e}") for k, v in err.items()})
         assert max(err.values()) < TOL
         stats_equal(gst, st)
+
+
+def test_refused_calls_leave_the_handle_intact():
+    """Handle-level argument and state errors through the C ABI return their
+    documented codes with a message and change nothing: the steps that
+    follow equal those of a handle that never saw them, bitwise."""
+    import ctypes
+
+    import torch
+
+    from paper_2602_10761_amd import runtime as R
+
+    say("refused calls")
+    ens = ens_small(nx=16, ny=16, nz=16, n=2000, v_jitter=2.0, precharge=0.1, c_el=5.0)
+    EINVAL, ESTATE = -1, -4
+    ref = sim_of(ens)
+    ref.step(4)
+    want = ref.state_np(0)
+    ref.close()
+
+    sim = sim_of(ens, traj_steps=2)
+    L, h = sim.L, sim.h
+    sim.step(2)
+    dev = torch.zeros(16 * 16 * 16 * 3, dtype=torch.float64, device=sim.dev)
+    P = R.TfParticles(*([None] * 8))
+    st = R.TfStatsOut()
+    bad_theta = np.array([ens.params["k_c"], ens.params["delta_u"], 1.5])
+    nan_theta = np.array([np.nan, ens.params["delta_u"], ens.params["e"]])
+    lam = R.TfParticles(*([dev.data_ptr()] * 8))
+    ww = torch.zeros(2, dtype=torch.float64, device=sim.dev)
+    dth = torch.zeros(3, dtype=torch.float64, device=sim.dev)
+    ph = (ctypes.c_double * R.TF_NPHASE)()
+    nst = ctypes.c_int32()
+    cases = [
+        ("n_steps < 0", EINVAL, lambda: L.tf_step(h, -1, 0)),
+        ("state of ensemble 1 of 1", EINVAL, lambda: L.tf_get_state(h, 1, ctypes.byref(P))),
+        ("state into NULL", EINVAL, lambda: L.tf_get_state(h, 0, ctypes.byref(P))),
+        ("stats of ensemble -1", EINVAL, lambda: L.tf_stats(h, -1, ctypes.byref(st))),
+        ("unknown field", EINVAL, lambda: L.tf_field(h, 0, 7, ctypes.c_void_p(dev.data_ptr()))),
+        ("deposit not kept", ESTATE, lambda: L.tf_field(h, 0, R.TF_FIELD_DEPOSIT, ctypes.c_void_p(dev.data_ptr()))),
+        ("restitution above 1", EINVAL,
+         lambda: L.tf_set_params(h, bad_theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))),
+        ("non-finite k_c", EINVAL,
+         lambda: L.tf_set_params(h, nan_theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))),
+        ("carrier NULL", EINVAL, lambda: L.tf_set_carrier(h, 0, None)),
+        ("poisson NULL", EINVAL, lambda: L.tf_poisson(h, 0, None, ctypes.c_void_p(dev.data_ptr()))),
+        ("reverse with nothing recorded", ESTATE,
+         lambda: L.tf_adjoint_step(h, ctypes.byref(lam), ctypes.c_void_p(ww.data_ptr()),
+                                   ctypes.c_void_p(dth.data_ptr()))),
+        ("record beyond capacity", -2, lambda: L.tf_step(h, 3, R.TF_STEP_RECORD)),
+        ("profile end without begin", ESTATE, lambda: L.tf_profile_end(h, ph, ctypes.byref(nst))),
+    ]
+    for name, code, call in cases:
+        got = call()
+        msg = L.tf_last_error().decode()
+        say(f"  {name}: {got} ({msg})")
+        assert got == code, name
+        assert msg
+    sim.step(2)
+    got = sim.state_np(0)
+    sim.close()
+    for k in KEYS:
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
