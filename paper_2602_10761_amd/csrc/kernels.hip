@@ -672,7 +672,9 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
   // [TB, TT) far list
   int a0 = 0, r0 = 0, rm = 0, r1 = 0, T = 0, TB = 0, TT = 0;
   const int* mvp = C.mv + (rA >> 1) * (long long)kMoverCap;
+  double vol = 1.0;  // cell volume of the pair's row (loaded with the set-up loads)
   if (ok) {
+    vol = C.vol[E.y_off + j];
     // (slot bounds clamped to [0, n_tot]: memory-safe even for inconsistent ranges)
     a0 = min(max(C.rs_old[rA], 0), (int)C.n_tot);
     T = min(max(C.rs_old[rA + 2], a0), (int)C.n_tot) - a0;
@@ -887,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_dep(Ctx C, Ens Eone, int on
     }
   }
   wave_sync();  // member lists read: the FFT buffers may overwrite them
-  const double rsc = (1.0 / 281474976710656.0) / C.vol[E.y_off + j];  // 2^-48 / V
+  const double rsc = (1.0 / 281474976710656.0) / vol;  // 2^-48 / V
   long long rq48[2] = {0, 0};
   if (ok) {
     for (int i = lane; i < nx; i += 64) {
