@@ -1619,9 +1619,12 @@ __device__ double ssm_dq(const Ens& E, double q, double d, double un, int id, un
 
 template <bool PP>
 __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PState& in, const PState& out, int s,
-                                         int p, int c, int ra, int rb, signed char* __restrict__ wall_rec) {
+                                         int p, int c, int ra, int rb, signed char* __restrict__ wall_rec, int pm) {
+  // the id is stored with the new state at the end: loaded here, so that
+  // the wave's last stores do not wait for a load issued after the update
+  const int pid = in.id[p];
   Fwd F;
-  eval_particle<true, PP>(C, E, in, s, p, c, ra, rb, F);
+  eval_particle<true, PP>(C, E, in, s, p, c, ra, rb, F, pm);
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int j = F.j;
   const double q = F.qc, d = F.d;  // charge after any particle-particle exchange
@@ -1650,7 +1653,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
     vyr = -E.e * v1y;
     double dq;
     if (E.charging) {
-      dq = ssm_dq(E, q, d, un, in.id[p], (unsigned)st[ST_STEPS]);
+      dq = ssm_dq(E, q, d, un, pid, (unsigned)st[ST_STEPS]);
     } else {
       const double f = E.fe * pow(un, 0.8);
       dq = -f * (E.dU + q);
@@ -1689,7 +1692,7 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   __builtin_nontemporal_store(v1z, &out.vz[s]);
   __builtin_nontemporal_store(q1, &out.q[s]);
   __builtin_nontemporal_store(d, &out.d[s]);
-  __builtin_nontemporal_store(in.id[p], &out.id[s]);
+  __builtin_nontemporal_store(pid, &out.id[s]);
   if (C.fslot) {
     // drag force of the step on this particle (2-way coupling source)
     const double mp = (E.rr * (kPi / 6.0)) * ((d * d) * d);
@@ -1699,10 +1702,11 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
     C.fslot[n + s] = ms * (F.u[1] - v1y);
     C.fslot[2 * n + s] = ms * (F.u[2] - v1z);
   }
-  // next cell: exact divisions in x, z; local face search in y from the old cell
+  // next cell: exact divisions in x, z; in y the old row when the faces read
+  // with the carrier still bracket the new position, else a local face search
   const int ni = clamp_floor(x1 / E.dx, nx);
   const int nk = clamp_floor(z1 / E.dz, nz);
-  const int nj = y_cell_from(yf, ny, yr, j);
+  const int nj = (yr >= F.yf0 && yr < F.yf1) ? j : y_cell_from(yf, ny, yr, j);
   const int key = (int)E.c_off + (nj * nz + nk) * nx + ni;
   __builtin_nontemporal_store(key, &out.key[s]);
   // the next sort takes a row pair's members from the pair's slot range of
@@ -1756,6 +1760,16 @@ __global__ __launch_bounds__(kBlock, ONE ? 4 : 3) void k_push(Ctx C, Ens Eone, P
   const int s = (int)(blk * kBlock + threadIdx.x);
   const bool act = s < C.n_tot;
   const int c = act ? C.skey[s] : 0x7fffffff;
+  // the old slots of the 32 slots before the wave (lanes 0..31, nearest
+  // first) and after it (lanes 32..63): the cell mates across the wave's ends
+  // need only their state loads
+  int pm = 0;
+  {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int s0 = s - lane;
+    const int t = lane < 32 ? s0 - 1 - lane : s0 + 64 + (lane - 32);
+    if (t >= 0 && t < C.n_tot) pm = C.perm[t];
+  }
   // the slots of the lane's cell from the wave's keys (every lane takes part)
   int ra, rb;
   cell_run(s, c, &ra, &rb);
@@ -1765,7 +1779,7 @@ __global__ __launch_bounds__(kBlock, ONE ? 4 : 3) void k_push(Ctx C, Ens Eone, P
     if (ra < 0) ra = C.start[c];
     if (rb < 0) rb = C.start[c + 1];
     if constexpr (ONE) {
-      push_one<PP>(C, Eone, in, out, s, p, c, ra, rb, wall_rec);
+      push_one<PP>(C, Eone, in, out, s, p, c, ra, rb, wall_rec, pm);
     } else {
       // the ensemble of the wave's first slot (one uniform search: an
       // ensemble's particles fill a contiguous slot range); lanes past its end
@@ -1777,7 +1791,7 @@ __global__ __launch_bounds__(kBlock, ONE ? 4 : 3) void k_push(Ctx C, Ens Eone, P
       while (!done) {
         const int e = __builtin_amdgcn_readfirstlane(e_lane);
         if (e_lane == e) {
-          push_one<PP>(C, C.ens[e], in, out, s, p, c, ra, rb, wall_rec);
+          push_one<PP>(C, C.ens[e], in, out, s, p, c, ra, rb, wall_rec, pm);
           done = true;
         }
       }

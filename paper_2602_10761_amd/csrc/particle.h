@@ -26,6 +26,7 @@ struct Fwd {
   int i, j, k, i1, k1, n00, n01, n10, n11, plane;
   double x, y, z, vx, vy, vz, q, d;
   double tx, ty, tz;
+  double yf0, yf1;  // faces of the particle's cell row (yf[j], yf[j + 1])
   double u[3], Ep[3], S[3];
   double ke, a[3], du[3], re, phid, sdr, iden, v1[3];
   double x1, y1, z1;  // after the update, before rebound and wrap
@@ -72,9 +73,11 @@ __device__ __forceinline__ PPHit pp_pair(int pj, const PState& in, double kpp, d
 
 // PP: compiled with the 4-way coupling (particle-particle collisions)
 // [ra, rb): the slots of cell c (its particles, s among them)
+// pmw (SORTED): lanes 0..31 hold the old slots of the 32 slots before the
+// wave (nearest first), lanes 32..63 those of the 32 slots after it
 template <bool SORTED, bool PP = false>
 __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const PState& in, int s, int p, int c,
-                                              int ra, int rb, Fwd& F) {
+                                              int ra, int rb, Fwd& F, int pmw = 0) {
   const int nx = E.nx, ny = E.ny, nz = E.nz;
   const int cl = c - (int)E.c_off;
   int jk, i, j, k;
@@ -174,9 +177,13 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
         const bool inw = src >= 0 && src < 64;
         double ox = __shfl(x, src & 63, 64), oy = __shfl(y, src & 63, 64);
         double oz = __shfl(z, src & 63, 64), oq = __shfl(q, src & 63, 64);
+        // a mate within 32 slots of the wave's ends: its old slot from pmw
+        // (read at the kernel's start), so only its state is loaded here
+        const int hb = s0 - 1 - t, ta = t - s0 - 64;
+        const int pmv = __shfl(pmw, hb >= 0 ? (hb & 31) : 32 + (ta & 31), 64);
         if (kk < n && t != s) {
           if (!inw) {
-            const int pt = C.perm[t];
+            const int pt = (hb >= 0 && hb < 32) || (ta >= 0 && ta < 32) ? pmv : C.perm[t];
             ox = in.x[pt];
             oy = in.y[pt];
             oz = in.z[pt];
@@ -227,6 +234,7 @@ __device__ __forceinline__ void eval_particle(const Ctx& C, const Ens& E, const 
   F.n00 = n00; F.n01 = n01; F.n10 = n10; F.n11 = n11; F.plane = plane;
   F.x = x; F.y = y; F.z = z; F.vx = vx; F.vy = vy; F.vz = vz; F.q = q; F.d = d;
   F.tx = tx; F.ty = ty; F.tz = tz;
+  F.yf0 = yf[j]; F.yf1 = yf[j + 1];
   F.u[0] = uc[0]; F.u[1] = uc[1]; F.u[2] = uc[2];
   F.Ep[0] = Ex; F.Ep[1] = Ey; F.Ep[2] = Ez;
   F.S[0] = sx; F.S[1] = sy; F.S[2] = sz;
