@@ -6,6 +6,9 @@ against each other (through the C ABI).
   ensemble of the batched handle bitwise equal to its own plain run, and one
   ensemble per mesh class from the batched handle against the oracle (1e-12
   after one step with exact deposit statistics and impacts, and after ten);
+* the 4e6-particle 192x160x192 workload over its 2000 steps: invariants
+  (flags, charge balance between particles and walls, containment, row
+  counts) and bitwise repeatability;
 * the 1e4-particle 32^3 workload at its own parameters over its 1000 steps:
   concentration and charge profiles within 1 % of the oracle's (measured:
   identical), and the same with wall-normal velocity jitter and charged
@@ -119,3 +122,46 @@ def test_config1_long_run(variant):
         err = np.abs(g - o).max() / max(np.abs(o).max(), 1e-300) if np.abs(o).max() > 0 else np.abs(g).max()
         say(f"  {k}: normwise rel diff {err:.2e}")
         assert err < 0.01, k
+
+
+def test_config3_full_length_invariants():
+    """The 4e6-particle 192x160x192 workload over its stated 2000 steps in the
+    launch configuration the benchmark times (tuned tiles, sort capacity and
+    push order), charged and with wall-normal velocity jitter so that
+    particles keep hitting the walls: no fault flag; the charge the particles
+    lose is the charge the walls gain (to the fixed-point rounding of the wall
+    sums, half a unit of 2^-40 per impact); every particle inside the
+    channel; every step counts every particle once in the row histogram; a
+    second run is bitwise the same.  The oracle's cost at this size rules out
+    a particle-by-particle comparison over 2000 steps; the full-size one- and
+    three-step comparisons cover that."""
+    from paper_2602_10761_amd import autotune
+    from paper_2602_10761_amd.runtime import TriboSim
+    ens = W.make_workload(3, precharge=0.05, v_jitter=3.0)[0]
+    autotune.ensure_tuned_workload([ens])
+    n = 2000
+    runs = []
+    for rep in range(2):
+        sim = TriboSim([ens])
+        sim.step(n)
+        runs.append((sim.state_np(0), sim.stats(0)))
+        sim.close()
+        say(f"config 3, {n} steps, run {rep}: impacts {runs[-1][1]['impacts']}")
+    s, st = runs[0]
+    assert st["steps"] == n and st["flags"] == 0
+    impacts = int(st["impacts"].sum())
+    assert impacts > 100000
+    wall = st["wallq"].sum() * 2.0 ** -40
+    q0, q1 = ens.q.sum(), s["q"].sum()
+    tol = impacts * 2.0 ** -41 + 1e-12 * (np.abs(s["q"]).sum() + abs(wall))
+    say(f"  charge: particles {q0:.6e} -> {q1:.6e}, walls {wall:.6e}, imbalance {q1 - q0 + wall:.2e} (bound {tol:.2e})")
+    assert abs(q1 - q0 + wall) < tol
+    r = 0.5 * s["d"]
+    m = ens.mesh
+    assert np.all((s["y"] >= r) & (s["y"] <= m.ly - r))
+    assert np.all((s["x"] >= 0) & (s["x"] < m.lx) & (s["z"] >= 0) & (s["z"] < m.lz))
+    assert int(st["crel_y"].sum()) == n * ens.n
+    for k in KEYS:
+        np.testing.assert_array_equal(runs[1][0][k], s[k], err_msg=k)
+    for k in ("impacts", "wallq", "unhist", "crel_y", "qcum_y", "qnow_y"):
+        np.testing.assert_array_equal(runs[1][1][k], st[k], err_msg=k)
