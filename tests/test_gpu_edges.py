@@ -14,7 +14,8 @@
   directions, binned the same way on both sides at every step;
 * particle Reynolds numbers above 1000 (the constant drag coefficient);
 * refused calls on a live handle (bad arguments, wrong state): their codes
-  and messages, and no effect on the steps that follow.
+  and messages, and no effect on the steps that follow;
+* one ensemble's state replaced in the middle of a batched run.
 
 Bars as for the other parity tests: deposit, impacts and integer statistics
 exact, particle state within 1e-12 after one step and after several.
@@ -383,3 +384,44 @@ def test_refused_calls_leave_the_handle_intact():
     sim.close()
     for k in KEYS:
         np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_resume_one_ensemble(graphs):
+    """Replacing one ensemble's state in the middle of a batched run (here by
+    its own state at that step, read back through the C ABI) restarts from a
+    full sort and continues bitwise as the uninterrupted run, for every
+    ensemble of the batch; a different state for it (its state two steps
+    later in a separate run) leaves the other ensembles' steps unchanged."""
+    say("batch resume, graphs", graphs)
+    batch = [ens_small(nx=16, ny=24, nz=16, n=3000, v_jitter=3.0, precharge=0.2, c_el=5.0, re_tau=40.0),
+             ens_small(nx=24, ny=16, nz=20, n=2500, v_jitter=2.0, precharge=0.1, seed=3),
+             ens_small(nx=12, ny=10, nz=8, n=900, v_jitter=3.0, precharge=0.3, seed=5)]
+    cont = sim_of(batch, graphs=graphs)
+    cont.step(12)
+    want = [cont.state_np(e) for e in range(3)]
+    cont.close()
+    sim = sim_of(batch, graphs=graphs)
+    sim.step(5)
+    mid = sim.state(1)
+    sim.set_state(1, mid)
+    sim.step(7)
+    got = [sim.state_np(e) for e in range(3)]
+    sim.close()
+    for e in range(3):
+        for k in KEYS:
+            np.testing.assert_array_equal(got[e][k], want[e][k], err_msg=f"ensemble {e} {k}")
+    # another state for ensemble 1: the others continue unchanged
+    other = sim_of(batch, graphs=graphs)
+    other.step(7)
+    later = other.state(1)
+    other.close()
+    sim = sim_of(batch, graphs=graphs)
+    sim.step(5)
+    sim.set_state(1, later)
+    sim.step(7)
+    got = [sim.state_np(e) for e in (0, 2)]
+    sim.close()
+    for g, e in zip(got, (0, 2)):
+        for k in KEYS:
+            np.testing.assert_array_equal(g[k], want[e][k], err_msg=f"ensemble {e} {k}")
