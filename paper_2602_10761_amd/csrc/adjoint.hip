@@ -62,15 +62,29 @@ __device__ __forceinline__ void ens_of_cell(const Ctx& C, const Ens& Eone, int o
 __global__ __launch_bounds__(kBlock) void k_adj_a(Ctx C, Ens Eone, int one, PState in, AdjLam lam1, AdjWork W,
                                                   const signed char* __restrict__ wallrec) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= C.n_tot) return;
+  const bool act = s < C.n_tot;
+  const int c = act ? C.skey[s] : 0x7fffffff;
+  // as in the push: the old slots of the 32 slots on either side of the wave
+  // and the lane's cell run from the wave's keys (every lane takes part)
+  int pm = 0;
+  {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int s0 = s - lane;
+    const int t = lane < 32 ? s0 - 1 - lane : s0 + 64 + (lane - 32);
+    if (t >= 0 && t < C.n_tot) pm = C.perm[t];
+  }
+  int ra, rb;
+  cell_run(s, c, &ra, &rb);
+  if (!act) return;
   const long long n = C.n_tot;
   const int p = C.perm[s];
-  const int c = C.skey[s];
+  if (ra < 0) ra = C.start[c];
+  if (rb < 0) rb = C.start[c + 1];
   int e;
   Ens E;
   ens_of_cell(C, Eone, one, c, &e, &E);
   Fwd F;
-  eval_particle<false>(C, E, in, s, p, c, C.start[c], C.start[c + 1], F);
+  eval_particle<true>(C, E, in, s, p, c, ra, rb, F, pm);
 
   const double lx = lam1.x[s], ly = lam1.y[s], lz = lam1.z[s];
   const double lvx = lam1.vx[s], lvy = lam1.vy[s], lq = lam1.q[s], lvz = lam1.vz[s];
@@ -226,28 +240,56 @@ __global__ __launch_bounds__(kBlock) void k_adj_div(Ctx C, Ens Eone, int one, Ad
 
 __global__ __launch_bounds__(kBlock) void k_adj_b(Ctx C, Ens Eone, int one, PState in, AdjWork W, AdjLam lam0) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= C.n_tot) return;
+  const bool act = s < C.n_tot;
   (void)Eone;
   (void)one;
   const long long n = C.n_tot;
+  const int c = act ? C.skey[s] : 0x7fffffff;
+  // as in the push: the cell mates' positions, charges and lambda_S from
+  // their lanes, those of cells across the wave's ends from memory (their
+  // old slots read here for the 32 slots on either side), ascending id
+  const int lane = (int)(threadIdx.x & 63u);
+  const int s0 = s - lane;
+  int pm = 0;
+  {
+    const int t = lane < 32 ? s0 - 1 - lane : s0 + 64 + (lane - 32);
+    if (t >= 0 && t < C.n_tot) pm = C.perm[t];
+  }
+  int a, b;
+  cell_run(s, c, &a, &b);
+  if (!act) return;
   const int p = C.perm[s];
-  const int c = C.skey[s];
+  if (a < 0) a = C.start[c];
+  if (b < 0) b = C.start[c + 1];
   double lpx = W.lamP.x[s], lpy = W.lamP.y[s], lpz = W.lamP.z[s];
   double lq = W.lamP.q[s] + W.lamQ[c];
   const double x = in.x[p], y = in.y[p], z = in.z[p], q = in.q[p];
   const double lsx = W.lamS[s], lsy = W.lamS[n + s], lsz = W.lamS[2 * n + s];
-  const int a = C.start[c], b = C.start[c + 1];
-  for (int t = a; t < b; ++t) {
-    if (t == s) continue;
-    const int pt = C.perm[t];
-    const double rx = x - in.x[pt], ry = y - in.y[pt], rz = z - in.z[pt];
+  const int nm = b - a;
+  for (int kk = 0; __any(kk < nm); ++kk) {
+    const int t = a + kk, src = t - s0;
+    double ox = __shfl(x, src & 63, 64), oy = __shfl(y, src & 63, 64);
+    double oz = __shfl(z, src & 63, 64), qt = __shfl(q, src & 63, 64);
+    double ltx = __shfl(lsx, src & 63, 64), lty = __shfl(lsy, src & 63, 64), ltz = __shfl(lsz, src & 63, 64);
+    const int hb = s0 - 1 - t, ta = t - s0 - 64;
+    const int pmv = __shfl(pm, hb >= 0 ? (hb & 31) : 32 + (ta & 31), 64);
+    if (!(kk < nm) || t == s) continue;
+    if (!(src >= 0 && src < 64)) {
+      const int pt = (hb >= 0 && hb < 32) || (ta >= 0 && ta < 32) ? pmv : C.perm[t];
+      ox = in.x[pt];
+      oy = in.y[pt];
+      oz = in.z[pt];
+      qt = in.q[pt];
+      ltx = W.lamS[t];
+      lty = W.lamS[n + t];
+      ltz = W.lamS[2 * n + t];
+    }
+    const double rx = x - ox, ry = y - oy, rz = z - oz;
     const double r2 = (rx * rx + ry * ry) + rz * rz;
     if (r2 > 0.0) {
       const double ri = rsqrt(r2);
       const double inv3 = ri * ri * ri;
       const double inv5 = inv3 * ri * ri;
-      const double ltx = W.lamS[t], lty = W.lamS[n + t], ltz = W.lamS[2 * n + t];
-      const double qt = in.q[pt];
       // S_t contains q_s (x_t - x_s)/|r|^3
       lq -= (ltx * rx + lty * ry + ltz * rz) * inv3;
       // d S_s / d x_s and d S_t / d x_s: J(r) (q_t lambda_S_s - q_s lambda_S_t)

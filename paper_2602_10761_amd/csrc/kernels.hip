@@ -1727,23 +1727,6 @@ __device__ __forceinline__ void push_one(const Ctx& C, const Ens& E, const PStat
   pair_count(C.pair_cnt, pnew);
 }
 
-// Slots [ra, rb) of cell c, from the sorted keys of the wave's lanes (which
-// hold consecutive slots s, so a cell's slots are a run of equal keys).  A run
-// that reaches the first or last lane may continue in the neighbouring wave:
-// then ra or rb is -1 and the caller reads the cell start.  Every lane of the
-// wave must take part.
-__device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
-  const int lane = (int)(threadIdx.x & 63u);
-  const int kp = __shfl_up(c, 1, 64);
-  const unsigned long long heads = __ballot(lane == 0 || kp != c);
-  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all for lane 63)
-  const int hl = 63 - __clzll(heads & upto);              // lane 0 is always a head
-  const unsigned long long after = heads & ~upto;
-  const int el = after ? __ffsll((long long)after) - 1 : 64;
-  const int s0 = s - lane;
-  *ra = hl == 0 ? -1 : s0 + hl;
-  *rb = el == 64 ? -1 : s0 + el;
-}
 
 // ONE (a handle of one ensemble, its descriptor by value): four waves per
 // SIMD (at most 128 VGPRs, none spilled); the batched form, which needs more

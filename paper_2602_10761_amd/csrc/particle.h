@@ -71,6 +71,24 @@ __device__ __forceinline__ PPHit pp_pair(int pj, const PState& in, double kpp, d
   return h;
 }
 
+// Slots [ra, rb) of cell c, from the sorted keys of the wave's lanes (which
+// hold consecutive slots s, so a cell's slots are a run of equal keys).  A run
+// that reaches the first or last lane may continue in the neighbouring wave:
+// then ra or rb is -1 and the caller reads the cell start.  Every lane of the
+// wave must take part.
+__device__ __forceinline__ void cell_run(int s, int c, int* ra, int* rb) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int kp = __shfl_up(c, 1, 64);
+  const unsigned long long heads = __ballot(lane == 0 || kp != c);
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all for lane 63)
+  const int hl = 63 - __clzll(heads & upto);              // lane 0 is always a head
+  const unsigned long long after = heads & ~upto;
+  const int el = after ? __ffsll((long long)after) - 1 : 64;
+  const int s0 = s - lane;
+  *ra = hl == 0 ? -1 : s0 + hl;
+  *rb = el == 64 ? -1 : s0 + el;
+}
+
 // PP: compiled with the 4-way coupling (particle-particle collisions)
 // [ra, rb): the slots of cell c (its particles, s among them)
 // pmw (SORTED): lanes 0..31 hold the old slots of the 32 slots before the
